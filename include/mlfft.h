@@ -1,0 +1,190 @@
+/*
+ * mlfft.h - C ABI of the MI355X MLFFT solver library.
+ *
+ * The library solves Z_A I = V for the two-level block-Toeplitz impedance
+ * matrix Z_A of an Nx x Ny array of identical cells with b basis functions
+ * each (Sec. II-A, eq. Tblock; Sec. III, "ZI = V"), using the multilevel FFT
+ * product (Sec. II-C, eq. multL; Sec. III-A) inside restarted GMRES (Sec. III-C).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an mlfft_status.  Negative values are errors and
+ *    leave a message retrievable with mlfft_last_error(); MLFFT_NOT_CONVERGED
+ *    (positive) means the call completed and its outputs are valid but some
+ *    right-hand side missed its tolerance.  No C++ exception crosses the ABI.
+ *  - Arguments are validated before any work is enqueued.
+ *  - Complex numbers are interleaved (re, im): complex128 = two doubles,
+ *    complex64 = two floats.
+ *  - Vector layout (the paper's order, eq. xc2 and eq. ZIVvec): W columns,
+ *    column w contiguous; inside a column the unknown of basis m of cell
+ *    (iy, ix) is at ((iy * Nx) + ix) * b + m.
+ *  - Device pointers are HIP device pointers of the context's device.  The
+ *    caller owns every pointer it passes; the library never frees them.
+ *  - Work is enqueued on the context's stream (the caller's stream, e.g. the
+ *    PyTorch current stream).  Calls documented as asynchronous return before
+ *    the work finishes; blocking calls synchronise the stream before returning.
+ *  - A context is not thread safe; the caller serialises calls on it.
+ *  - The library allocates its own device memory (spectra, preconditioner,
+ *    spectral and Krylov workspaces) with hipMalloc outside of the matvec and
+ *    preconditioner hot paths, and frees it in mlfft_destroy().
+ */
+#ifndef MLFFT_H
+#define MLFFT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mlfft_ctx_s* mlfft_ctx;
+
+typedef enum {
+    MLFFT_OK = 0,
+    MLFFT_NOT_CONVERGED = 1,
+    MLFFT_E_ARG = -1,        /* invalid argument (sizes, null pointers, non-finite input) */
+    MLFFT_E_NOMEM = -2,      /* device allocation failed */
+    MLFFT_E_HIP = -3,        /* a HIP runtime call or kernel launch failed */
+    MLFFT_E_SINGULAR = -4,   /* a required inverse does not exist */
+    MLFFT_E_STATE = -5       /* call not valid in the current state (e.g. unknown array id) */
+} mlfft_status;
+
+typedef enum {
+    MLFFT_FP64 = 0,          /* complex128 data, FP64 FFTs and FP64 MFMA block product */
+    MLFFT_FP32 = 1,          /* complex64 data, FP32 FFTs and FP32 MFMA block product */
+    MLFFT_FP32_BF16GEMM = 2  /* complex64 data, FP32 FFTs, block product with bf16 inputs and FP32 accumulation */
+} mlfft_prec;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the handle. */
+mlfft_status mlfft_create(int device, void* hip_stream, mlfft_ctx* out);
+
+/* Free every device buffer the context owns and the context itself.  NULL is accepted. */
+mlfft_status mlfft_destroy(mlfft_ctx ctx);
+
+/* Message of the last error on this context; valid until the next call on it.
+ * With ctx == NULL: the message of the last failed mlfft_create(). */
+const char* mlfft_last_error(mlfft_ctx ctx);
+
+/* Change the stream the context enqueues on. */
+mlfft_status mlfft_set_stream(mlfft_ctx ctx, void* hip_stream);
+
+/* Register (or replace) array `array_id` (>= 0) and build everything the
+ * solver needs from its unique blocks.
+ *
+ * blocks: (2Ny-1) * (2Nx-1) * b * b complex128, layout [p+Ny-1][q+Nx-1][m][n],
+ * where R_{p,q}[m][n] couples test basis m of cell (iy, ix) with source basis n
+ * of cell (iy-p, ix-q) (T_ij = t_{i-j}, eq. T and eq. Tblock).  These are the
+ * "unique blocks" of Z_A (Sec. II-C, storage (2N^[1]-1)(N^[0])^2 per level).
+ * blocks_on_device: 0 = host pointer, 1 = device pointer.  The library copies
+ * what it needs; the caller may free the blocks when the call returns.
+ *
+ * Built here (blocking; reported separately from solve time, like the paper's
+ * "Con." split, Sec. V):
+ *  - the block spectra G_hat(k) = 2-D DFT of the block grid embedded in the
+ *    (2Ny) x (2Nx) circulant (eqs. cT1, circL1, circL2, multL), in FP64 with
+ *    FP32 and bf16 copies;
+ *  - the two-level Strang block-circulant preconditioner on the Ny x Nx torus
+ *    and the FP64 inverse of each of its Nx*Ny frequency blocks, with FP32 and
+ *    bf16 copies.  A frequency block whose reciprocal 1-norm condition number
+ *    is below 1e-12 is replaced by the inverse of the self block R_{0,0}
+ *    (the Kindt preconditioner of Sec. III-B); the count is reported by
+ *    mlfft_array_info().  If R_{0,0} itself is singular the call fails with
+ *    MLFFT_E_SINGULAR;
+ *  - the inverse of R_{0,0} for the self-block preconditioner.
+ * Limits: 1 <= Nx, Ny <= 32, 1 <= b <= 256.  Non-finite blocks: MLFFT_E_ARG. */
+mlfft_status mlfft_set_blocks(mlfft_ctx ctx, int array_id, int Nx, int Ny, int b,
+                              const void* blocks, int blocks_on_device);
+
+/* Remove an array and free its buffers. */
+mlfft_status mlfft_drop_array(mlfft_ctx ctx, int array_id);
+
+typedef struct {
+    int Nx, Ny, b;
+    int Px, Py;              /* matvec circulant grid, 2Nx x 2Ny */
+    int pc_fallbacks;        /* preconditioner frequencies replaced by the self-block inverse */
+    double pc_min_rcond;     /* smallest reciprocal condition number over the preconditioner blocks */
+    size_t device_bytes;     /* device memory held for this array */
+} mlfft_array_info_t;
+
+mlfft_status mlfft_array_info(mlfft_ctx ctx, int array_id, mlfft_array_info_t* out);
+
+/* y = Z_A x for W columns (eq. multL): zero-pad every column to the
+ * (2Ny) x (2Nx) grid (eq. xc2), blockwise 2-level FFT (eq. F2), per-frequency
+ * b x b block product, inverse FFT, keep the first Ny x Nx cells.
+ * x, y: device pointers, W columns in the vector layout; complex128 for
+ * MLFFT_FP64, complex64 otherwise.  x and y must not overlap.
+ * Asynchronous on the context's stream. */
+mlfft_status mlfft_matvec(mlfft_ctx ctx, int array_id, int W, const void* x, void* y, mlfft_prec prec);
+
+/* z = P^{-1} r with P the preconditioner `kind`:
+ *   1 = two-level Strang block circulant: z = IFFT2(S_hat(k)^{-1} FFT2(r)) on the
+ *       Ny x Nx torus;
+ *   2 = self-block (Kindt) preconditioner P'_K of Sec. III-B: every cell's
+ *       b-vector multiplied by R_{0,0}^{-1}.
+ * Layout and precision rules as for mlfft_matvec.  Asynchronous. */
+mlfft_status mlfft_precond_apply(mlfft_ctx ctx, int array_id, int kind, int W, const void* r, void* z,
+                                 mlfft_prec prec);
+
+
+/* ------------------------------------------------------------------ solve */
+
+typedef struct {
+    int restart;         /* GMRES restart length m, 1..31 (default 30) */
+    int max_restarts;    /* restart cycles per inner solve (default 100) */
+    double tol;          /* target true FP64 relative residual ||V_w - Z I_w|| / ||V_w|| per column (default 1e-6) */
+    int inner_prec;      /* mlfft_prec of the inner GMRES (default MLFFT_FP32).  MLFFT_FP64 = plain FP64 GMRES:
+                            the outer loop then only confirms the true residual */
+    double inner_tol;    /* residual reduction asked of each inner solve with FP32 / BF16 inner precision
+                            (default 1e-4); ignored for MLFFT_FP64 */
+    int max_outer;       /* FP64 refinement steps (default 10) */
+    int precond;         /* 0 none, 1 block circulant (default), 2 self block (Kindt), 3 learned correction of the
+                            block-circulant output (flexible GMRES; needs a network, see mlfft_net_create) */
+    int orth;            /* 1 classical Gram-Schmidt, 2 classical Gram-Schmidt applied twice (default); FP64 sums */
+    int x0_given;        /* 1: I holds the initial guess on entry; 0: start from zero (default) */
+    int record_history;  /* 1: fill info->history */
+    int use_graph;       /* reserved, must be 0 */
+} mlfft_solve_opts;
+
+typedef struct {
+    int* iters;          /* [W] inner GMRES iterations per column, or NULL (host, caller-owned) */
+    int* outer;          /* [W] refinement steps that worked on the column, or NULL */
+    double* relres;      /* [W] final true FP64 relative residual, or NULL */
+    int* converged;      /* [W] 1 if relres <= tol, or NULL */
+    double* history;     /* [history_len * W] residual estimate / ||V_w|| after each inner iteration
+                            (row-major by iteration), or NULL */
+    int history_len;     /* rows of history */
+    int fallbacks;       /* out: learned-correction outputs replaced by the plain block-circulant output */
+    int matvecs64;       /* out: FP64 MLFFT products used for true residuals */
+    int matvecs_inner;   /* out: batched MLFFT products in the inner precision */
+    int precond_applies; /* out: batched preconditioner applies */
+    int net_applies;     /* out: batched network corrections */
+} mlfft_solve_info;
+
+/* Fill *opts with the defaults above. */
+mlfft_status mlfft_solve_default_opts(mlfft_solve_opts* opts);
+
+/* Solve Z_A I = V for the W columns of V (Sec. III, "ZI = V"; multiple right-hand
+ * sides of Sec. III-C, eq. ZIVmat): restarted GMRES with the MLFFT matvec and the
+ * chosen preconditioner, one Krylov space per column, FP64 iterative refinement
+ * around an FP32 / BF16 inner solve.  V, I: device, complex128, W columns in the
+ * vector layout.  opts == NULL uses the defaults; info may be NULL.
+ * Blocking: returns when every column converged (MLFFT_OK) or the limits are
+ * reached (MLFFT_NOT_CONVERGED, outputs valid).  Zero columns of V give zero
+ * columns of I.  Non-finite residuals: MLFFT_E_ARG. */
+mlfft_status mlfft_solve(mlfft_ctx ctx, int array_id, int W, const void* V, void* I,
+                         const mlfft_solve_opts* opts, mlfft_solve_info* info);
+
+/* The same for several arrays of different shapes in one batch: every MLFFT
+ * product, preconditioner apply and Krylov step of the solve covers all arrays
+ * in one grouped launch.  V[i], I[i]: device, complex128, W[i] columns of array
+ * array_ids[i] (ids distinct).  info: NULL or one struct for the whole batch whose
+ * per-column arrays are indexed by the concatenated column order. */
+mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids, const int* W,
+                               const void* const* V, void* const* I,
+                               const mlfft_solve_opts* opts, mlfft_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLFFT_H */

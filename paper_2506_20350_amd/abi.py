@@ -1,0 +1,187 @@
+"""ctypes binding of the C ABI in include/mlfft.h.
+
+Argument marshalling only: every function here forwards to the function of the
+same name in libmlfft.so.  Device buffers are passed as raw pointers (for
+PyTorch tensors, ``tensor.data_ptr()``); streams as ``hipStream_t`` values
+(``torch.cuda.current_stream().cuda_stream``).  There is no fallback: if the
+library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "lib", "libmlfft.so")
+HEADERS = [os.path.join(os.path.dirname(PKG), "include", "mlfft.h")]
+
+MLFFT_OK = 0
+MLFFT_NOT_CONVERGED = 1
+MLFFT_E_ARG = -1
+MLFFT_E_NOMEM = -2
+MLFFT_E_HIP = -3
+MLFFT_E_SINGULAR = -4
+MLFFT_E_STATE = -5
+
+MLFFT_FP64 = 0
+MLFFT_FP32 = 1
+MLFFT_FP32_BF16GEMM = 2
+
+STATUS_NAMES = {0: "MLFFT_OK", 1: "MLFFT_NOT_CONVERGED", -1: "MLFFT_E_ARG", -2: "MLFFT_E_NOMEM",
+                -3: "MLFFT_E_HIP", -4: "MLFFT_E_SINGULAR", -5: "MLFFT_E_STATE"}
+
+
+class MlfftError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ArrayInfo(ctypes.Structure):
+    _fields_ = [("Nx", ctypes.c_int), ("Ny", ctypes.c_int), ("b", ctypes.c_int),
+                ("Px", ctypes.c_int), ("Py", ctypes.c_int), ("pc_fallbacks", ctypes.c_int),
+                ("pc_min_rcond", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("max_restarts", ctypes.c_int), ("tol", ctypes.c_double),
+                ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
+                ("precond", ctypes.c_int), ("orth", ctypes.c_int), ("x0_given", ctypes.c_int),
+                ("record_history", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.POINTER(ctypes.c_int)), ("outer", ctypes.POINTER(ctypes.c_int)),
+                ("relres", ctypes.POINTER(ctypes.c_double)), ("converged", ctypes.POINTER(ctypes.c_int)),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int),
+                ("fallbacks", ctypes.c_int), ("matvecs64", ctypes.c_int), ("matvecs_inner", ctypes.c_int),
+                ("precond_applies", ctypes.c_int), ("net_applies", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_ST = ctypes.c_int
+
+_SIGNATURES = {
+    "mlfft_create": (_ST, [_I, _P, ctypes.POINTER(_P)]),
+    "mlfft_destroy": (_ST, [_P]),
+    "mlfft_last_error": (ctypes.c_char_p, [_P]),
+    "mlfft_set_stream": (_ST, [_P, _P]),
+    "mlfft_set_blocks": (_ST, [_P, _I, _I, _I, _I, _P, _I]),
+    "mlfft_drop_array": (_ST, [_P, _I]),
+    "mlfft_array_info": (_ST, [_P, _I, ctypes.POINTER(ArrayInfo)]),
+    "mlfft_matvec": (_ST, [_P, _I, _I, _P, _P, _I]),
+    "mlfft_precond_apply": (_ST, [_P, _I, _I, _I, _P, _P, _I]),
+    "mlfft_solve_default_opts": (_ST, [ctypes.POINTER(SolveOpts)]),
+    "mlfft_solve": (_ST, [_P, _I, _I, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
+    "mlfft_solve_batch": (_ST, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_P),
+                                ctypes.POINTER(_P), ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
+    "mlfft_matvec_batch": (_ST, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_P),
+                                 ctypes.POINTER(_P), _I]),
+    "mlfft_net_create": (_ST, [_P, _I, _I]),
+    "mlfft_net_set_weights": (_ST, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+    "mlfft_net_get_weights": (_ST, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+    "mlfft_net_num_weights": (ctypes.c_size_t, [_P]),
+    "mlfft_net_forward": (_ST, [_P, _I, _I, _I, _P, _P]),
+    "mlfft_net_train_step": (_ST, [_P, _I, _I, _I, _P, _P, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]),
+    "mlfft_net_grads": (_ST, [_P, _I, _I, _I, _P, _P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "mlfft_net_apply": (_ST, [_P, _I, _I, _P, _P]),
+    "mlfft_conv3x3": (_ST, [_P, _I, _I, _I, _I, _I, _P, _P, _P, _I]),
+}
+
+_lib = None
+
+
+def header_symbols() -> list:
+    """Every function name declared in include/*.h."""
+    names = []
+    for h in HEADERS:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names += re.findall(r"\b(mlfft_[a-z0-9_]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2506_20350_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(ctx, status: int, what: str = "") -> int:
+    if status < 0:
+        msg = lib().mlfft_last_error(ctx)
+        raise MlfftError(status, (msg.decode() if msg else "") + (f" ({what})" if what else ""))
+    return status
+
+
+def mlfft_create(device: int = 0, stream: int = 0):
+    h = ctypes.c_void_p()
+    st = lib().mlfft_create(device, stream or None, ctypes.byref(h))
+    if st != MLFFT_OK:
+        raise MlfftError(st, lib().mlfft_last_error(None).decode())
+    return h
+
+
+def mlfft_destroy(ctx):
+    return check(ctx, lib().mlfft_destroy(ctx))
+
+
+def mlfft_set_stream(ctx, stream: int):
+    return check(ctx, lib().mlfft_set_stream(ctx, stream or None))
+
+
+def mlfft_set_blocks(ctx, array_id: int, Nx: int, Ny: int, b: int, blocks_ptr: int, on_device: bool):
+    return check(ctx, lib().mlfft_set_blocks(ctx, array_id, Nx, Ny, b, blocks_ptr, int(on_device)))
+
+
+def mlfft_drop_array(ctx, array_id: int):
+    return check(ctx, lib().mlfft_drop_array(ctx, array_id))
+
+
+def mlfft_array_info(ctx, array_id: int) -> ArrayInfo:
+    info = ArrayInfo()
+    check(ctx, lib().mlfft_array_info(ctx, array_id, ctypes.byref(info)))
+    return info
+
+
+def mlfft_matvec(ctx, array_id: int, W: int, x_ptr: int, y_ptr: int, prec: int):
+    return check(ctx, lib().mlfft_matvec(ctx, array_id, W, x_ptr, y_ptr, prec))
+
+
+def mlfft_precond_apply(ctx, array_id: int, kind: int, W: int, r_ptr: int, z_ptr: int, prec: int):
+    return check(ctx, lib().mlfft_precond_apply(ctx, array_id, kind, W, r_ptr, z_ptr, prec))
+
+
+def mlfft_solve_default_opts() -> SolveOpts:
+    o = SolveOpts()
+    st = lib().mlfft_solve_default_opts(ctypes.byref(o))
+    if st != MLFFT_OK:
+        raise MlfftError(st, "mlfft_solve_default_opts")
+    return o
+
+
+def mlfft_solve(ctx, array_id: int, W: int, V_ptr: int, I_ptr: int, opts: SolveOpts, info: SolveInfo) -> int:
+    return check(ctx, lib().mlfft_solve(ctx, array_id, W, V_ptr, I_ptr, ctypes.byref(opts),
+                                        ctypes.byref(info) if info is not None else None))
+
+
+def mlfft_solve_batch(ctx, array_ids, Ws, V_ptrs, I_ptrs, opts: SolveOpts, info: SolveInfo) -> int:
+    n = len(array_ids)
+    ids = (ctypes.c_int * n)(*array_ids)
+    ws = (ctypes.c_int * n)(*Ws)
+    vp = (ctypes.c_void_p * n)(*V_ptrs)
+    ip = (ctypes.c_void_p * n)(*I_ptrs)
+    return check(ctx, lib().mlfft_solve_batch(ctx, n, ids, ws, vp, ip, ctypes.byref(opts),
+                                              ctypes.byref(info) if info is not None else None))

@@ -1,0 +1,165 @@
+"""PyTorch-facing wrapper of the C ABI.
+
+PyTorch only provides device memory and the stream here; every step of the
+solver path runs in libmlfft.so.  Tensors are passed by pointer after their
+dtype, device, size and contiguity are checked, so that the library never sees
+a buffer of the wrong shape.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import abi
+
+PREC = {"fp64": abi.MLFFT_FP64, "fp32": abi.MLFFT_FP32, "bf16": abi.MLFFT_FP32_BF16GEMM}
+PREC_DTYPE = {abi.MLFFT_FP64: torch.complex128, abi.MLFFT_FP32: torch.complex64,
+              abi.MLFFT_FP32_BF16GEMM: torch.complex64}
+
+
+def _prec(p) -> int:
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+class Context:
+    """One library context on one device, enqueueing on the current PyTorch stream."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        stream = torch.cuda.current_stream(self.torch_device).cuda_stream
+        self.h = abi.mlfft_create(device, stream)
+        self.arrays = {}
+
+    def close(self):
+        if self.h is not None:
+            abi.mlfft_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync_stream(self):
+        abi.mlfft_set_stream(self.h, torch.cuda.current_stream(self.torch_device).cuda_stream)
+
+    # ---------------------------------------------------------------- arrays
+    def set_blocks(self, array_id: int, blocks) -> None:
+        """blocks: complex128 array (2Ny-1, 2Nx-1, b, b), host (numpy / CPU tensor) or device tensor."""
+        self.sync_stream()
+        if isinstance(blocks, np.ndarray):
+            blocks = torch.from_numpy(np.ascontiguousarray(blocks, dtype=np.complex128))
+        if blocks.dtype != torch.complex128 or blocks.dim() != 4:
+            raise ValueError("blocks must be a complex128 tensor of shape (2Ny-1, 2Nx-1, b, b)")
+        blocks = blocks.contiguous()
+        py, qx, b, b2 = blocks.shape
+        if b != b2 or py % 2 == 0 or qx % 2 == 0:
+            raise ValueError("blocks must have shape (2Ny-1, 2Nx-1, b, b)")
+        Nx, Ny = (qx + 1) // 2, (py + 1) // 2
+        on_dev = blocks.is_cuda
+        abi.mlfft_set_blocks(self.h, array_id, Nx, Ny, b, blocks.data_ptr(), on_dev)
+        self.arrays[array_id] = (Nx, Ny, b)
+
+    def info(self, array_id: int) -> abi.ArrayInfo:
+        return abi.mlfft_array_info(self.h, array_id)
+
+    def _check_vec(self, array_id: int, t: torch.Tensor, prec: int, name: str) -> int:
+        Nx, Ny, b = self.arrays[array_id]
+        if not t.is_cuda or t.device.index != self.device:
+            raise ValueError(f"{name} must be on cuda:{self.device}")
+        if t.dtype != PREC_DTYPE[prec]:
+            raise ValueError(f"{name} must be {PREC_DTYPE[prec]} for this precision")
+        if not t.is_contiguous() or t.dim() != 2 or t.shape[1] != Nx * Ny * b:
+            raise ValueError(f"{name} must be a contiguous (W, {Nx * Ny * b}) tensor")
+        return t.shape[0]
+
+    # ---------------------------------------------------------------- operators
+    def matvec(self, array_id: int, x: torch.Tensor, y: torch.Tensor = None, prec="fp64") -> torch.Tensor:
+        p = _prec(prec)
+        W = self._check_vec(array_id, x, p, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        if self._check_vec(array_id, y, p, "y") != W:
+            raise ValueError("x and y must have the same number of columns")
+        self.sync_stream()
+        abi.mlfft_matvec(self.h, array_id, W, x.data_ptr(), y.data_ptr(), p)
+        return y
+
+    def precond_apply(self, array_id: int, r: torch.Tensor, z: torch.Tensor = None, kind: int = 1,
+                      prec="fp64") -> torch.Tensor:
+        p = _prec(prec)
+        W = self._check_vec(array_id, r, p, "r")
+        if z is None:
+            z = torch.empty_like(r)
+        if self._check_vec(array_id, z, p, "z") != W:
+            raise ValueError("r and z must have the same number of columns")
+        self.sync_stream()
+        abi.mlfft_precond_apply(self.h, array_id, kind, W, r.data_ptr(), z.data_ptr(), p)
+        return z
+
+    # ---------------------------------------------------------------- solve
+    @staticmethod
+    def make_opts(**kw) -> abi.SolveOpts:
+        o = abi.mlfft_solve_default_opts()
+        for k, v in kw.items():
+            if k == "inner_prec":
+                v = _prec(v)
+            if not hasattr(o, k):
+                raise ValueError(f"unknown solve option {k}")
+            setattr(o, k, v)
+        return o
+
+    @staticmethod
+    def _info(Wt: int, history_len: int):
+        arrs = dict(iters=np.zeros(Wt, np.int32), outer=np.zeros(Wt, np.int32), relres=np.zeros(Wt),
+                    converged=np.zeros(Wt, np.int32),
+                    history=np.zeros(max(history_len, 1) * Wt))
+        info = abi.SolveInfo()
+        info.iters = arrs["iters"].ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        info.outer = arrs["outer"].ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        info.relres = arrs["relres"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        info.converged = arrs["converged"].ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        info.history = arrs["history"].ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if history_len else None
+        info.history_len = history_len
+        return info, arrs
+
+    @staticmethod
+    def _pack(info, arrs, status, Wt, history_len):
+        out = dict(status=status, iters=arrs["iters"].copy(), outer=arrs["outer"].copy(),
+                   relres=arrs["relres"].copy(), converged=arrs["converged"].astype(bool),
+                   fallbacks=info.fallbacks, matvecs64=info.matvecs64, matvecs_inner=info.matvecs_inner,
+                   precond_applies=info.precond_applies, net_applies=info.net_applies)
+        if history_len:
+            out["history"] = arrs["history"].reshape(history_len, Wt).copy()
+        return out
+
+    def solve(self, array_id: int, V: torch.Tensor, I: torch.Tensor = None, history_len: int = 0, **opts):
+        """Solve Z I = V (complex128 device tensors of shape (W, N)); returns (I, info dict)."""
+        W = self._check_vec(array_id, V, abi.MLFFT_FP64, "V")
+        if I is None:
+            I = torch.zeros_like(V)
+        self._check_vec(array_id, I, abi.MLFFT_FP64, "I")
+        o = self.make_opts(record_history=1 if history_len else 0, **opts)
+        info, arrs = self._info(W, history_len)
+        self.sync_stream()
+        st = abi.mlfft_solve(self.h, array_id, W, V.data_ptr(), I.data_ptr(), o, info)
+        return I, self._pack(info, arrs, st, W, history_len)
+
+    def solve_batch(self, array_ids, Vs, Is=None, history_len: int = 0, **opts):
+        """One batched solve over several arrays; returns (list of I, info dict over the concatenated columns)."""
+        Ws = [self._check_vec(a, v, abi.MLFFT_FP64, "V") for a, v in zip(array_ids, Vs)]
+        if Is is None:
+            Is = [torch.zeros_like(v) for v in Vs]
+        for a, i in zip(array_ids, Is):
+            self._check_vec(a, i, abi.MLFFT_FP64, "I")
+        o = self.make_opts(record_history=1 if history_len else 0, **opts)
+        Wt = sum(Ws)
+        info, arrs = self._info(Wt, history_len)
+        self.sync_stream()
+        st = abi.mlfft_solve_batch(self.h, list(array_ids), Ws, [v.data_ptr() for v in Vs],
+                                   [i.data_ptr() for i in Is], o, info)
+        return Is, self._pack(info, arrs, st, Wt, history_len)

@@ -1,0 +1,75 @@
+"""Build the HIP library libmlfft.so for gfx950, in-tree.
+
+    python -m paper_2506_20350_amd.build [-j N] [-v]
+
+Generates the FFT codelet header, compiles every source in csrc/ with hipcc
+(--offload-arch=gfx950, packed-FP32 instructions disabled) in parallel and
+links paper_2506_20350_amd/lib/libmlfft.so.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(PKG, "_build")
+LIBDIR = os.path.join(PKG, "lib")
+LIB = os.path.join(LIBDIR, "libmlfft.so")
+
+SOURCES = ["fft2d.hip", "bgemm.hip", "setup.hip", "krylov.hip", "net.hip", "lib.cpp", "solve.cpp", "netapi.cpp"]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wno-unused-result", "-I", CSRC, "-I", os.path.join(ROOT, "include")]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l)
+    if p.returncode != 0:
+        raise RuntimeError(f"command failed ({p.returncode}): {' '.join(cmd)}\n{out}")
+    if verbose and out.strip():
+        print(out)
+    return out
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(LIBDIR, exist_ok=True)
+    _run([sys.executable, os.path.join(CSRC, "gen_fft.py"), os.path.join(CSRC, "fft_codelets.h"), "32"], verbose)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in srcs]
+    jobs = jobs or min(8, os.cpu_count() or 1)
+
+    def comp(i):
+        return _run([HIPCC] + CFLAGS + ["-c", os.path.join(CSRC, srcs[i]), "-o", objs[i]], verbose)
+
+    # the heaviest translation units first
+    order = sorted(range(len(srcs)), key=lambda i: -os.path.getsize(os.path.join(CSRC, srcs[i])))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(comp, order))
+    tmp = LIB + ".tmp"
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs, verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("-v", action="store_true")
+    a = ap.parse_args()
+    print(build(a.j, a.v))
+
+
+if __name__ == "__main__":
+    main()

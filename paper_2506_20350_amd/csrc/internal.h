@@ -1,0 +1,76 @@
+// Internal declarations shared by the kernels' translation units and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include "common.h"
+
+namespace mlfft {
+
+constexpr int kMaxGrid = 32;      // largest Nx, Ny handled by the in-register FFT codelets
+
+// One array's share of a grouped 2-D FFT launch over W columns.
+// Spatial layout (paper order of a column): in[w][iy][ix][m], m < b.
+// Spectral layout: out[k][w][m] with k = ky*Px + kx.
+// pad = 1: the Py x Px = 2Ny x 2Nx circulant grid of the MLFFT product (input
+//          zero-padded, inverse output cropped to Ny x Nx);
+// pad = 0: the Ny x Nx torus of the block-circulant preconditioner.
+struct FftTask {
+    const void* in;
+    void* out;
+    const void* addend;     // inverse only: optional, same layout as out
+    double alpha;           // inverse only: out = alpha * F^{-1}(in) [+ beta * addend]
+    double beta;
+    int Nx, Ny, b, W;
+    int cm;                 // basis functions per workgroup (m chunk)
+    int nmc;                // number of m chunks
+    int block_begin;        // first workgroup of this task in the grouped grid
+    int pad;
+};
+
+// One array's share of a grouped per-frequency block product
+// Y[k][w][m] = sum_n G[k][m][n] X[k][w][n]  (k < K, w < W, m, n < b).
+struct GemmTask {
+    const void* G;          // [K][b][b] complex (double2 / float2 / bf16 pairs)
+    const void* X;          // [K][W][b]
+    void* Y;                // [K][W][b]
+    long gstride;           // elements between consecutive G[k] (b*b; 0 = one G shared by all k)
+    int K, b, W;
+    int mgroups;            // workgroups per frequency (row groups)
+    int block_begin;
+};
+
+enum Prec { P64 = 0, P32 = 1, PBF16 = 2 };
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_fft_fwd(int prec, const FftTask* tasks_host, const FftTask* tasks_dev, int ntasks,
+                          hipStream_t s);
+hipError_t launch_fft_inv(int prec, const FftTask* tasks_host, const FftTask* tasks_dev, int ntasks,
+                          hipStream_t s);
+// fills cm / nmc / block_begin for a list of tasks; returns the total grid size and the
+// block size / dynamic LDS bytes the grouped launch needs
+void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block, size_t* lds);
+
+hipError_t launch_bgemm(int prec, const GemmTask* tasks_host, const GemmTask* tasks_dev, int ntasks,
+                        hipStream_t s);
+void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int* grid, int* bp_max);
+int gemm_bp(int prec, int b);
+
+// spectra / preconditioner setup (all FP64)
+hipError_t launch_lag_dft_x(const double2* R, double2* T, int nlagy, int nlagx, int lagx0, int Px,
+                            const double* wx, int bb, hipStream_t s);
+hipError_t launch_lag_dft_y(const double2* T, double2* G, int nlagy, int lagy0, int Py, int Px,
+                            const double* wy, int bb, hipStream_t s);
+hipError_t launch_cast_c64_to_c32(const double2* a, float2* b, size_t n, hipStream_t s);
+hipError_t launch_cast_c64_to_bf16(const double2* a, uint32_t* b, size_t n, hipStream_t s);
+hipError_t launch_batched_inverse(double2* A, double2* Ainv, double* rcond, int* info, int nb, int b,
+                                  hipStream_t s);
+hipError_t launch_fill_identity_fallback(double2* Sinv, const double2* R00inv, const int* bad,
+                                         int nb, int b, hipStream_t s);
+
+}  // namespace mlfft
+
+namespace mlfft {
+hipError_t launch_nonfinite(const double* a, size_t n, int* flag, hipStream_t s);
+hipError_t launch_replicate(double2* dst, const double2* src, int nb, int bb, hipStream_t s);
+}  // namespace mlfft

@@ -1,0 +1,445 @@
+// Batched per-RHS restarted GMRES building blocks (Sec. III-C: GMRES driven by
+// a matvec and a preconditioner; one independent Krylov space per right-hand
+// side, all W of them advanced together).
+//
+// Storage: the Krylov basis is Vb[i][w][n] (i-th basis vector of column w,
+// n < N = Nx*Ny*b) in the inner precision (complex64 or complex128); the
+// Hessenberg matrices, Givens rotations and least-squares right-hand sides are
+// complex128 per column: H[w][i][j] ((m+1) x m, row-major), cs[w][j],
+// sn[w][j], g[w][i].  All inner products and norms accumulate in FP64.
+// state[w]: 0 = iterating in this cycle, 1 = done for this cycle, 2 = inactive.
+// Columns of several arrays share one launch: column w of a vector starts at
+// element coff[w] and has cN[w] entries; basis vector i lives at i * S.
+#include "internal.h"
+#include "krylov.h"
+
+namespace mlfft {
+
+template<typename C> struct Acc;   // widen a stored complex to complex128
+template<> struct Acc<float2> { static __device__ __forceinline__ double2 w(float2 a) { return make_double2(a.x, a.y); } };
+template<> struct Acc<double2> { static __device__ __forceinline__ double2 w(double2 a) { return a; } };
+
+template<typename C> __device__ __forceinline__ C narrow(double2 a);
+template<> __device__ __forceinline__ float2 narrow<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+template<> __device__ __forceinline__ double2 narrow<double2>(double2 a) { return a; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide sums (256 threads = 4 waves) of the CNT per-thread values vals[i]
+// for i < lim and i = CNT-1; results land in out[] (LDS) for all threads.  The
+// loop bound is a compile-time constant so vals[] stays in registers.
+template<int CNT>
+__device__ __forceinline__ void block_sum(const double* vals, int lim, double* red, double* out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < CNT; ++i) {
+        if (i < lim || i == CNT - 1) {
+            const double s = wave_sum(vals[i]);
+            if (lane == 0) red[wave * 72 + i] = s;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < CNT; i += blockDim.x) {
+        if (i < lim || i == CNT - 1) {
+            double s = 0.0;
+            for (int q = 0; q < nw; ++q) s += red[q * 72 + i];
+            out[i] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Per-column norms ||x_w||_2 in FP64.
+template<typename C>
+__global__ void __launch_bounds__(256) colnorm_kernel(const C* __restrict__ x, const size_t* __restrict__ coff,
+                                                      const int* __restrict__ cN, double* __restrict__ out) {
+    __shared__ double red[4 * 72];
+    __shared__ double res[1];
+    const C* xw = x + coff[blockIdx.x];
+    const size_t N = cN[blockIdx.x];
+    double s = 0.0;
+    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+        const double2 v = Acc<C>::w(xw[n]);
+        s = fma(v.x, v.x, fma(v.y, v.y, s));
+    }
+    block_sum<1>(&s, 0, red, res);
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(res[0]);
+}
+
+// One Arnoldi step for every iterating column: orthogonalise u = Vb[j+1] against
+// Vb[0..j] (classical Gram-Schmidt, applied twice when orth == 2), store the
+// coefficients in H[:, j] and u / ||u|| in Vb[j+1].
+template<typename C, int MAXJ>
+__global__ void __launch_bounds__(256) arnoldi_kernel(C* __restrict__ Vb, int j, size_t vstride,
+                                                      const size_t* __restrict__ coff, const int* __restrict__ cN,
+                                                      double2* __restrict__ H, int m, const int* __restrict__ state,
+                                                      int orth) {
+    __shared__ double red[4 * 72];
+    __shared__ double sh[2 * MAXJ + 1];
+    __shared__ double h1[2 * MAXJ + 2];
+    const int w = blockIdx.x;
+    const size_t N = cN[w];
+    const C* __restrict__ V = Vb + coff[w];
+    C* __restrict__ u = Vb + (size_t)(j + 1) * vstride + coff[w];
+    if (state[w] != 0) {
+        // retired column: keep its unused basis slot at zero so repeated products stay finite
+        for (size_t n = threadIdx.x; n < N; n += blockDim.x) u[n] = narrow<C>(make_double2(0.0, 0.0));
+        return;
+    }
+    double vals[2 * MAXJ + 1];
+    // pass 1: h1 = V^H u and ||u||^2
+#pragma unroll
+    for (int i = 0; i < 2 * MAXJ + 1; ++i) vals[i] = 0.0;
+    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+        const double2 un = Acc<C>::w(u[n]);
+        vals[2 * MAXJ] = fma(un.x, un.x, fma(un.y, un.y, vals[2 * MAXJ]));
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i) {
+            if (i <= j) {
+                const double2 v = Acc<C>::w(V[(size_t)i * vstride + n]);
+                vals[2 * i] = fma(v.x, un.x, fma(v.y, un.y, vals[2 * i]));
+                vals[2 * i + 1] = fma(v.x, un.y, fma(-v.y, un.x, vals[2 * i + 1]));
+            }
+        }
+    }
+    // reduce the j+1 coefficients and the norm (kept in the last slot)
+    block_sum<2 * MAXJ + 1>(vals, 2 * (j + 1), red, sh);
+    for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) h1[i] = sh[i];
+    if (threadIdx.x == 0) h1[2 * (j + 1)] = sh[2 * MAXJ];
+    __syncthreads();
+    double beta2;
+    if (orth == 2) {
+        // pass 2: h2 = V^H u' and ||u'||^2 with u' = u - V h1 (u' is not stored)
+#pragma unroll
+        for (int i = 0; i < 2 * MAXJ + 1; ++i) vals[i] = 0.0;
+        for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+            double2 up = Acc<C>::w(u[n]);
+            double2 vv[MAXJ];
+#pragma unroll
+            for (int i = 0; i < MAXJ; ++i) {
+                if (i <= j) {
+                    vv[i] = Acc<C>::w(V[(size_t)i * vstride + n]);
+                    const double hr = h1[2 * i], hi = h1[2 * i + 1];
+                    up.x -= hr * vv[i].x - hi * vv[i].y;
+                    up.y -= hr * vv[i].y + hi * vv[i].x;
+                }
+            }
+            vals[2 * MAXJ] = fma(up.x, up.x, fma(up.y, up.y, vals[2 * MAXJ]));
+#pragma unroll
+            for (int i = 0; i < MAXJ; ++i) {
+                if (i <= j) {
+                    vals[2 * i] = fma(vv[i].x, up.x, fma(vv[i].y, up.y, vals[2 * i]));
+                    vals[2 * i + 1] = fma(vv[i].x, up.y, fma(-vv[i].y, up.x, vals[2 * i + 1]));
+                }
+            }
+        }
+        block_sum<2 * MAXJ + 1>(vals, 2 * (j + 1), red, sh);
+        // ||u''||^2 = ||u'||^2 - ||h2||^2 (h2 is at rounding level; the subtraction is benign)
+        double hn = 0.0;
+        for (int i = 0; i <= j; ++i) hn += sh[2 * i] * sh[2 * i] + sh[2 * i + 1] * sh[2 * i + 1];
+        beta2 = sh[2 * MAXJ] - hn;
+        __syncthreads();
+        for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) h1[i] += sh[i];
+        __syncthreads();
+    } else {
+        double hn = 0.0;
+        for (int i = 0; i <= j; ++i) hn += h1[2 * i] * h1[2 * i] + h1[2 * i + 1] * h1[2 * i + 1];
+        beta2 = h1[2 * (j + 1)] - hn;
+    }
+    const double unorm2 = h1[2 * (j + 1)];
+    double beta = beta2 > 0.0 ? sqrt(beta2) : 0.0;
+    // happy breakdown: the new direction vanishes relative to the matvec output
+    const bool brk = !(beta > 1e-14 * sqrt(unorm2)) || !(beta > 1e-300);
+    if (brk) beta = 0.0;
+    const double inv = brk ? 0.0 : 1.0 / beta;
+    // pass 3: v_{j+1} = (u - V h) / beta, in place
+    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+        double2 up = Acc<C>::w(u[n]);
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i) {
+            if (i <= j) {
+                const double2 v = Acc<C>::w(V[(size_t)i * vstride + n]);
+                const double hr = h1[2 * i], hi = h1[2 * i + 1];
+                up.x -= hr * v.x - hi * v.y;
+                up.y -= hr * v.y + hi * v.x;
+            }
+        }
+        u[n] = narrow<C>(make_double2(up.x * inv, up.y * inv));
+    }
+    if (threadIdx.x <= j) {
+        H[((size_t)w * (m + 1) + threadIdx.x) * m + j] = make_double2(h1[2 * threadIdx.x], h1[2 * threadIdx.x + 1]);
+    }
+    if (threadIdx.x == 0) H[((size_t)w * (m + 1) + j + 1) * m + j] = make_double2(beta, 0.0);
+}
+
+// Apply the earlier rotations to H[:, j], build rotation j, update g, record
+// the residual estimate |g[j+1]| and retire columns that reached their target.
+__global__ void givens_kernel(double2* __restrict__ H, double* __restrict__ cs, double2* __restrict__ sn,
+                              double2* __restrict__ g, int j, int m, int W, int* __restrict__ state,
+                              const double* __restrict__ target, int* __restrict__ kcyc, int* __restrict__ iters,
+                              double* __restrict__ est, double* __restrict__ hist, int hist_len,
+                              const double* __restrict__ scale) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= W || state[w] != 0) return;
+    double2* Hw = H + (size_t)w * (m + 1) * m;
+    double* csw = cs + (size_t)w * m;
+    double2* snw = sn + (size_t)w * m;
+    double2* gw = g + (size_t)w * (m + 1);
+    for (int i = 0; i < j; ++i) {
+        const double2 a = Hw[i * m + j], b = Hw[(i + 1) * m + j];
+        const double c = csw[i];
+        const double2 s = snw[i];
+        // [c, s; -conj(s), c] [a; b]
+        Hw[i * m + j] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
+        Hw[(i + 1) * m + j] = make_double2(-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y);
+    }
+    const double2 a = Hw[j * m + j], b = Hw[(j + 1) * m + j];
+    const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+    double c;
+    double2 s;
+    if (nb == 0.0) { c = 1.0; s = make_double2(0.0, 0.0); }
+    else if (na == 0.0) { c = 0.0; s = make_double2(b.x / nb, -b.y / nb); }
+    else {
+        const double r = hypot(na, nb);
+        c = na / r;
+        // s = (a/|a|) conj(b) / r
+        const double2 ph = make_double2(a.x / na, a.y / na);
+        s = make_double2((ph.x * b.x + ph.y * b.y) / r, (ph.y * b.x - ph.x * b.y) / r);
+    }
+    csw[j] = c;
+    snw[j] = s;
+    Hw[j * m + j] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
+    Hw[(j + 1) * m + j] = make_double2(0.0, 0.0);
+    const double2 gj = gw[j];
+    gw[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+    gw[j] = make_double2(c * gj.x, c * gj.y);
+    const double e = hypot(gw[j + 1].x, gw[j + 1].y);
+    est[w] = e;
+    kcyc[w] = j + 1;
+    const int it = ++iters[w];
+    if (hist && it <= hist_len) hist[(size_t)(it - 1) * W + w] = e * (scale ? scale[w] : 1.0);
+    if (!(e > target[w]) || nb == 0.0) state[w] = 1;
+}
+
+// Start a cycle: beta = ||r_w||; columns at or below target become inactive;
+// v_0 = r / beta, g = (beta, 0, ...).
+template<typename C>
+__global__ void __launch_bounds__(256) cycle_start_kernel(const C* __restrict__ r, C* __restrict__ v0,
+                                                          const size_t* __restrict__ coff, const int* __restrict__ cN,
+                                                          double2* __restrict__ g, int m, int* __restrict__ state,
+                                                          const double* __restrict__ target, int* __restrict__ kcyc,
+                                                          double* __restrict__ est) {
+    __shared__ double red[4 * 72];
+    __shared__ double res[1];
+    const int w = blockIdx.x;
+    const size_t N = cN[w];
+    C* vw = v0 + coff[w];
+    if (state[w] == 2) {
+        if (threadIdx.x == 0) kcyc[w] = 0;
+        for (size_t n = threadIdx.x; n < N; n += blockDim.x) vw[n] = narrow<C>(make_double2(0.0, 0.0));
+        return;
+    }
+    const C* rw = r + coff[w];
+    double s = 0.0;
+    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+        const double2 v = Acc<C>::w(rw[n]);
+        s = fma(v.x, v.x, fma(v.y, v.y, s));
+    }
+    block_sum<1>(&s, 0, red, res);
+    const double beta = sqrt(res[0]);
+    const bool done = !(beta > target[w]);
+    if (threadIdx.x == 0) {
+        est[w] = beta;
+        kcyc[w] = 0;
+        state[w] = done ? 2 : 0;
+        for (int i = 0; i <= m; ++i) g[(size_t)w * (m + 1) + i] = make_double2(i == 0 ? beta : 0.0, 0.0);
+    }
+    const double inv = done ? 0.0 : 1.0 / beta;
+    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+        const double2 v = Acc<C>::w(rw[n]);
+        vw[n] = narrow<C>(make_double2(v.x * inv, v.y * inv));
+    }
+}
+
+// y = H(1:k, 1:k)^{-1} g(1:k) per column (upper triangular after the rotations).
+__global__ void lsq_kernel(const double2* __restrict__ H, const double2* __restrict__ g, double2* __restrict__ y,
+                           const int* __restrict__ kcyc, int m, int W) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= W) return;
+    const int k = kcyc[w];
+    const double2* Hw = H + (size_t)w * (m + 1) * m;
+    const double2* gw = g + (size_t)w * (m + 1);
+    double2* yw = y + (size_t)w * m;
+    for (int i = k - 1; i >= 0; --i) {
+        double2 s = gw[i];
+        for (int l = i + 1; l < k; ++l) {
+            const double2 h = Hw[i * m + l], yl = yw[l];
+            s.x -= h.x * yl.x - h.y * yl.y;
+            s.y -= h.x * yl.y + h.y * yl.x;
+        }
+        const double2 d = Hw[i * m + i];
+        const double den = d.x * d.x + d.y * d.y;
+        yw[i] = den > 0.0 ? make_double2((s.x * d.x + s.y * d.y) / den, (s.y * d.x - s.x * d.y) / den)
+                          : make_double2(0.0, 0.0);
+    }
+    for (int i = k; i < m; ++i) yw[i] = make_double2(0.0, 0.0);
+}
+
+// out_w (+)= sum_{i < k_w} y[w][i] B_i[w]  (accumulate != 0 adds to out)
+template<typename C>
+__global__ void __launch_bounds__(256) combine_kernel(const C* __restrict__ B, size_t bstride,
+                                                      const size_t* __restrict__ coff, const int* __restrict__ cN,
+                                                      const double2* __restrict__ y, const int* __restrict__ kcyc,
+                                                      int m, C* __restrict__ out, int accumulate) {
+    const int w = blockIdx.y;
+    const int k = kcyc[w];
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (size_t)cN[w]) return;
+    const size_t o = coff[w] + n;
+    double2 acc = accumulate ? Acc<C>::w(out[o]) : make_double2(0.0, 0.0);
+    for (int i = 0; i < k; ++i) {
+        const double2 yi = y[(size_t)w * m + i];
+        const double2 b = Acc<C>::w(B[(size_t)i * bstride + o]);
+        acc.x += yi.x * b.x - yi.y * b.y;
+        acc.y += yi.x * b.y + yi.y * b.x;
+    }
+    if (k > 0 || !accumulate) out[o] = narrow<C>(acc);
+}
+
+// dst += src (per column, same precision)
+template<typename C>
+__global__ void add_cols_kernel(C* __restrict__ dst, const C* __restrict__ src, const size_t* __restrict__ coff,
+                                const int* __restrict__ cN) {
+    const int w = blockIdx.y;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (size_t)cN[w]) return;
+    const size_t o = coff[w] + n;
+    const double2 a = Acc<C>::w(dst[o]), b = Acc<C>::w(src[o]);
+    dst[o] = narrow<C>(make_double2(a.x + b.x, a.y + b.y));
+}
+
+// dst = src * s[w] (per column real scale; converts precision)
+template<typename A, typename B>
+__global__ void scale_cols_kernel(const A* __restrict__ src, B* __restrict__ dst, const size_t* __restrict__ coff,
+                                  const int* __restrict__ cN, const double* __restrict__ s, int invert) {
+    const int w = blockIdx.y;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (size_t)cN[w]) return;
+    const size_t o = coff[w] + n;
+    double f = s ? s[w] : 1.0;
+    if (invert) f = f > 0.0 ? 1.0 / f : 0.0;
+    const double2 v = Acc<A>::w(src[o]);
+    dst[o] = narrow<B>(make_double2(v.x * f, v.y * f));
+}
+
+// x64 += s[w] * d (d in the inner precision)
+template<typename C>
+__global__ void axpy_cols_kernel(double2* __restrict__ x, const C* __restrict__ d, const size_t* __restrict__ coff,
+                                 const int* __restrict__ cN, const double* __restrict__ s, const int* __restrict__ mask) {
+    const int w = blockIdx.y;
+    if (mask && !mask[w]) return;
+    const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (size_t)cN[w]) return;
+    const size_t o = coff[w] + n;
+    const double f = s ? s[w] : 1.0;
+    const double2 v = Acc<C>::w(d[o]);
+    double2 xo = x[o];
+    xo.x = fma(f, v.x, xo.x);
+    xo.y = fma(f, v.y, xo.y);
+    x[o] = xo;
+}
+
+// ------------------------------------------------------------------ launchers
+
+static dim3 cols_grid(size_t maxN, int W) { return dim3((unsigned)((maxN + 255) / 256), (unsigned)W); }
+
+template<typename C>
+hipError_t k_colnorm(const void* x, const Cols& c, double* out, hipStream_t s) {
+    if (c.W <= 0) return hipSuccess;
+    hipLaunchKernelGGL(colnorm_kernel<C>, dim3(c.W), dim3(256), 0, s, (const C*)x, c.off, c.N, out);
+    return hipGetLastError();
+}
+
+template<typename C>
+hipError_t k_arnoldi(void* Vb, int j, const Cols& c, double2* H, int m, const int* state, int orth, hipStream_t s) {
+    const int need = j + 1;
+    const size_t S = c.S;
+    if (need <= 4)       hipLaunchKernelGGL((arnoldi_kernel<C, 4>), dim3(c.W), dim3(256), 0, s, (C*)Vb, j, S, c.off, c.N, H, m, state, orth);
+    else if (need <= 8)  hipLaunchKernelGGL((arnoldi_kernel<C, 8>), dim3(c.W), dim3(256), 0, s, (C*)Vb, j, S, c.off, c.N, H, m, state, orth);
+    else if (need <= 16) hipLaunchKernelGGL((arnoldi_kernel<C, 16>), dim3(c.W), dim3(256), 0, s, (C*)Vb, j, S, c.off, c.N, H, m, state, orth);
+    else if (need <= 32) hipLaunchKernelGGL((arnoldi_kernel<C, 32>), dim3(c.W), dim3(256), 0, s, (C*)Vb, j, S, c.off, c.N, H, m, state, orth);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t k_givens(double2* H, double* cs, double2* sn, double2* g, int j, int m, int W, int* state,
+                    const double* target, int* kcyc, int* iters, double* est, double* hist, int hist_len,
+                    const double* scale, hipStream_t s) {
+    hipLaunchKernelGGL(givens_kernel, dim3((W + 63) / 64), dim3(64), 0, s, H, cs, sn, g, j, m, W, state, target, kcyc,
+                       iters, est, hist, hist_len, scale);
+    return hipGetLastError();
+}
+
+template<typename C>
+hipError_t k_cycle_start(const void* r, void* v0, const Cols& c, double2* g, int m, int* state, const double* target,
+                         int* kcyc, double* est, hipStream_t s) {
+    hipLaunchKernelGGL(cycle_start_kernel<C>, dim3(c.W), dim3(256), 0, s, (const C*)r, (C*)v0, c.off, c.N, g, m, state,
+                       target, kcyc, est);
+    return hipGetLastError();
+}
+
+hipError_t k_lsq(const double2* H, const double2* g, double2* y, const int* kcyc, int m, int W, hipStream_t s) {
+    hipLaunchKernelGGL(lsq_kernel, dim3((W + 63) / 64), dim3(64), 0, s, H, g, y, kcyc, m, W);
+    return hipGetLastError();
+}
+
+template<typename C>
+hipError_t k_combine(const void* B, const Cols& c, const double2* y, const int* kcyc, int m, void* out, int acc,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel<C>, cols_grid(c.maxN, c.W), dim3(256), 0, s, (const C*)B, c.S, c.off, c.N, y,
+                       kcyc, m, (C*)out, acc);
+    return hipGetLastError();
+}
+
+template<typename C>
+hipError_t k_add_cols(void* dst, const void* src, const Cols& c, hipStream_t s) {
+    hipLaunchKernelGGL(add_cols_kernel<C>, cols_grid(c.maxN, c.W), dim3(256), 0, s, (C*)dst, (const C*)src, c.off,
+                       c.N);
+    return hipGetLastError();
+}
+
+template<typename A, typename B>
+hipError_t k_scale_cols(const void* src, void* dst, const Cols& c, const double* sc, int invert, hipStream_t s) {
+    hipLaunchKernelGGL((scale_cols_kernel<A, B>), cols_grid(c.maxN, c.W), dim3(256), 0, s, (const A*)src, (B*)dst,
+                       c.off, c.N, sc, invert);
+    return hipGetLastError();
+}
+
+template<typename C>
+hipError_t k_axpy_cols(double2* x, const void* d, const Cols& c, const double* sc, const int* mask, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_cols_kernel<C>, cols_grid(c.maxN, c.W), dim3(256), 0, s, x, (const C*)d, c.off, c.N, sc,
+                       mask);
+    return hipGetLastError();
+}
+
+#define INST(C)                                                                                                   \
+    template hipError_t k_colnorm<C>(const void*, const Cols&, double*, hipStream_t);                             \
+    template hipError_t k_arnoldi<C>(void*, int, const Cols&, double2*, int, const int*, int, hipStream_t);       \
+    template hipError_t k_cycle_start<C>(const void*, void*, const Cols&, double2*, int, int*, const double*,     \
+                                         int*, double*, hipStream_t);                                             \
+    template hipError_t k_combine<C>(const void*, const Cols&, const double2*, const int*, int, void*, int,       \
+                                     hipStream_t);                                                                \
+    template hipError_t k_add_cols<C>(void*, const void*, const Cols&, hipStream_t);                              \
+    template hipError_t k_axpy_cols<C>(double2*, const void*, const Cols&, const double*, const int*, hipStream_t);
+INST(float2)
+INST(double2)
+template hipError_t k_scale_cols<double2, float2>(const void*, void*, const Cols&, const double*, int, hipStream_t);
+template hipError_t k_scale_cols<double2, double2>(const void*, void*, const Cols&, const double*, int, hipStream_t);
+template hipError_t k_scale_cols<float2, float2>(const void*, void*, const Cols&, const double*, int, hipStream_t);
+template hipError_t k_scale_cols<float2, double2>(const void*, void*, const Cols&, const double*, int, hipStream_t);
+
+}  // namespace mlfft

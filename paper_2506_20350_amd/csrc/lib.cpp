@@ -1,0 +1,486 @@
+// C ABI of the MLFFT library: contexts, arrays (spectra and preconditioner
+// setup), the MLFFT matvec and the preconditioner apply.  The Krylov solver
+// driver lives in solve.cpp.
+#include "lib.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+using namespace mlfft;
+
+static thread_local std::string g_create_error;
+
+mlfft_status Ctx::fail(mlfft_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return st;
+}
+
+mlfft_status Ctx::hip_fail(hipError_t e, const char* what) {
+    (void)hipGetLastError();
+    if (e == hipErrorOutOfMemory) return fail(MLFFT_E_NOMEM, "%s: out of device memory", what);
+    return fail(MLFFT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+hipError_t Buf::ensure(size_t bytes) {
+    if (n >= bytes && p) return hipSuccess;
+    release();
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) { p = nullptr; n = 0; return e; }
+    n = bytes;
+    return hipSuccess;
+}
+
+void Buf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+}
+
+int* Ctx::pinned_state(int n) {
+    if (n > pinned_n) {
+        if (pinned) (void)hipHostFree(pinned);
+        pinned = nullptr;
+        pinned_n = 0;
+        if (hipHostMalloc((void**)&pinned, (size_t)n * sizeof(int), hipHostMallocDefault) != hipSuccess) return nullptr;
+        pinned_n = n;
+    }
+    return pinned;
+}
+
+Array* Ctx::find(int id) {
+    auto it = arrays.find(id);
+    return it == arrays.end() ? nullptr : &it->second;
+}
+
+size_t Array::bytes() const {
+    return G64.n + G32.n + G16.n + S64.n + S32.n + S16.n + K64.n + K32.n + K16.n;
+}
+
+void Array::release() {
+    G64.release(); G32.release(); G16.release();
+    S64.release(); S32.release(); S16.release();
+    K64.release(); K32.release(); K16.release();
+}
+
+#define HIPCHK(call, what)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return c->hip_fail(e_, what);  \
+    } while (0)
+
+int prec_elem_bytes(int prec) { return prec == P64 ? 16 : 8; }
+
+// ------------------------------------------------------------------ matvec core
+
+mlfft_status Ctx::upload_tasks(const void* host, size_t bytes, void** dev) {
+    // Task tables are small and a solve reuses the same few tables every
+    // iteration: keep each distinct table resident on the device, uploaded once
+    // with a blocking copy (so the host blob may be freed at once).
+    Ctx* c = this;
+    std::string key((const char*)host, bytes);
+    for (auto& e : task_cache)
+        if (e.first == key) { *dev = e.second.p; return MLFFT_OK; }
+    if (task_cache.size() >= 64) {
+        HIPCHK(hipStreamSynchronize(stream), "task cache flush");
+        task_cache.clear();
+    }
+    task_cache.emplace_back(key, Buf());
+    Buf& b = task_cache.back().second;
+    HIPCHK(b.ensure(bytes), "task table");
+    HIPCHK(hipMemcpy(b.p, host, bytes, hipMemcpyHostToDevice), "task table upload");
+    *dev = b.p;
+    return MLFFT_OK;
+}
+
+// y = alpha * Z x + beta * addend over a group of arrays (one grouped launch per phase)
+mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec) {
+    Ctx* c = this;
+    const int nt = (int)items.size();
+    if (nt == 0) return MLFFT_OK;
+    const int eb = prec_elem_bytes(prec);
+    // spectral workspaces
+    size_t need = 0;
+    std::vector<size_t> off(nt);
+    for (int i = 0; i < nt; ++i) {
+        const Array* a = items[i].arr;
+        off[i] = need;
+        need += (size_t)a->K * a->b * items[i].W * eb;
+        need = (need + 255) / 256 * 256;
+    }
+    HIPCHK(spec_a.ensure(need), "spectral workspace");
+    HIPCHK(spec_b.ensure(need), "spectral workspace");
+    std::vector<FftTask> fw(nt), iv(nt);
+    std::vector<GemmTask> gm(nt);
+    for (int i = 0; i < nt; ++i) {
+        const MatvecItem& it = items[i];
+        const Array* a = it.arr;
+        FftTask t{};
+        t.in = it.x; t.out = (char*)spec_a.p + off[i]; t.addend = nullptr; t.alpha = 1.0; t.beta = 0.0;
+        t.Nx = a->Nx; t.Ny = a->Ny; t.b = a->b; t.W = it.W; t.pad = 1;
+        fw[i] = t;
+        GemmTask g{};
+        g.G = prec == P64 ? a->G64.p : prec == P32 ? a->G32.p : a->G16.p;
+        g.X = (char*)spec_a.p + off[i]; g.Y = (char*)spec_b.p + off[i];
+        g.K = a->K; g.b = a->b; g.W = it.W; g.gstride = (long)a->b * a->b;
+        gm[i] = g;
+        FftTask u{};
+        u.in = (char*)spec_b.p + off[i]; u.out = it.y; u.addend = it.addend;
+        u.alpha = it.alpha / (double)a->K; u.beta = it.beta;
+        u.Nx = a->Nx; u.Ny = a->Ny; u.b = a->b; u.W = it.W; u.pad = 1;
+        iv[i] = u;
+    }
+    int grid, block, gridg, bpm;
+    size_t lds;
+    plan_fft_tasks(prec, fw.data(), nt, &grid, &block, &lds);
+    plan_fft_tasks(prec, iv.data(), nt, &grid, &block, &lds);
+    plan_gemm_tasks(prec, gm.data(), nt, &gridg, &bpm);
+    void* dfw = nullptr;
+    void* div = nullptr;
+    void* dgm = nullptr;
+    if (nt > 1) {
+        const size_t sf = sizeof(FftTask) * nt, sg = sizeof(GemmTask) * nt;
+        std::vector<char> blob(2 * sf + sg);
+        memcpy(blob.data(), fw.data(), sf);
+        memcpy(blob.data() + sf, iv.data(), sf);
+        memcpy(blob.data() + 2 * sf, gm.data(), sg);
+        void* d;
+        mlfft_status st = upload_tasks(blob.data(), blob.size(), &d);
+        if (st != MLFFT_OK) return st;
+        dfw = d; div = (char*)d + sf; dgm = (char*)d + 2 * sf;
+    }
+    HIPCHK(launch_fft_fwd(prec, fw.data(), (const FftTask*)dfw, nt, stream), "forward MLFFT launch");
+    HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, stream), "block product launch");
+    HIPCHK(launch_fft_inv(prec, iv.data(), (const FftTask*)div, nt, stream), "inverse MLFFT launch");
+    return MLFFT_OK;
+}
+
+// z = alpha * P^{-1} r (+ beta * addend) with the block-circulant or self-block preconditioner
+mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, int prec) {
+    Ctx* c = this;
+    const int nt = (int)items.size();
+    if (nt == 0) return MLFFT_OK;
+    const int eb = prec_elem_bytes(prec);
+    if (kind == 2) {
+        // self block: one b x b product per cell, the whole vector as one frequency
+        std::vector<GemmTask> gm(nt);
+        for (int i = 0; i < nt; ++i) {
+            const MatvecItem& it = items[i];
+            const Array* a = it.arr;
+            if (it.addend || it.alpha != 1.0) return fail(MLFFT_E_ARG, "self-block apply has no epilogue");
+            GemmTask g{};
+            g.G = prec == P64 ? a->K64.p : prec == P32 ? a->K32.p : a->K16.p;
+            g.X = it.x; g.Y = it.y; g.K = it.W; g.b = a->b; g.W = a->Nx * a->Ny; g.gstride = 0;
+            gm[i] = g;
+        }
+        int gridg, bpm;
+        plan_gemm_tasks(prec, gm.data(), nt, &gridg, &bpm);
+        void* dgm = nullptr;
+        if (nt > 1) {
+            mlfft_status st = upload_tasks(gm.data(), sizeof(GemmTask) * nt, &dgm);
+            if (st != MLFFT_OK) return st;
+        }
+        HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, stream), "self-block apply launch");
+        return MLFFT_OK;
+    }
+    size_t need = 0;
+    std::vector<size_t> off(nt);
+    for (int i = 0; i < nt; ++i) {
+        const Array* a = items[i].arr;
+        off[i] = need;
+        need += (size_t)a->Nx * a->Ny * a->b * items[i].W * eb;
+        need = (need + 255) / 256 * 256;
+    }
+    HIPCHK(spec_a.ensure(need), "preconditioner workspace");
+    HIPCHK(spec_b.ensure(need), "preconditioner workspace");
+    std::vector<FftTask> fw(nt), iv(nt);
+    std::vector<GemmTask> gm(nt);
+    for (int i = 0; i < nt; ++i) {
+        const MatvecItem& it = items[i];
+        const Array* a = it.arr;
+        FftTask t{};
+        t.in = it.x; t.out = (char*)spec_a.p + off[i]; t.alpha = 1.0;
+        t.Nx = a->Nx; t.Ny = a->Ny; t.b = a->b; t.W = it.W; t.pad = 0;
+        fw[i] = t;
+        GemmTask g{};
+        g.G = prec == P64 ? a->S64.p : prec == P32 ? a->S32.p : a->S16.p;
+        g.X = (char*)spec_a.p + off[i]; g.Y = (char*)spec_b.p + off[i];
+        g.K = a->Nx * a->Ny; g.b = a->b; g.W = it.W; g.gstride = (long)a->b * a->b;
+        gm[i] = g;
+        FftTask u{};
+        u.in = (char*)spec_b.p + off[i]; u.out = it.y; u.addend = it.addend;
+        u.alpha = it.alpha / (double)(a->Nx * a->Ny); u.beta = it.beta;
+        u.Nx = a->Nx; u.Ny = a->Ny; u.b = a->b; u.W = it.W; u.pad = 0;
+        iv[i] = u;
+    }
+    int grid, block, gridg, bpm;
+    size_t lds;
+    plan_fft_tasks(prec, fw.data(), nt, &grid, &block, &lds);
+    plan_fft_tasks(prec, iv.data(), nt, &grid, &block, &lds);
+    plan_gemm_tasks(prec, gm.data(), nt, &gridg, &bpm);
+    void* dfw = nullptr;
+    void* div = nullptr;
+    void* dgm = nullptr;
+    if (nt > 1) {
+        const size_t sf = sizeof(FftTask) * nt, sg = sizeof(GemmTask) * nt;
+        std::vector<char> blob(2 * sf + sg);
+        memcpy(blob.data(), fw.data(), sf);
+        memcpy(blob.data() + sf, iv.data(), sf);
+        memcpy(blob.data() + 2 * sf, gm.data(), sg);
+        void* d;
+        mlfft_status st = upload_tasks(blob.data(), blob.size(), &d);
+        if (st != MLFFT_OK) return st;
+        dfw = d; div = (char*)d + sf; dgm = (char*)d + 2 * sf;
+    }
+    HIPCHK(launch_fft_fwd(prec, fw.data(), (const FftTask*)dfw, nt, stream), "preconditioner FFT launch");
+    HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, stream), "preconditioner product launch");
+    HIPCHK(launch_fft_inv(prec, iv.data(), (const FftTask*)div, nt, stream), "preconditioner IFFT launch");
+    return MLFFT_OK;
+}
+
+// ------------------------------------------------------------------ setup
+
+static void strang_weights(int N, std::vector<double>& w) {
+    // lags -(N-1) .. N-1: weight 1 for 2|p| < N, 1/2 for 2|p| = N, 0 otherwise
+    w.assign(2 * N - 1, 0.0);
+    for (int p = -(N - 1); p < N; ++p) {
+        const int a = p < 0 ? -p : p;
+        w[p + N - 1] = 2 * a < N ? 1.0 : (2 * a == N ? 0.5 : 0.0);
+    }
+}
+
+static mlfft_status build_array(Ctx* c, Array& a, const double2* Rdev) {
+    const int Nx = a.Nx, Ny = a.Ny, b = a.b;
+    const int bb = b * b;
+    const int nly = 2 * Ny - 1, nlx = 2 * Nx - 1;
+    hipStream_t s = c->stream;
+    // spectra on the (2Ny) x (2Nx) grid
+    Buf T;
+    const size_t tb = (size_t)nly * a.Px * bb * sizeof(double2);
+    HIPCHK(T.ensure(tb), "spectra scratch");
+    HIPCHK(a.G64.ensure((size_t)a.K * bb * sizeof(double2)), "spectra");
+    HIPCHK(a.G32.ensure((size_t)a.K * bb * sizeof(float2)), "spectra");
+    HIPCHK(a.G16.ensure((size_t)a.K * bb * sizeof(uint32_t)), "spectra");
+    HIPCHK(launch_lag_dft_x(Rdev, (double2*)T.p, nly, nlx, -(Nx - 1), a.Px, nullptr, bb, s), "spectra x");
+    HIPCHK(launch_lag_dft_y((double2*)T.p, (double2*)a.G64.p, nly, -(Ny - 1), a.Py, a.Px, nullptr, bb, s),
+           "spectra y");
+    HIPCHK(launch_cast_c64_to_c32((double2*)a.G64.p, (float2*)a.G32.p, (size_t)a.K * bb, s), "spectra cast");
+    HIPCHK(launch_cast_c64_to_bf16((double2*)a.G64.p, (uint32_t*)a.G16.p, (size_t)a.K * bb, s), "spectra cast");
+    // Strang block circulant on the Ny x Nx torus
+    std::vector<double> wx, wy;
+    strang_weights(Nx, wx);
+    strang_weights(Ny, wy);
+    Buf Wt;
+    HIPCHK(Wt.ensure((wx.size() + wy.size()) * sizeof(double)), "weights");
+    HIPCHK(hipMemcpyAsync(Wt.p, wx.data(), wx.size() * sizeof(double), hipMemcpyHostToDevice, s), "weights");
+    HIPCHK(hipMemcpyAsync((double*)Wt.p + wx.size(), wy.data(), wy.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s), "weights");
+    const int Kp = Nx * Ny;
+    Buf Sh, Aw, rc, inf;
+    HIPCHK(Sh.ensure((size_t)Kp * bb * sizeof(double2)), "preconditioner scratch");
+    HIPCHK(launch_lag_dft_x(Rdev, (double2*)T.p, nly, nlx, -(Nx - 1), Nx, (double*)Wt.p, bb, s), "strang x");
+    HIPCHK(launch_lag_dft_y((double2*)T.p, (double2*)Sh.p, nly, -(Ny - 1), Ny, Nx, (double*)Wt.p + wx.size(), bb, s),
+           "strang y");
+    HIPCHK(a.S64.ensure((size_t)Kp * bb * sizeof(double2)), "preconditioner");
+    HIPCHK(a.S32.ensure((size_t)Kp * bb * sizeof(float2)), "preconditioner");
+    HIPCHK(a.S16.ensure((size_t)Kp * bb * sizeof(uint32_t)), "preconditioner");
+    HIPCHK(rc.ensure((size_t)(Kp + 1) * sizeof(double)), "rcond");
+    HIPCHK(inf.ensure((size_t)(Kp + 1) * sizeof(int)), "info");
+    HIPCHK(launch_batched_inverse((double2*)Sh.p, (double2*)a.S64.p, (double*)rc.p, (int*)inf.p, Kp, b, s),
+           "preconditioner inverse");
+    // self block inverse
+    HIPCHK(Aw.ensure((size_t)bb * sizeof(double2)), "self block");
+    HIPCHK(a.K64.ensure((size_t)bb * sizeof(double2)), "self block");
+    const double2* R00 = Rdev + ((size_t)(Ny - 1) * nlx + (Nx - 1)) * bb;
+    HIPCHK(hipMemcpyAsync(Aw.p, R00, (size_t)bb * sizeof(double2), hipMemcpyDeviceToDevice, s), "self block");
+    HIPCHK(launch_batched_inverse((double2*)Aw.p, (double2*)a.K64.p, (double*)rc.p + Kp, (int*)inf.p + Kp, 1, b, s),
+           "self block inverse");
+    std::vector<double> rcond(Kp + 1);
+    std::vector<int> info(Kp + 1);
+    HIPCHK(hipMemcpyAsync(rcond.data(), rc.p, (Kp + 1) * sizeof(double), hipMemcpyDeviceToHost, s), "rcond");
+    HIPCHK(hipMemcpyAsync(info.data(), inf.p, (Kp + 1) * sizeof(int), hipMemcpyDeviceToHost, s), "info");
+    HIPCHK(hipStreamSynchronize(s), "setup");
+    if (info[Kp] != 0 || !(rcond[Kp] >= 1e-14))
+        return c->fail(MLFFT_E_SINGULAR, "self block R_{0,0} is singular (rcond %.3e)", rcond[Kp]);
+    std::vector<int> bad(Kp);
+    a.pc_fallbacks = 0;
+    a.pc_min_rcond = 1.0;
+    for (int k = 0; k < Kp; ++k) {
+        bad[k] = (info[k] != 0 || !(rcond[k] >= 1e-12)) ? 1 : 0;
+        a.pc_fallbacks += bad[k];
+        if (rcond[k] < a.pc_min_rcond) a.pc_min_rcond = rcond[k];
+    }
+    if (a.pc_fallbacks) {
+        HIPCHK(hipMemcpyAsync(inf.p, bad.data(), Kp * sizeof(int), hipMemcpyHostToDevice, s), "fallback flags");
+        HIPCHK(launch_fill_identity_fallback((double2*)a.S64.p, (double2*)a.K64.p, (int*)inf.p, Kp, b, s),
+               "fallback");
+    }
+    HIPCHK(launch_cast_c64_to_c32((double2*)a.S64.p, (float2*)a.S32.p, (size_t)Kp * bb, s), "cast");
+    HIPCHK(launch_cast_c64_to_bf16((double2*)a.S64.p, (uint32_t*)a.S16.p, (size_t)Kp * bb, s), "cast");
+    HIPCHK(a.K32.ensure((size_t)bb * sizeof(float2)), "self block");
+    HIPCHK(a.K16.ensure((size_t)bb * sizeof(uint32_t)), "self block");
+    HIPCHK(launch_cast_c64_to_c32((double2*)a.K64.p, (float2*)a.K32.p, (size_t)bb, s), "cast");
+    HIPCHK(launch_cast_c64_to_bf16((double2*)a.K64.p, (uint32_t*)a.K16.p, (size_t)bb, s), "cast");
+    HIPCHK(hipStreamSynchronize(s), "setup");
+    // scratch buffers (T, Sh, Aw, ...) are released by their destructors after the sync
+    return MLFFT_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+mlfft_status mlfft_create(int device, void* hip_stream, mlfft_ctx* out) {
+    if (!out) { g_create_error = "out is NULL"; return MLFFT_E_ARG; }
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device < 0 || device >= n) {
+        g_create_error = "invalid device or no HIP device";
+        (void)hipGetLastError();
+        return MLFFT_E_ARG;
+    }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) { g_create_error = hipGetErrorString(e); return MLFFT_E_HIP; }
+    Ctx* c = new Ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return MLFFT_OK;
+}
+
+mlfft_status mlfft_destroy(mlfft_ctx ctx) {
+    if (!ctx) return MLFFT_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->arrays) kv.second.release();
+    ctx->release_workspaces();
+    delete ctx;
+    return MLFFT_OK;
+}
+
+const char* mlfft_last_error(mlfft_ctx ctx) {
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+mlfft_status mlfft_set_stream(mlfft_ctx ctx, void* hip_stream) {
+    if (!ctx) return MLFFT_E_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return MLFFT_OK;
+}
+
+mlfft_status mlfft_set_blocks(mlfft_ctx ctx, int array_id, int Nx, int Ny, int b, const void* blocks,
+                              int blocks_on_device) {
+    if (!ctx) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    if (array_id < 0) return c->fail(MLFFT_E_ARG, "array_id must be >= 0");
+    if (Nx < 1 || Ny < 1 || Nx > kMaxGrid || Ny > kMaxGrid)
+        return c->fail(MLFFT_E_ARG, "Nx, Ny must be in [1, %d] (got %d, %d)", kMaxGrid, Nx, Ny);
+    if (b < 1 || b > 256) return c->fail(MLFFT_E_ARG, "b must be in [1, 256] (got %d)", b);
+    if (!blocks) return c->fail(MLFFT_E_ARG, "blocks is NULL");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    const size_t nblk = (size_t)(2 * Ny - 1) * (2 * Nx - 1) * b * b;
+    if (!blocks_on_device) {
+        const double* h = (const double*)blocks;
+        for (size_t i = 0; i < 2 * nblk; ++i)
+            if (!std::isfinite(h[i])) return c->fail(MLFFT_E_ARG, "blocks contain a non-finite value at %zu", i / 2);
+    }
+    Buf R;
+    HIPCHK(R.ensure(nblk * sizeof(double2)), "block upload");
+    HIPCHK(hipMemcpyAsync(R.p, blocks, nblk * sizeof(double2),
+                          blocks_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream),
+           "block upload");
+    if (blocks_on_device) {
+        Buf flag;
+        HIPCHK(flag.ensure(sizeof(int)), "flag");
+        HIPCHK(hipMemsetAsync(flag.p, 0, sizeof(int), c->stream), "flag");
+        HIPCHK(launch_nonfinite((const double*)R.p, 2 * nblk, (int*)flag.p, c->stream), "finite check");
+        int hflag = 0;
+        HIPCHK(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream), "flag");
+        HIPCHK(hipStreamSynchronize(c->stream), "finite check");
+        if (hflag) return c->fail(MLFFT_E_ARG, "blocks contain a non-finite value");
+    }
+    auto old = c->arrays.find(array_id);
+    if (old != c->arrays.end()) {
+        HIPCHK(hipStreamSynchronize(c->stream), "replace array");
+        old->second.release();
+        c->arrays.erase(old);
+    }
+    Array a;
+    a.Nx = Nx; a.Ny = Ny; a.b = b;
+    a.Px = 2 * Nx; a.Py = 2 * Ny; a.K = a.Px * a.Py;
+    mlfft_status st = build_array(c, a, (const double2*)R.p);
+    if (st != MLFFT_OK) { a.release(); return st; }
+    c->arrays.emplace(array_id, std::move(a));
+    return MLFFT_OK;
+}
+
+mlfft_status mlfft_drop_array(mlfft_ctx ctx, int array_id) {
+    if (!ctx) return MLFFT_E_ARG;
+    auto it = ctx->arrays.find(array_id);
+    if (it == ctx->arrays.end()) return ctx->fail(MLFFT_E_STATE, "unknown array id %d", array_id);
+    (void)hipStreamSynchronize(ctx->stream);
+    it->second.release();
+    ctx->arrays.erase(it);
+    return MLFFT_OK;
+}
+
+mlfft_status mlfft_array_info(mlfft_ctx ctx, int array_id, mlfft_array_info_t* out) {
+    if (!ctx || !out) return MLFFT_E_ARG;
+    Array* a = ctx->find(array_id);
+    if (!a) return ctx->fail(MLFFT_E_STATE, "unknown array id %d", array_id);
+    out->Nx = a->Nx; out->Ny = a->Ny; out->b = a->b; out->Px = a->Px; out->Py = a->Py;
+    out->pc_fallbacks = a->pc_fallbacks;
+    out->pc_min_rcond = a->pc_min_rcond;
+    out->device_bytes = a->bytes();
+    return MLFFT_OK;
+}
+
+mlfft_status mlfft_matvec(mlfft_ctx ctx, int array_id, int W, const void* x, void* y, mlfft_prec prec) {
+    if (!ctx) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    Array* a = c->find(array_id);
+    if (!a) return c->fail(MLFFT_E_STATE, "unknown array id %d", array_id);
+    if (W < 0) return c->fail(MLFFT_E_ARG, "W must be >= 0");
+    if (prec < MLFFT_FP64 || prec > MLFFT_FP32_BF16GEMM) return c->fail(MLFFT_E_ARG, "invalid precision");
+    if (W == 0) return MLFFT_OK;
+    if (!x || !y) return c->fail(MLFFT_E_ARG, "x or y is NULL");
+    const size_t vb = (size_t)a->Nx * a->Ny * a->b * W * prec_elem_bytes(prec);
+    if ((const char*)x < (const char*)y + vb && (const char*)y < (const char*)x + vb)
+        return c->fail(MLFFT_E_ARG, "x and y overlap");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    std::vector<MatvecItem> items(1);
+    items[0] = MatvecItem{a, W, x, y, nullptr, 1.0, 0.0};
+    return c->matvec_group(items, prec);
+}
+
+mlfft_status mlfft_precond_apply(mlfft_ctx ctx, int array_id, int kind, int W, const void* r, void* z,
+                                 mlfft_prec prec) {
+    if (!ctx) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    Array* a = c->find(array_id);
+    if (!a) return c->fail(MLFFT_E_STATE, "unknown array id %d", array_id);
+    if (kind != 1 && kind != 2) return c->fail(MLFFT_E_ARG, "preconditioner kind must be 1 or 2");
+    if (W < 0) return c->fail(MLFFT_E_ARG, "W must be >= 0");
+    if (prec < MLFFT_FP64 || prec > MLFFT_FP32_BF16GEMM) return c->fail(MLFFT_E_ARG, "invalid precision");
+    if (W == 0) return MLFFT_OK;
+    if (!r || !z) return c->fail(MLFFT_E_ARG, "r or z is NULL");
+    const size_t vb = (size_t)a->Nx * a->Ny * a->b * W * prec_elem_bytes(prec);
+    if ((const char*)r < (const char*)z + vb && (const char*)z < (const char*)r + vb)
+        return c->fail(MLFFT_E_ARG, "r and z overlap");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    std::vector<MatvecItem> items(1);
+    items[0] = MatvecItem{a, W, r, z, nullptr, 1.0, 0.0};
+    return c->precond_group(items, kind, prec);
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Host-side state of the MLFFT library (contexts, arrays, workspaces).
+#pragma once
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "../../include/mlfft.h"
+
+namespace mlfft {
+
+struct Buf {
+    void* p = nullptr;
+    size_t n = 0;
+    Buf() = default;
+    Buf(const Buf&) = delete;
+    Buf& operator=(const Buf&) = delete;
+    Buf(Buf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    Buf& operator=(Buf&& o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~Buf() { release(); }
+    hipError_t ensure(size_t bytes);
+    void release();
+};
+
+struct Array {
+    int Nx = 0, Ny = 0, b = 0, Px = 0, Py = 0, K = 0;
+    Buf G64, G32, G16;      // block spectra [K][b][b]: complex128, complex64, bf16 pairs
+    Buf S64, S32, S16;      // Strang preconditioner inverse spectra [Nx*Ny][b][b]
+    Buf K64, K32, K16;      // self-block inverse R_{0,0}^{-1}
+    int pc_fallbacks = 0;
+    double pc_min_rcond = 1.0;
+    size_t bytes() const;
+    void release();
+};
+
+// y = alpha * Op(x) + beta * addend for one array (W columns)
+struct MatvecItem {
+    const Array* arr;
+    int W;
+    const void* x;
+    void* y;
+    const void* addend;
+    double alpha;
+    double beta;
+};
+
+}  // namespace mlfft
+
+struct mlfft_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::map<int, mlfft::Array> arrays;
+    mlfft::Buf spec_a, spec_b;     // spectral workspaces of the matvec / preconditioner
+    std::vector<std::pair<std::string, mlfft::Buf>> task_cache;   // device copies of grouped-launch task tables
+    mlfft::Buf solve_ws;           // Krylov workspace (solve.cpp)
+    mlfft::Buf solve_ws2;
+    int* pinned = nullptr;         // pinned host buffer for per-column state read-back
+    int pinned_n = 0;
+    struct Net* net = nullptr;     // learned preconditioner (netapi.cpp)
+
+    int* pinned_state(int n);
+    bool net_ready() const;
+    // z = learned correction of the block-circulant output y (W columns of array a)
+    mlfft_status net_correct(const mlfft::Array* a, int W, const void* y, void* z, int prec, int* fallbacks);
+    void net_release();
+
+    mlfft_status fail(mlfft_status st, const char* fmt, ...);
+    mlfft_status hip_fail(hipError_t e, const char* what);
+    mlfft::Array* find(int id);
+    mlfft_status upload_tasks(const void* host, size_t bytes, void** dev);
+    mlfft_status matvec_group(const std::vector<mlfft::MatvecItem>& items, int prec);
+    mlfft_status precond_group(const std::vector<mlfft::MatvecItem>& items, int kind, int prec);
+    void release_workspaces() {
+        spec_a.release(); spec_b.release(); task_cache.clear(); solve_ws.release(); solve_ws2.release();
+        if (pinned) (void)hipHostFree(pinned);
+        pinned = nullptr;
+        pinned_n = 0;
+        net_release();
+    }
+};
+
+typedef mlfft_ctx_s Ctx;
+
+int prec_elem_bytes(int prec);

@@ -1,0 +1,397 @@
+// Restarted (flexible) GMRES driver with FP64 iterative refinement, for one
+// array or a batch of arrays of different shapes (Sec. III-C; right-hand sides
+// are the element-port excitations of Sec. IV).
+//
+// Outer loop (FP64): r = V - Z x with the FP64 MLFFT product; every column whose
+// true relative residual ||r_w|| / ||V_w|| is above tol gets an inner solve of
+// Z d = r_w / ||r_w|| in the inner precision, and x_w += ||r_w|| d_w.
+// Inner solve: per-column restarted GMRES(m), right preconditioned (flexible
+// when the preconditioner is the learned correction), classical Gram-Schmidt
+// with re-orthogonalisation and FP64 accumulation, Givens least squares in FP64
+// and per-column retirement once the residual estimate meets the column's
+// target.  With the FP64 inner precision this is plain FP64 GMRES; the outer
+// loop then only confirms the true residual.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "krylov.h"
+#include "lib.h"
+
+using namespace mlfft;
+
+#define HIPCHK(call, what)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return c->hip_fail(e_, what);  \
+    } while (0)
+#define STCHK(call)                                          \
+    do {                                                     \
+        mlfft_status s_ = (call);                            \
+        if (s_ < 0) return s_;                               \
+    } while (0)
+
+namespace {
+
+struct Seg {           // one array of the batch
+    Array* arr;
+    int W;
+    size_t off;        // first element of the array's columns inside a batch vector
+    size_t N;          // unknowns per column
+    const void* V;     // caller's excitations (complex128)
+    void* I;           // caller's solution (complex128)
+};
+
+// Device memory for one solve, carved out of the context's solve workspaces.
+struct Work {
+    size_t S = 0;                 // elements of one batch vector
+    int Wt = 0;                   // total columns
+    size_t maxN = 0;
+    // FP64 vectors
+    double2 *v64, *x64, *r64;
+    // inner-precision vectors (bytes eb per element)
+    void *rT, *dT, *tmpT, *tmp2T, *Vb, *Zb;
+    // per column
+    size_t* coff;
+    int* cN;
+    double *vnorm, *rnorm, *target, *est, *hist;
+    int *state, *kcyc, *iters, *mask;
+    double2 *H, *g, *sn, *y;
+    double* cs;
+};
+
+}  // namespace
+
+static size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
+
+mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& o, mlfft_solve_info* info);
+
+extern "C" mlfft_status mlfft_solve_default_opts(mlfft_solve_opts* o) {
+    if (!o) return MLFFT_E_ARG;
+    o->restart = 30;
+    o->max_restarts = 100;
+    o->tol = 1e-6;
+    o->inner_prec = MLFFT_FP32;
+    o->inner_tol = 1e-4;
+    o->max_outer = 10;
+    o->precond = 1;
+    o->orth = 2;
+    o->x0_given = 0;
+    o->record_history = 0;
+    o->use_graph = 0;
+    return MLFFT_OK;
+}
+
+static mlfft_status check_opts(Ctx* c, const mlfft_solve_opts& o) {
+    if (o.restart < 1 || o.restart > 31) return c->fail(MLFFT_E_ARG, "restart must be in [1, 31]");
+    if (o.max_restarts < 1) return c->fail(MLFFT_E_ARG, "max_restarts must be >= 1");
+    if (!(o.tol > 0.0) || !(o.tol < 1.0)) return c->fail(MLFFT_E_ARG, "tol must be in (0, 1)");
+    if (o.inner_prec < MLFFT_FP64 || o.inner_prec > MLFFT_FP32_BF16GEMM)
+        return c->fail(MLFFT_E_ARG, "invalid inner precision");
+    if (o.inner_prec != MLFFT_FP64 && (!(o.inner_tol > 0.0) || !(o.inner_tol < 1.0)))
+        return c->fail(MLFFT_E_ARG, "inner_tol must be in (0, 1)");
+    if (o.max_outer < 1) return c->fail(MLFFT_E_ARG, "max_outer must be >= 1");
+    if (o.precond < 0 || o.precond > 3) return c->fail(MLFFT_E_ARG, "precond must be 0, 1, 2 or 3");
+    if (o.orth != 1 && o.orth != 2) return c->fail(MLFFT_E_ARG, "orth must be 1 or 2");
+    if (o.use_graph != 0 && o.use_graph != 1) return c->fail(MLFFT_E_ARG, "use_graph must be 0 or 1");
+    if (o.precond == 3 && !c->net_ready()) return c->fail(MLFFT_E_STATE, "learned preconditioner requested but no network is loaded");
+    return MLFFT_OK;
+}
+
+// y = alpha * Z x + beta * addend over all segments (x, y, addend are batch vectors)
+static mlfft_status batch_matvec(Ctx* c, std::vector<Seg>& segs, const void* x, void* y, const void* addend,
+                                 double alpha, double beta, int prec) {
+    const int eb = prec_elem_bytes(prec);
+    std::vector<MatvecItem> items;
+    for (auto& s : segs)
+        items.push_back(MatvecItem{s.arr, s.W, (const char*)x + s.off * eb, (char*)y + s.off * eb,
+                                   addend ? (const char*)addend + s.off * eb : nullptr, alpha, beta});
+    return c->matvec_group(items, prec);
+}
+
+// z = P^{-1} r (kind 1 / 2), or the learned correction of the block-circulant output (kind 3)
+static mlfft_status batch_precond(Ctx* c, std::vector<Seg>& segs, int kind, const void* r, void* z, void* scratch,
+                                  int prec, int* fallbacks) {
+    const int eb = prec_elem_bytes(prec);
+    std::vector<MatvecItem> items;
+    void* dst = kind == 3 ? scratch : z;
+    for (auto& s : segs)
+        items.push_back(MatvecItem{s.arr, s.W, (const char*)r + s.off * eb, (char*)dst + s.off * eb, nullptr, 1.0, 0.0});
+    STCHK(c->precond_group(items, kind == 3 ? 1 : kind, prec));
+    if (kind == 3) {
+        for (auto& s : segs) {
+            mlfft_status st = c->net_correct(s.arr, s.W, (const char*)scratch + s.off * eb, (char*)z + s.off * eb, prec,
+                                             fallbacks);
+            if (st < 0) return st;
+        }
+    }
+    return MLFFT_OK;
+}
+
+template<typename C>
+static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const Cols& cols, const mlfft_solve_opts& o,
+                                int prec, mlfft_solve_info* info, std::vector<int>& hstate) {
+    hipStream_t s = c->stream;
+    const int m = o.restart;
+    const int eb = prec_elem_bytes(prec);
+    const size_t vb = w.S * eb;
+    const bool flexible = o.precond == 3;
+    const int Wt = w.Wt;
+    int* pinned_state = c->pinned_state(Wt);
+    if (!pinned_state) return c->fail(MLFFT_E_NOMEM, "pinned host buffer");
+    HIPCHK(hipMemsetAsync(w.dT, 0, vb, s), "zero d");
+    HIPCHK(hipMemsetAsync(w.kcyc, 0, Wt * sizeof(int), s), "zero k");
+    for (int cyc = 0; cyc < o.max_restarts; ++cyc) {
+        const void* res = w.rT;
+        if (cyc > 0) {
+            STCHK(batch_matvec(c, segs, w.dT, w.tmpT, w.rT, -1.0, 1.0, prec));
+            if (info) info->matvecs_inner += 1;
+            res = w.tmpT;
+        }
+        HIPCHK(k_cycle_start<C>(res, w.Vb, cols, w.g, m, w.state, w.target, w.kcyc, w.est, s), "cycle start");
+        HIPCHK(hipMemcpyAsync(pinned_state, w.state, Wt * sizeof(int), hipMemcpyDeviceToHost, s), "state");
+        HIPCHK(hipStreamSynchronize(s), "cycle start");
+        int running = 0;
+        for (int i = 0; i < Wt; ++i) running += pinned_state[i] == 0;
+        if (running == 0) break;
+        for (int j = 0; j < m; ++j) {
+            void* vj = (char*)w.Vb + (size_t)j * vb;
+            void* vnext = (char*)w.Vb + (size_t)(j + 1) * vb;
+            const void* zsrc = vj;
+            if (o.precond) {
+                void* zdst = flexible ? (char*)w.Zb + (size_t)j * vb : w.tmp2T;
+                STCHK(batch_precond(c, segs, o.precond, vj, zdst, w.tmpT, prec, info ? &info->fallbacks : nullptr));
+                if (info) info->precond_applies += 1;
+                zsrc = zdst;
+            }
+            STCHK(batch_matvec(c, segs, zsrc, vnext, nullptr, 1.0, 0.0, prec));
+            if (info) info->matvecs_inner += 1;
+            HIPCHK(k_arnoldi<C>(w.Vb, j, cols, w.H, m, w.state, o.orth, s), "arnoldi");
+            HIPCHK(k_givens(w.H, w.cs, w.sn, w.g, j, m, Wt, w.state, w.target, w.kcyc, w.iters, w.est,
+                            o.record_history ? w.hist : nullptr, info ? info->history_len : 0, w.rnorm, s),
+                   "givens");
+            HIPCHK(hipMemcpyAsync(pinned_state, w.state, Wt * sizeof(int), hipMemcpyDeviceToHost, s), "state");
+            HIPCHK(hipStreamSynchronize(s), "iteration");
+            running = 0;
+            for (int i = 0; i < Wt; ++i) running += pinned_state[i] == 0;
+            if (running == 0) break;
+        }
+        HIPCHK(k_lsq(w.H, w.g, w.y, w.kcyc, m, Wt, s), "least squares");
+        if (flexible) {
+            HIPCHK(k_combine<C>(w.Zb, cols, w.y, w.kcyc, m, w.dT, 1, s), "update");
+        } else if (o.precond) {
+            HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, w.tmpT, 0, s), "update");
+            STCHK(batch_precond(c, segs, o.precond, w.tmpT, w.tmp2T, nullptr, prec, nullptr));
+            if (info) info->precond_applies += 1;
+            HIPCHK(k_add_cols<C>(w.dT, w.tmp2T, cols, s), "update");
+        } else {
+            HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, w.dT, 1, s), "update");
+        }
+    }
+    (void)hstate;
+    return MLFFT_OK;
+}
+
+mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& o, mlfft_solve_info* info) {
+    hipStream_t s = c->stream;
+    const int prec = o.inner_prec;
+    const int eb = prec_elem_bytes(prec);
+    const int m = o.restart;
+    Work w;
+    // column layout
+    std::vector<size_t> hoff;
+    std::vector<int> hN;
+    std::vector<int> seg_of;
+    size_t S = 0;
+    for (size_t i = 0; i < segs.size(); ++i) {
+        Seg& sg = segs[i];
+        sg.N = (size_t)sg.arr->Nx * sg.arr->Ny * sg.arr->b;
+        sg.off = S;
+        for (int q = 0; q < sg.W; ++q) {
+            hoff.push_back(S + (size_t)q * sg.N);
+            hN.push_back((int)sg.N);
+            seg_of.push_back((int)i);
+        }
+        S += sg.N * sg.W;
+        w.maxN = std::max(w.maxN, sg.N);
+    }
+    w.S = S;
+    w.Wt = (int)hoff.size();
+    const int Wt = w.Wt;
+    if (Wt == 0) return MLFFT_OK;
+    const bool flexible = o.precond == 3;
+    // carve the workspaces
+    const size_t v64b = align_up(S * 16), vTb = align_up(S * eb);
+    size_t big = 3 * v64b + 4 * vTb + (size_t)(m + 1) * vTb + (flexible ? (size_t)m * vTb : 0);
+    const int hist_len = (info && o.record_history) ? info->history_len : 0;
+    size_t small = align_up(Wt * sizeof(size_t)) + 5 * align_up(Wt * sizeof(int)) +
+                   6 * align_up(Wt * sizeof(double)) + align_up((size_t)Wt * (m + 1) * m * 16) +
+                   align_up((size_t)Wt * (m + 1) * 16) + 2 * align_up((size_t)Wt * m * 16) +
+                   align_up((size_t)Wt * m * 8) + align_up((size_t)std::max(hist_len, 1) * Wt * 8);
+    HIPCHK(c->solve_ws.ensure(big), "Krylov workspace");
+    HIPCHK(c->solve_ws2.ensure(small), "Krylov workspace");
+    char* p = (char*)c->solve_ws.p;
+    w.v64 = (double2*)p; p += v64b;
+    w.x64 = (double2*)p; p += v64b;
+    w.r64 = (double2*)p; p += v64b;
+    w.rT = p; p += vTb;
+    w.dT = p; p += vTb;
+    w.tmpT = p; p += vTb;
+    w.tmp2T = p; p += vTb;
+    w.Vb = p; p += (size_t)(m + 1) * vTb;
+    w.Zb = flexible ? (void*)p : nullptr;
+    char* q = (char*)c->solve_ws2.p;
+    w.coff = (size_t*)q; q += align_up(Wt * sizeof(size_t));
+    w.cN = (int*)q; q += align_up(Wt * sizeof(int));
+    w.state = (int*)q; q += align_up(Wt * sizeof(int));
+    w.kcyc = (int*)q; q += align_up(Wt * sizeof(int));
+    w.iters = (int*)q; q += align_up(Wt * sizeof(int));
+    w.mask = (int*)q; q += align_up(Wt * sizeof(int));
+    w.vnorm = (double*)q; q += align_up(Wt * sizeof(double));
+    w.rnorm = (double*)q; q += align_up(Wt * sizeof(double));
+    w.target = (double*)q; q += align_up(Wt * sizeof(double));
+    w.est = (double*)q; q += align_up(Wt * sizeof(double));
+    double* scratch_d = (double*)q; q += align_up(Wt * sizeof(double));
+    q += align_up(Wt * sizeof(double));
+    w.H = (double2*)q; q += align_up((size_t)Wt * (m + 1) * m * 16);
+    w.g = (double2*)q; q += align_up((size_t)Wt * (m + 1) * 16);
+    w.sn = (double2*)q; q += align_up((size_t)Wt * m * 16);
+    w.y = (double2*)q; q += align_up((size_t)Wt * m * 16);
+    w.cs = (double*)q; q += align_up((size_t)Wt * m * 8);
+    w.hist = (double*)q;
+    (void)scratch_d;
+    Cols cols{w.coff, w.cN, Wt, S, w.maxN};
+    HIPCHK(hipMemcpyAsync(w.coff, hoff.data(), Wt * sizeof(size_t), hipMemcpyHostToDevice, s), "columns");
+    HIPCHK(hipMemcpyAsync(w.cN, hN.data(), Wt * sizeof(int), hipMemcpyHostToDevice, s), "columns");
+    HIPCHK(hipMemsetAsync(w.iters, 0, Wt * sizeof(int), s), "iters");
+    if (hist_len) HIPCHK(hipMemsetAsync(w.hist, 0, (size_t)hist_len * Wt * 8, s), "history");
+    // gather V (and x0) into batch vectors
+    for (auto& sg : segs) {
+        HIPCHK(hipMemcpyAsync(w.v64 + sg.off, sg.V, sg.N * sg.W * 16, hipMemcpyDeviceToDevice, s), "gather V");
+        if (o.x0_given)
+            HIPCHK(hipMemcpyAsync(w.x64 + sg.off, sg.I, sg.N * sg.W * 16, hipMemcpyDeviceToDevice, s), "gather x0");
+    }
+    if (!o.x0_given) HIPCHK(hipMemsetAsync(w.x64, 0, S * 16, s), "zero x");
+    HIPCHK(k_colnorm<double2>(w.v64, cols, w.vnorm, s), "norms");
+    std::vector<double> hv(Wt), hr(Wt), ht(Wt);
+    std::vector<int> hstate(Wt), outer_used(Wt, 0);
+    HIPCHK(hipMemcpyAsync(hv.data(), w.vnorm, Wt * sizeof(double), hipMemcpyDeviceToHost, s), "norms");
+    bool r_current = false;     // r64 holds V - Z x64 for the current x64
+    for (int outer = 0; outer < o.max_outer; ++outer) {
+        if (outer == 0 && !o.x0_given) {
+            HIPCHK(hipMemcpyAsync(w.r64, w.v64, S * 16, hipMemcpyDeviceToDevice, s), "r = V");
+        } else {
+            STCHK(batch_matvec(c, segs, w.x64, w.r64, w.v64, -1.0, 1.0, P64));
+            if (info) info->matvecs64 += 1;
+        }
+        HIPCHK(k_colnorm<double2>(w.r64, cols, w.rnorm, s), "norms");
+        HIPCHK(hipMemcpyAsync(hr.data(), w.rnorm, Wt * sizeof(double), hipMemcpyDeviceToHost, s), "norms");
+        HIPCHK(hipStreamSynchronize(s), "norms");
+        int active = 0;
+        for (int i = 0; i < Wt; ++i) {
+            const bool done = !(hv[i] > 0.0) || hr[i] <= o.tol * hv[i];
+            if (!std::isfinite(hr[i])) return c->fail(MLFFT_E_ARG, "non-finite residual in column %d (check V and x0)", i);
+            hstate[i] = done ? 2 : 0;
+            active += !done;
+            // inner target, relative to the unit-norm inner right-hand side
+            const double need = done ? 1.0 : 0.9 * o.tol * hv[i] / hr[i];
+            ht[i] = prec == P64 ? need : std::max(o.inner_tol, need);
+            if (!done) outer_used[i] = outer + 1;
+        }
+        if (active == 0) { r_current = true; break; }
+        HIPCHK(hipMemcpyAsync(w.state, hstate.data(), Wt * sizeof(int), hipMemcpyHostToDevice, s), "state");
+        HIPCHK(hipMemcpyAsync(w.target, ht.data(), Wt * sizeof(double), hipMemcpyHostToDevice, s), "targets");
+        for (int i = 0; i < Wt; ++i) hstate[i] = hstate[i] == 0;
+        HIPCHK(hipMemcpyAsync(w.mask, hstate.data(), Wt * sizeof(int), hipMemcpyHostToDevice, s), "mask");
+        if (prec == P64)
+            HIPCHK((k_scale_cols<double2, double2>(w.r64, w.rT, cols, w.rnorm, 1, s)), "scale r");
+        else
+            HIPCHK((k_scale_cols<double2, float2>(w.r64, w.rT, cols, w.rnorm, 1, s)), "scale r");
+        mlfft_status st = prec == P64 ? inner_solve<double2>(c, segs, w, cols, o, prec, info, hstate)
+                                      : inner_solve<float2>(c, segs, w, cols, o, prec, info, hstate);
+        if (st < 0) return st;
+        if (prec == P64)
+            HIPCHK(k_axpy_cols<double2>(w.x64, w.dT, cols, w.rnorm, w.mask, s), "update x");
+        else
+            HIPCHK(k_axpy_cols<float2>(w.x64, w.dT, cols, w.rnorm, w.mask, s), "update x");
+    }
+    // final true FP64 residual (already at hand when the loop stopped on convergence)
+    if (!r_current) {
+        STCHK(batch_matvec(c, segs, w.x64, w.r64, w.v64, -1.0, 1.0, P64));
+        if (info) info->matvecs64 += 1;
+    }
+    HIPCHK(k_colnorm<double2>(w.r64, cols, w.rnorm, s), "norms");
+    HIPCHK(hipMemcpyAsync(hr.data(), w.rnorm, Wt * sizeof(double), hipMemcpyDeviceToHost, s), "norms");
+    std::vector<int> hit(Wt);
+    HIPCHK(hipMemcpyAsync(hit.data(), w.iters, Wt * sizeof(int), hipMemcpyDeviceToHost, s), "iters");
+    for (auto& sg : segs)
+        HIPCHK(hipMemcpyAsync(sg.I, w.x64 + sg.off, sg.N * sg.W * 16, hipMemcpyDeviceToDevice, s), "scatter x");
+    std::vector<double> hh;
+    if (hist_len) {
+        hh.resize((size_t)hist_len * Wt);
+        HIPCHK(hipMemcpyAsync(hh.data(), w.hist, hh.size() * 8, hipMemcpyDeviceToHost, s), "history");
+    }
+    HIPCHK(hipStreamSynchronize(s), "solve");
+    bool all = true;
+    for (int i = 0; i < Wt; ++i) {
+        const double rr = hv[i] > 0.0 ? hr[i] / hv[i] : 0.0;
+        const bool ok = rr <= o.tol;
+        all = all && ok;
+        if (info) {
+            if (info->relres) info->relres[i] = rr;
+            if (info->converged) info->converged[i] = ok;
+            if (info->iters) info->iters[i] = hit[i];
+            if (info->outer) info->outer[i] = outer_used[i];
+        }
+    }
+    if (info && info->history && hist_len) {
+        // history[it][w]: residual estimate relative to ||V_w||
+        for (int it = 0; it < hist_len; ++it)
+            for (int i = 0; i < Wt; ++i)
+                info->history[(size_t)it * Wt + i] = hv[i] > 0.0 ? hh[(size_t)it * Wt + i] / hv[i] : 0.0;
+    }
+    return all ? MLFFT_OK : MLFFT_NOT_CONVERGED;
+}
+
+extern "C" {
+
+mlfft_status mlfft_solve(mlfft_ctx ctx, int array_id, int W, const void* V, void* I, const mlfft_solve_opts* opts,
+                         mlfft_solve_info* info) {
+    if (!ctx) return MLFFT_E_ARG;
+    return mlfft_solve_batch(ctx, 1, &array_id, &W, &V, &I, opts, info);
+}
+
+mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids, const int* Ws,
+                               const void* const* V, void* const* I, const mlfft_solve_opts* opts,
+                               mlfft_solve_info* info) {
+    if (!ctx) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    if (n_arrays < 1 || !array_ids || !Ws || !V || !I) return c->fail(MLFFT_E_ARG, "empty or NULL batch description");
+    mlfft_solve_opts o;
+    if (opts) o = *opts; else mlfft_solve_default_opts(&o);
+    STCHK(check_opts(c, o));
+    std::vector<Seg> segs;
+    for (int i = 0; i < n_arrays; ++i) {
+        Array* a = c->find(array_ids[i]);
+        if (!a) return c->fail(MLFFT_E_STATE, "unknown array id %d", array_ids[i]);
+        for (int j = 0; j < i; ++j)
+            if (array_ids[j] == array_ids[i]) return c->fail(MLFFT_E_ARG, "array id %d appears twice", array_ids[i]);
+        if (Ws[i] < 0) return c->fail(MLFFT_E_ARG, "W must be >= 0");
+        if (Ws[i] == 0) continue;
+        if (!V[i] || !I[i]) return c->fail(MLFFT_E_ARG, "V or I is NULL for array %d", array_ids[i]);
+        segs.push_back(Seg{a, Ws[i], 0, 0, V[i], I[i]});
+    }
+    if (info) {
+        info->fallbacks = 0;
+        info->matvecs64 = 0;
+        info->matvecs_inner = 0;
+        info->precond_applies = 0;
+        info->net_applies = 0;
+        if (!info->history) info->history_len = 0;
+    }
+    HIPCHK(hipSetDevice(c->device), "set device");
+    return solve_impl(c, segs, o, info);
+}
+
+}  // extern "C"

@@ -1,0 +1,36 @@
+"""The C ABI library loads and exports every function its header declares (CPU only)."""
+import ctypes
+
+import pytest
+
+from paper_2506_20350_amd import abi
+
+
+def test_header_declares_the_core_calls():
+    names = abi.header_symbols()
+    for core in ["mlfft_create", "mlfft_set_blocks", "mlfft_matvec", "mlfft_precond_apply"]:
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = abi.lib()
+    missing = [n for n in abi.header_symbols() if not hasattr(L, n)]
+    assert not missing, f"symbols declared in include/mlfft.h but not exported: {missing}"
+
+
+def test_every_exported_call_has_a_binding_signature():
+    for n in abi.header_symbols():
+        assert n in abi._SIGNATURES, n
+
+
+def test_create_rejects_null_out_pointer_without_touching_a_gpu():
+    st = abi.lib().mlfft_create(0, None, None)
+    assert st == abi.MLFFT_E_ARG
+    assert b"NULL" in abi.lib().mlfft_last_error(None)
+
+
+def test_calls_on_null_context_are_argument_errors():
+    L = abi.lib()
+    assert L.mlfft_destroy(None) == abi.MLFFT_OK
+    assert L.mlfft_matvec(None, 0, 1, None, None, 0) == abi.MLFFT_E_ARG
+    assert L.mlfft_set_blocks(None, 0, 1, 1, 1, None, 0) == abi.MLFFT_E_ARG

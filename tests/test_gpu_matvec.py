@@ -1,0 +1,157 @@
+"""GPU parity of the MLFFT matvec and the preconditioner apply against the oracle.
+
+Bars: FP64 1e-12 relative (norm over all columns), FP32 1e-5, block product
+with bf16 inputs 2e-2 (its own bound: bf16 keeps 8 significant bits, so one
+rounding of G and of the transformed vector costs ~2^-9 relative each).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import precond as opc
+from oracle import toeplitz as tp
+from paper_2506_20350_amd import abi, synth
+from tests.gpu_util import ctx, relerr, to_dev, to_host  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 2e-2}
+DT = {"fp64": torch.complex128, "fp32": torch.complex64, "bf16": torch.complex64}
+
+# (Nx, Ny, b, W, generator): single cell, ragged W over one 64-column tile, b not a
+# multiple of 8, prime grid sizes, the largest grid, large and maximal b
+CASES = [
+    (1, 1, 3, 2, "random"),
+    (3, 2, 5, 3, "random"),
+    (4, 4, 24, 1, "green"),
+    (5, 7, 12, 70, "random"),
+    (13, 11, 17, 5, "green"),
+    (10, 10, 64, 100, "green"),
+    (32, 32, 8, 3, "random"),
+    (2, 3, 200, 2, "green"),
+    (3, 2, 256, 1, "random"),
+    (7, 1, 9, 4, "random"),
+    (1, 6, 10, 4, "random"),
+]
+
+
+def make_blocks(Nx, Ny, b, kind, seed=0):
+    if kind == "green":
+        return synth.green_blocks(Nx, Ny, b, np.pi, seed=seed)
+    return synth.random_blocks(Nx, Ny, b, seed=seed + 17)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:4])) + c[4][0])
+def test_matvec_matches_oracle(ctx, case, prec):
+    Nx, Ny, b, W, kind = case
+    blocks = make_blocks(Nx, Ny, b, kind)
+    ctx.set_blocks(1, blocks)
+    X = synth.random_vectors(Nx * Ny * b, W, seed=3)
+    ref = tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)
+    y = ctx.matvec(1, to_dev(X, DT[prec]), prec=prec)
+    err = relerr(to_host(y), ref)
+    assert err <= TOL[prec], err
+
+
+@pytest.mark.parametrize("case", [(3, 2, 5, 3, "random"), (4, 4, 24, 2, "green")], ids=str)
+def test_matvec_fp64_matches_dense(ctx, case):
+    Nx, Ny, b, W, kind = case
+    blocks = make_blocks(Nx, Ny, b, kind)
+    ctx.set_blocks(2, blocks)
+    X = synth.random_vectors(Nx * Ny * b, W, seed=5)
+    ref = tp.matvec_dense(tp.dense_Z(blocks), X)
+    y = ctx.matvec(2, to_dev(X))
+    assert relerr(to_host(y), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", [(4, 4, 24, 3), (5, 7, 12, 70), (13, 11, 17, 5), (10, 10, 64, 100), (1, 1, 4, 2),
+                                  (32, 32, 8, 2), (6, 5, 200, 2)], ids=str)
+def test_block_circulant_apply_matches_oracle(ctx, case, prec):
+    Nx, Ny, b, W = case
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=1)
+    ctx.set_blocks(3, blocks)
+    R = synth.random_vectors(Nx * Ny * b, W, seed=2)
+    ref = opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)
+    z = ctx.precond_apply(3, to_dev(R, DT[prec]), kind=1, prec=prec)
+    assert relerr(to_host(z), ref) <= TOL[prec] * 10
+    assert ctx.info(3).pc_fallbacks == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_self_block_apply_matches_oracle(ctx, prec):
+    Nx, Ny, b, W = 5, 3, 20, 7
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=4)
+    ctx.set_blocks(4, blocks)
+    R = synth.random_vectors(Nx * Ny * b, W, seed=6)
+    ref = opc.kindt_apply(blocks, R)
+    z = ctx.precond_apply(4, to_dev(R, DT[prec]), kind=2, prec=prec)
+    assert relerr(to_host(z), ref) <= TOL[prec] * 10
+
+
+def test_periodic_operator_is_inverted_exactly_by_block_circulant(ctx):
+    Nx, Ny, b, W = 6, 4, 8, 3
+    blocks = synth.periodic_blocks(Nx, Ny, b, seed=2)
+    ctx.set_blocks(5, blocks)
+    X = synth.random_vectors(Nx * Ny * b, W, seed=1)
+    y = ctx.matvec(5, to_dev(X))
+    z = ctx.precond_apply(5, y, kind=1)
+    assert relerr(to_host(z), X) <= 1e-12
+
+
+def test_matvec_is_deterministic(ctx):
+    Nx, Ny, b, W = 10, 10, 64, 100
+    ctx.set_blocks(6, synth.green_blocks(Nx, Ny, b, np.pi, seed=0))
+    x = to_dev(synth.random_vectors(Nx * Ny * b, W, seed=9), torch.complex64)
+    y1 = ctx.matvec(6, x, prec="fp32").clone()
+    y2 = ctx.matvec(6, x, prec="fp32")
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+
+
+def test_set_blocks_rejects_bad_input(ctx):
+    blocks = synth.green_blocks(3, 3, 4, np.pi, seed=0)
+    bad = blocks.copy()
+    bad[1, 2, 0, 3] = np.nan
+    with pytest.raises(abi.MlfftError) as e:
+        ctx.set_blocks(7, bad)
+    assert e.value.status == abi.MLFFT_E_ARG
+    with pytest.raises(abi.MlfftError) as e:
+        ctx.set_blocks(7, to_dev(bad))
+    assert e.value.status == abi.MLFFT_E_ARG
+    too_big = np.zeros((1, 65, 1, 1), dtype=np.complex128)
+    with pytest.raises(abi.MlfftError):
+        ctx.set_blocks(7, too_big)
+    singular = np.zeros((1, 1, 2, 2), dtype=np.complex128)
+    with pytest.raises(abi.MlfftError) as e:
+        ctx.set_blocks(7, singular)
+    assert e.value.status == abi.MLFFT_E_SINGULAR
+    with pytest.raises(abi.MlfftError) as e:
+        abi.mlfft_matvec(ctx.h, 12345, 1, 0, 0, 0)
+    assert e.value.status == abi.MLFFT_E_STATE
+
+
+def test_blocks_from_device_memory(ctx):
+    Nx, Ny, b, W = 4, 5, 6, 3
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=3)
+    ctx.set_blocks(8, to_dev(blocks))
+    X = synth.random_vectors(Nx * Ny * b, W, seed=4)
+    y = ctx.matvec(8, to_dev(X))
+    assert relerr(to_host(y), tp.matvec_fft(blocks, X)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_30x30_b120_sampled_columns(ctx, prec):
+    """30x30 array, b = 120, W = 900 in one launch; 3 sampled columns checked one by one."""
+    Nx = Ny = 30
+    b, W = 120, 900
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0)
+    ctx.set_blocks(9, blocks)
+    V = synth.port_rhs(Nx, Ny, b)
+    X = V + 0.1 * synth.random_vectors(Nx * Ny * b, W, seed=11)
+    y = to_host(ctx.matvec(9, to_dev(X, DT[prec]), prec=prec))
+    cols = [0, 451, 899]
+    ref = tp.matvec_fft(blocks, X[cols], 2 * Ny, 2 * Nx)
+    assert relerr(y[cols], ref) <= TOL[prec]
+    assert np.all(np.isfinite(y))

@@ -1,0 +1,161 @@
+"""GPU solves (GMRES with FP64 refinement) against the oracle's direct solutions.
+
+Bars: the final solution matches the LU solution (or, where a dense Z does not
+fit, the oracle's FP64 GMRES solution at 1e-12) to 1e-6 relative after
+refinement; parity runs refine to a tighter residual than the metric's 1e-6 so
+that the error bound ||e|| <= cond(Z) ||r|| leaves room (cond ~ 1.3-1.7 for the
+Green's-function generator).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct, krylov, precond
+from oracle import toeplitz as tp
+from paper_2506_20350_amd import abi, synth
+from tests.gpu_util import ctx, relerr, to_dev, to_host  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def test_c1_plain_fp64_gmres_matches_lu_and_oracle_iterations(ctx):
+    """4x4 array, b = 24, kd = pi, centre port, GMRES(30), no preconditioner, tol 1e-8."""
+    Nx = Ny = 4
+    b = 24
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0)
+    V = synth.port_rhs(Nx, Ny, b, cols=[synth.centre_element(Nx, Ny)])
+    ctx.set_blocks(10, blocks)
+    I, info = ctx.solve(10, to_dev(V), tol=1e-8, inner_prec="fp64", precond=0, history_len=40)
+    assert info["status"] == abi.MLFFT_OK and info["converged"].all()
+    Z = tp.dense_Z(blocks)
+    ref = direct.lu_solve(Z, V)
+    assert relerr(to_host(I), ref) <= 1e-7
+    assert info["relres"][0] <= 1e-8
+    mv = lambda X: tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)
+    ores = krylov.gmres_columns(mv, V, None, tol=1e-8 * 0.9)[0]
+    assert info["iters"][0] == ores.iters
+    h = info["history"][:info["iters"][0], 0]
+    np.testing.assert_allclose(h, ores.history, rtol=1e-6)
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("pc", [0, 1, 2])
+def test_small_array_all_ports_match_lu(ctx, inner, pc):
+    Nx, Ny, b = 5, 7, 12
+    blocks = synth.green_blocks(Nx, Ny, b, 2 * np.pi / 3, seed=1)
+    V = synth.port_rhs(Nx, Ny, b)
+    ctx.set_blocks(11, blocks)
+    I, info = ctx.solve(11, to_dev(V), tol=1e-10, inner_prec=inner, precond=pc)
+    assert info["status"] == abi.MLFFT_OK, info
+    ref = direct.lu_solve(tp.dense_Z(blocks), V)
+    assert relerr(to_host(I), ref) <= 1e-8
+    assert np.all(info["relres"] <= 1e-10)
+    if inner != "fp64":
+        assert info["outer"].max() >= 2          # refinement actually worked
+
+
+def test_c2_fp32_refined_block_circulant_matches_lu(ctx):
+    """10x10 array, b = 64, 100 port excitations, FP32 inner + FP64 refinement to 1e-8."""
+    Nx = Ny = 10
+    b = 64
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0)
+    V = synth.port_rhs(Nx, Ny, b)
+    ctx.set_blocks(12, blocks)
+    I, info = ctx.solve(12, to_dev(V), tol=1e-8, inner_prec="fp32", precond=1)
+    assert info["status"] == abi.MLFFT_OK
+    ref = direct.lu_solve(tp.dense_Z(blocks), V)
+    assert relerr(to_host(I), ref) <= 1e-6
+    assert np.all(info["relres"] <= 1e-8)
+
+
+def test_batch_of_uneven_arrays_matches_per_array_lu(ctx):
+    shapes = [(4, 6, 24, 0.6 * np.pi), (7, 3, 16, np.pi), (5, 5, 40, 0.8 * np.pi)]
+    ids, Vs, refs = [], [], []
+    for i, (Nx, Ny, b, kd) in enumerate(shapes):
+        blocks = synth.green_blocks(Nx, Ny, b, kd, seed=1000 + i)
+        ctx.set_blocks(20 + i, blocks)
+        V = synth.port_rhs(Nx, Ny, b)
+        ids.append(20 + i)
+        Vs.append(to_dev(V))
+        refs.append(direct.lu_solve(tp.dense_Z(blocks), V))
+    Is, info = ctx.solve_batch(ids, Vs, tol=1e-10, inner_prec="fp32", precond=1)
+    assert info["status"] == abi.MLFFT_OK
+    for I, ref in zip(Is, refs):
+        assert relerr(to_host(I), ref) <= 1e-8
+    assert info["relres"].shape[0] == sum(v.shape[0] for v in Vs)
+
+
+def test_initial_guess_and_zero_columns(ctx):
+    Nx, Ny, b = 4, 4, 8
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=3)
+    ctx.set_blocks(13, blocks)
+    V = synth.port_rhs(Nx, Ny, b, cols=[0, 5, 9])
+    V[1] = 0.0                                  # an all-zero excitation
+    ref = direct.lu_solve(tp.dense_Z(blocks), V)
+    I, info = ctx.solve(13, to_dev(V), to_dev(ref), tol=1e-8, x0_given=1, inner_prec="fp64")
+    assert info["status"] == abi.MLFFT_OK and np.all(info["iters"] == 0)
+    I2, info2 = ctx.solve(13, to_dev(V), tol=1e-10, inner_prec="fp32")
+    out = to_host(I2)
+    assert np.all(out[1] == 0) and info2["iters"][1] == 0
+    assert relerr(out, ref) <= 1e-8
+
+
+def test_periodic_operator_converges_in_one_iteration(ctx):
+    Nx, Ny, b = 6, 4, 8
+    blocks = synth.periodic_blocks(Nx, Ny, b, seed=5)
+    ctx.set_blocks(14, blocks)
+    V = synth.random_vectors(Nx * Ny * b, 4, seed=2)
+    I, info = ctx.solve(14, to_dev(V), tol=1e-10, inner_prec="fp64", precond=1)
+    assert info["status"] == abi.MLFFT_OK
+    assert np.all(info["iters"] == 1)
+    assert relerr(to_host(I), direct.lu_solve(tp.dense_Z(blocks), V)) <= 1e-10
+
+
+def test_limits_report_not_converged(ctx):
+    Nx, Ny, b = 5, 5, 16
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0, alpha=0.3)
+    ctx.set_blocks(15, blocks)
+    V = synth.port_rhs(Nx, Ny, b, cols=[0, 12])
+    I, info = ctx.solve(15, to_dev(V), tol=1e-12, inner_prec="fp64", precond=0, restart=2, max_restarts=1,
+                        max_outer=1)
+    assert info["status"] == abi.MLFFT_NOT_CONVERGED
+    assert np.all(info["relres"] > 1e-12) and np.all(np.isfinite(info["relres"]))
+    assert not info["converged"].any()
+
+
+def test_solve_rejects_bad_arguments(ctx):
+    Nx, Ny, b = 3, 3, 4
+    ctx.set_blocks(16, synth.green_blocks(Nx, Ny, b, np.pi, seed=0))
+    V = to_dev(synth.port_rhs(Nx, Ny, b))
+    with pytest.raises(abi.MlfftError) as e:
+        ctx.solve(16, V, restart=40)
+    assert e.value.status == abi.MLFFT_E_ARG
+    with pytest.raises(abi.MlfftError) as e:
+        ctx.solve(16, V, precond=3)
+    assert e.value.status in (abi.MLFFT_E_STATE, abi.MLFFT_E_ARG)
+    bad = V.clone()
+    bad[0, 0] = float("nan")
+    with pytest.raises(abi.MlfftError) as e:
+        ctx.solve(16, bad)
+    assert e.value.status == abi.MLFFT_E_ARG
+
+
+@pytest.mark.parametrize("kd", [2 * np.pi / 3, np.pi])
+def test_full_size_30x30_b120_sampled_columns(ctx, kd):
+    """30x30 array, b = 120, all 900 ports in one solve (FP32 inner, FP64 refinement);
+    three columns checked against the oracle's FP64 GMRES solution at 1e-12."""
+    Nx = Ny = 30
+    b = 120
+    blocks = synth.green_blocks(Nx, Ny, b, kd, seed=0)
+    ctx.set_blocks(17, blocks)
+    V = synth.port_rhs(Nx, Ny, b)
+    I, info = ctx.solve(17, to_dev(V), tol=1e-8, inner_prec="fp32", precond=1)
+    assert info["status"] == abi.MLFFT_OK
+    assert np.all(info["relres"] <= 1e-8)
+    out = to_host(I)
+    cols = [0, 465, 899]
+    mv = lambda X: tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)
+    Sinv = precond.strang_inverse_spectrum(blocks)
+    pc = lambda X: precond.strang_apply(Sinv, X)
+    ref = np.array([r.x for r in krylov.gmres_columns(mv, V[cols], pc, tol=1e-12)])
+    assert relerr(out[cols], ref) <= 1e-6
