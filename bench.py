@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MLFFT-accelerated GMRES solve on one MI355X.
+
+A step is one full solve of all element-port excitations of one synthetic
+array (every column driven to a true FP64 relative residual <= tol): the
+batched MLFFT products, preconditioner applies, Krylov steps and FP64
+refinement all run inside the timed region; the block spectra and the
+preconditioner are built before it (setup, reported separately).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c5]
+                    [--form fp32|bf16|fp64|learned] [--no-cpu-baseline]
+
+Prints one JSON line (see the keys below).  Only one GPU is used: --gpus N
+with N > 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks (dense): HBM3E 8 TB/s; MFMA FP64 78.6, FP32 157.3, BF16 2500 TFLOP/s
+PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0}
+
+WORKLOADS = {
+    # 30x30 array, b = 120, all 900 ports, kd = pi (one of the two frequencies of the paper-scale case)
+    "c3": dict(Nx=30, Ny=30, b=120, kd=math.pi, seed=0),
+    # 30x30 array, b = 200 (dense element), all 900 ports, kd = pi
+    "c5": dict(Nx=30, Ny=30, b=200, kd=math.pi, seed=0),
+}
+
+FORMS = {
+    "fp32": dict(inner_prec="fp32", precond=1, label="FP32 inner GMRES(30) + FP64 refinement, block-circulant preconditioner"),
+    "bf16": dict(inner_prec="bf16", precond=1, label="FP32 inner GMRES(30) with bf16-input block product + FP64 refinement, block-circulant preconditioner"),
+    "fp64": dict(inner_prec="fp64", precond=1, label="plain FP64 GMRES(30), block-circulant preconditioner"),
+    "learned": dict(inner_prec="fp32", precond=3, label="FP32 inner flexible GMRES(30) with learned correction + FP64 refinement"),
+}
+
+DTYPE = {"fp32": "f32+f64", "bf16": "bf16xf32+f64", "fp64": "f64", "learned": "f32+bf16+f64"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_solves(ctx, aid, Vd, steps, warmup, form, tol, torch, inner_tol=None):
+    opts = dict(FORMS[form])
+    opts.pop("label")
+    if inner_tol is not None and opts["inner_prec"] != "fp64":
+        opts["inner_tol"] = inner_tol
+    I = torch.zeros_like(Vd)
+    info = None
+    for _ in range(warmup):
+        I.zero_()
+        I, info = ctx.solve(aid, Vd, I, tol=tol, **opts)
+    from paper_2506_20350_amd import abi
+    abi.mlfft_profile_enable(ctx.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(steps):
+        I, info = ctx.solve(aid, Vd, I, tol=tol, **opts)   # x0 = 0 (x0_given defaults to 0)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = abi.mlfft_profile_read(ctx.h)
+    abi.mlfft_profile_enable(ctx.h, False)
+    return I, infos, t1 - t0, stats
+
+
+def roofline_of(stats):
+    """Roofline of the kernel group with the largest total time."""
+    dom = max(stats, key=lambda s: s["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    if dom["flops"] > 0:
+        peak = PEAK_MFMA_TFLOPS[dom["prec"]]
+        ach = dom["flops"] / dom["launches"] / (avg_ms * 1e-3) / 1e12
+        # a block product is MFMA-bound when its intensity exceeds the ridge, else HBM-bound
+        intensity = dom["flops"] / dom["bytes"]
+        ridge = peak * 1e12 / (PEAK_HBM_GBS * 1e9)
+        if intensity >= ridge:
+            return dom, dict(bound="mfma", achieved=round(ach, 2), peak=peak, unit="TFLOP/s",
+                             frac=round(ach / peak, 4), traffic=None)
+    ach = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
+    return dom, dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                     frac=round(ach / PEAK_HBM_GBS, 4), traffic=None)
+
+
+def cpu_baseline(blocks, V, cfg, tol, n_cols):
+    """The oracle (FP64 MLFFT GMRES(30), Strang block-circulant preconditioner) on host cores."""
+    from oracle import krylov, precond
+    from oracle import toeplitz as tp
+    Nx, Ny = cfg["Nx"], cfg["Ny"]
+    c0 = time.perf_counter()
+    Gh = tp.spectra(blocks, 2 * Ny, 2 * Nx)
+    Sinv = precond.strang_inverse_spectrum(blocks)
+    setup = time.perf_counter() - c0
+    mv = lambda X: tp.matvec_spectral(Gh, X, Nx, Ny)
+    pc = lambda X: precond.strang_apply(Sinv, X)
+    cols = list(np.linspace(0, V.shape[0] - 1, n_cols).astype(int))
+    cpu0 = os.times()
+    t0 = time.perf_counter()
+    res = krylov.gmres_columns(mv, V[cols], pc, tol=tol)
+    wall = time.perf_counter() - t0
+    cpu1 = os.times()
+    cpu = (cpu1.user - cpu0.user) + (cpu1.system - cpu0.system)
+    solved = sum(r.converged for r in res)
+    return dict(value=round(solved / wall, 4), unit="RHS/s", cores=max(1, round(cpu / wall)),
+                kind="oracle",
+                sample=f"{n_cols} of {V.shape[0]} port columns (evenly spaced) of the same array, solved one by one "
+                       f"to the same tol; spectra + preconditioner setup {setup:.1f} s not included; "
+                       f"host logical CPUs {os.cpu_count()}"), cols, res, mv, pc
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
+    ap.add_argument("--form", choices=sorted(FORMS), default="fp32")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="residual reduction asked of each FP32 inner solve (library default if omitted)")
+    ap.add_argument("--compare", choices=sorted(FORMS) + ["none"], default="fp64",
+                    help="second form timed on the same GPU for comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cols", type=int, default=3)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy kernel (for HBM counter calibration)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this build "
+              "(the path would shard right-hand sides across GPUs, see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if a.calib_copy:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copied 1 GiB three times")
+        return
+
+    from paper_2506_20350_amd import synth
+    from paper_2506_20350_amd.api import Context
+
+    cfg = WORKLOADS[a.workload]
+    Nx, Ny, b = cfg["Nx"], cfg["Ny"], cfg["b"]
+    W = Nx * Ny
+    log(f"[bench] workload {a.workload}: {Nx}x{Ny} b={b} W={W}; generating blocks")
+    blocks = synth.green_blocks(Nx, Ny, b, cfg["kd"], seed=cfg["seed"])
+    V = synth.port_rhs(Nx, Ny, b)
+    ctx = Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.set_blocks(0, blocks)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"[bench] setup (spectra + preconditioner) {setup_s:.2f} s")
+    Vd = torch.from_numpy(V).cuda()
+    if FORMS[a.form]["precond"] == 3:
+        from paper_2506_20350_amd import learned
+        log("[bench] training the learned correction")
+        learned.prepare(ctx, cfg)
+    I, infos, dt, stats = timed_solves(ctx, 0, Vd, a.steps, a.warmup, a.form, a.tol, torch, a.inner_tol)
+    conv = [int(np.sum(inf["relres"] <= a.tol)) for inf in infos]
+    value = sum(conv) / dt
+    last = infos[-1]
+    log(f"[bench] {a.form}: {dt / a.steps * 1e3:.1f} ms/step, {value:.1f} RHS/s, "
+        f"iters mean {last['iters'].mean():.2f}, max relres {last['relres'].max():.2e}")
+    dom, roof = roofline_of(stats)
+    kernels = [dict(name=s["name"], prec=s["prec"], launches=s["launches"], avg_ms=round(s["ms"] / s["launches"], 4),
+                    total_ms=round(s["ms"], 3)) for s in sorted(stats, key=lambda s: -s["ms"])]
+    out = dict(metric="solved RHS/s @ rel-res 1e-6 (30x30 array); MLFFT matvec % HBM/MFMA peak",
+               value=round(value, 2), unit="RHS/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+               ms_per_step=round(dt / a.steps * 1e3, 3), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype=DTYPE[a.form], data="synthetic",
+               config=dict(workload=f"{Nx}x{Ny} array, b={b}, kd={cfg['kd']:.4f}, {W} port RHS, "
+                                    f"{FORMS[a.form]['label']}, tol {a.tol:g}",
+                           Nx=Nx, Ny=Ny, b=b, W=W, form=a.form, tol=a.tol),
+               roofline=roof,
+               roofline_kernel=dict(name=dom["name"], prec=dom["prec"], launches=dom["launches"],
+                                    avg_ms=round(dom["ms"] / dom["launches"], 4),
+                                    algorithmic_bytes=dom["bytes"] / dom["launches"],
+                                    algorithmic_flops=dom["flops"] / dom["launches"]),
+               kernels=kernels, setup_s=round(setup_s, 3),
+               iters_mean=float(last["iters"].mean()), outer_max=int(last["outer"].max()),
+               max_relres=float(last["relres"].max()), converged_per_step=conv)
+    if a.compare != "none" and a.compare != a.form:
+        _, cinfos, cdt, cstats = timed_solves(ctx, 0, Vd, 1, 1, a.compare, a.tol, torch)
+        cval = int(np.sum(cinfos[-1]["relres"] <= a.tol)) / cdt
+        out["compare"] = dict(form=a.compare, label=FORMS[a.compare]["label"], value=round(cval, 2), unit="RHS/s",
+                              ms_per_step=round(cdt * 1e3, 3), iters_mean=float(cinfos[-1]["iters"].mean()),
+                              speedup_of_measured_form=round(value / cval, 3))
+        log(f"[bench] compare {a.compare}: {cdt * 1e3:.1f} ms/step, {cval:.1f} RHS/s")
+    if not a.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle) on a bounded sample")
+        cb, cols, res, mv, pc = cpu_baseline(blocks, V, cfg, a.tol, a.cpu_cols)
+        out["cpu_baseline"] = cb
+        # error of the GPU solution against the oracle's FP64 solution at 1e-12 (first sampled column)
+        from oracle import krylov
+        ref = krylov.gmres_columns(mv, V[cols[:1]], pc, tol=1e-12)[0].x
+        got = I[cols[0]].cpu().numpy()
+        out["err_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        log(f"[bench] cpu baseline {cb['value']} RHS/s on {cb['cores']} cores; err vs oracle {out['err_vs_oracle']:.2e}")
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -134,8 +134,9 @@ typedef struct {
     double tol;          /* target true FP64 relative residual ||V_w - Z I_w|| / ||V_w|| per column (default 1e-6) */
     int inner_prec;      /* mlfft_prec of the inner GMRES (default MLFFT_FP32).  MLFFT_FP64 = plain FP64 GMRES:
                             the outer loop then only confirms the true residual */
-    double inner_tol;    /* residual reduction asked of each inner solve with FP32 / BF16 inner precision
-                            (default 1e-4); ignored for MLFFT_FP64 */
+    double inner_tol;    /* floor of the residual reduction asked of each FP32 / BF16 inner solve; every inner
+                            solve aims at max(inner_tol, 0.9 * tol * ||V_w|| / ||r_w||).  0 (default) = automatic:
+                            3e-7 for MLFFT_FP32, 1e-2 for MLFFT_FP32_BF16GEMM; ignored for MLFFT_FP64 */
     int max_outer;       /* FP64 refinement steps (default 10) */
     int precond;         /* 0 none, 1 block circulant (default), 2 self block (Kindt), 3 learned correction of the
                             block-circulant output (flexible GMRES; needs a network, see mlfft_net_create) */
@@ -182,6 +183,27 @@ mlfft_status mlfft_solve(mlfft_ctx ctx, int array_id, int W, const void* V, void
 mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids, const int* W,
                                const void* const* V, void* const* I,
                                const mlfft_solve_opts* opts, mlfft_solve_info* info);
+
+/* ------------------------------------------------------------------ profiling */
+
+typedef struct {
+    char name[32];       /* kernel group: mlfft_fwd_fft, block_gemm, mlfft_inv_fft, precond_fwd_fft, precond_gemm,
+                            precond_inv_fft, arnoldi, net_forward, net_backward */
+    int prec;            /* mlfft_prec of the launches */
+    long launches;
+    double ms;           /* summed launch durations (HIP events on the context's stream) */
+    double bytes;        /* summed algorithmic bytes (minimum HBM traffic of the operation) */
+    double flops;        /* summed algorithmic flops (block products: 8 b^2 W per frequency) */
+} mlfft_kernel_stat;
+
+/* Enable (1) or disable (0) per-launch timing of the hot kernels; either call
+ * discards earlier records.  Enabling adds two event records per launch. */
+mlfft_status mlfft_profile_enable(mlfft_ctx ctx, int enable);
+
+/* Aggregate the records since the last mlfft_profile_enable() per (group, prec).
+ * Writes at most max_out entries to out and the number of groups to *n_out.
+ * Blocking (synchronises the stream). */
+mlfft_status mlfft_profile_read(mlfft_ctx ctx, mlfft_kernel_stat* out, int max_out, int* n_out);
 
 #ifdef __cplusplus
 }

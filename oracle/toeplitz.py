@@ -162,6 +162,22 @@ def spectra(blocks: np.ndarray, Py: int, Px: int) -> np.ndarray:
     return np.fft.fft2(block_grid(blocks, Py, Px), axes=(0, 1))
 
 
+def matvec_spectral(Gh: np.ndarray, X: np.ndarray, Nx: int, Ny: int) -> np.ndarray:
+    """Z_A X from precomputed block spectra Gh (Py, Px, b, b) of eq. multL.
+
+    Zero-pad every column to the Py x Px grid (eq. xc2), 2-D DFT over the grid
+    axes, one b x b product per frequency, inverse DFT, keep Ny x Nx cells.
+    """
+    Py, Px, b, _ = Gh.shape
+    W = X.shape[0]
+    u = np.zeros((W, Py, Px, b), dtype=np.result_type(Gh, X))
+    u[:, :Ny, :Nx, :] = X.reshape(W, Ny, Nx, b)
+    uh = np.fft.fft2(u, axes=(1, 2))
+    vh = np.einsum('yxmn,wyxn->wyxm', Gh, uh)
+    v = np.fft.ifft2(vh, axes=(1, 2))
+    return v[:, :Ny, :Nx, :].reshape(W, -1)
+
+
 def matvec_fft(blocks: np.ndarray, X: np.ndarray, Py: int | None = None,
                Px: int | None = None) -> np.ndarray:
     """Z_A X via the blockwise 2-level FFT (eq. multL, L = 2).
@@ -175,14 +191,7 @@ def matvec_fft(blocks: np.ndarray, X: np.ndarray, Py: int | None = None,
     Nx, Ny, b = shape_of(blocks)
     Py = 2 * Ny - 1 if Py is None else Py
     Px = 2 * Nx - 1 if Px is None else Px
-    W = X.shape[0]
-    Gh = spectra(blocks, Py, Px)
-    u = np.zeros((W, Py, Px, b), dtype=np.result_type(blocks, X))
-    u[:, :Ny, :Nx, :] = X.reshape(W, Ny, Nx, b)
-    uh = np.fft.fft2(u, axes=(1, 2))
-    vh = np.einsum('yxmn,wyxn->wyxm', Gh, uh)
-    v = np.fft.ifft2(vh, axes=(1, 2))
-    return v[:, :Ny, :Nx, :].reshape(W, -1)
+    return matvec_spectral(spectra(blocks, Py, Px), X, Nx, Ny)
 
 
 # ----------------------------------------------- blockwise multilevel DFTs

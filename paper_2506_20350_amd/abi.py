@@ -185,3 +185,24 @@ def mlfft_solve_batch(ctx, array_ids, Ws, V_ptrs, I_ptrs, opts: SolveOpts, info:
     ip = (ctypes.c_void_p * n)(*I_ptrs)
     return check(ctx, lib().mlfft_solve_batch(ctx, n, ids, ws, vp, ip, ctypes.byref(opts),
                                               ctypes.byref(info) if info is not None else None))
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("prec", ctypes.c_int), ("launches", ctypes.c_long),
+                ("ms", ctypes.c_double), ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
+_SIGNATURES["mlfft_profile_enable"] = (_ST, [_P, _I])
+_SIGNATURES["mlfft_profile_read"] = (_ST, [_P, ctypes.POINTER(KernelStat), _I, ctypes.POINTER(_I)])
+
+
+def mlfft_profile_enable(ctx, enable: bool):
+    return check(ctx, lib().mlfft_profile_enable(ctx, int(enable)))
+
+
+def mlfft_profile_read(ctx) -> list:
+    buf = (KernelStat * 32)()
+    n = ctypes.c_int(0)
+    check(ctx, lib().mlfft_profile_read(ctx, buf, 32, ctypes.byref(n)))
+    return [dict(name=buf[i].name.decode(), prec=buf[i].prec, launches=buf[i].launches, ms=buf[i].ms,
+                 bytes=buf[i].bytes, flops=buf[i].flops) for i in range(min(n.value, 32))]

@@ -77,7 +77,7 @@ template<> struct MfmaReal<double> {
     }
 };
 
-template<typename T, int BP, int NT>
+template<typename T, int BP, int NT, int TAG>
 __global__ void __launch_bounds__(512) bgemm_real_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
     typedef MfmaReal<T> M;
     typedef typename M::c_t C;
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(512) bgemm_real_kernel(GemmTask t0, const Gemm
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) { return f32_to_bf16_bits(f); }
 
-template<int BP, int NT>
+template<int BP, int NT, int TAG>
 __global__ void __launch_bounds__(512) bgemm_bf16_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
     extern __shared__ unsigned char smem_raw[];
     unsigned short* xs = reinterpret_cast<unsigned short*>(smem_raw);
@@ -284,33 +284,33 @@ void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int* grid, int* bp_m
 }
 
 template<typename T, int BP, int NT>
-static hipError_t launch_real_nt(const GemmTask* th, const GemmTask* td, int ntasks, int grid, int waves,
+static hipError_t launch_real_nt(const GemmTask* th, const GemmTask* td, int ntasks, int grid, int waves, int tag,
                                  hipStream_t s) {
     const size_t lds = (size_t)NT * (2 * BP + 2) * sizeof(T);
-    (void)hipFuncSetAttribute((const void*)bgemm_real_kernel<T, BP, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    hipLaunchKernelGGL((bgemm_real_kernel<T, BP, NT>), dim3(grid), dim3(64 * waves), lds, s, th[0],
-                       ntasks > 1 ? td : nullptr, ntasks > 1 ? ntasks : 0);
+    auto k = tag ? bgemm_real_kernel<T, BP, NT, 1> : bgemm_real_kernel<T, BP, NT, 0>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, s, th[0], ntasks > 1 ? td : nullptr,
+                       ntasks > 1 ? ntasks : 0);
     return hipGetLastError();
 }
 
 // 64-column tiles when they fit the 160 KB of LDS, 32-column tiles otherwise (FP64, b > 160)
 template<typename T, int BP>
-static hipError_t launch_real(const GemmTask* th, const GemmTask* td, int ntasks, int grid, int waves,
+static hipError_t launch_real(const GemmTask* th, const GemmTask* td, int ntasks, int grid, int waves, int tag,
                               hipStream_t s) {
     if ((size_t)kNT * (2 * BP + 2) * sizeof(T) <= 160 * 1024)
-        return launch_real_nt<T, BP, kNT>(th, td, ntasks, grid, waves, s);
-    return launch_real_nt<T, BP, kNT / 2>(th, td, ntasks, grid, waves, s);
+        return launch_real_nt<T, BP, kNT>(th, td, ntasks, grid, waves, tag, s);
+    return launch_real_nt<T, BP, kNT / 2>(th, td, ntasks, grid, waves, tag, s);
 }
 
 template<int BP>
-static hipError_t launch_b16(const GemmTask* th, const GemmTask* td, int ntasks, int grid, int waves,
+static hipError_t launch_b16(const GemmTask* th, const GemmTask* td, int ntasks, int grid, int waves, int tag,
                              hipStream_t s) {
     const size_t lds = (size_t)kNT * (2 * BP + 8) * sizeof(unsigned short);
-    (void)hipFuncSetAttribute((const void*)bgemm_bf16_kernel<BP, kNT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-    hipLaunchKernelGGL((bgemm_bf16_kernel<BP, kNT>), dim3(grid), dim3(64 * waves), lds, s, th[0],
-                       ntasks > 1 ? td : nullptr, ntasks > 1 ? ntasks : 0);
+    auto k = tag ? bgemm_bf16_kernel<BP, kNT, 1> : bgemm_bf16_kernel<BP, kNT, 0>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, s, th[0], ntasks > 1 ? td : nullptr,
+                       ntasks > 1 ? ntasks : 0);
     return hipGetLastError();
 }
 
@@ -320,7 +320,7 @@ static hipError_t launch_b16(const GemmTask* th, const GemmTask* td, int ntasks,
 #define MLFFT_BP16(X) X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128) X(144) X(160) X(176) X(192) \
     X(208) X(224) X(240) X(256)
 
-hipError_t launch_bgemm(int prec, const GemmTask* th, const GemmTask* td, int ntasks, hipStream_t s) {
+hipError_t launch_bgemm(int prec, const GemmTask* th, const GemmTask* td, int ntasks, int tag, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
     int grid = 0, bpm = 0, wmax = 1;
     for (int i = 0; i < ntasks; ++i) {
@@ -334,21 +334,21 @@ hipError_t launch_bgemm(int prec, const GemmTask* th, const GemmTask* td, int nt
     if (grid == 0) return hipSuccess;
     if (prec == P64) {
         switch (bpm) {
-#define C64(B) case B: return launch_real<double, B>(th, td, ntasks, grid, wmax, s);
+#define C64(B) case B: return launch_real<double, B>(th, td, ntasks, grid, wmax, tag, s);
             MLFFT_BP8(C64)
 #undef C64
             default: return hipErrorInvalidValue;
         }
     } else if (prec == P32) {
         switch (bpm) {
-#define C32(B) case B: return launch_real<float, B>(th, td, ntasks, grid, wmax, s);
+#define C32(B) case B: return launch_real<float, B>(th, td, ntasks, grid, wmax, tag, s);
             MLFFT_BP8(C32)
 #undef C32
             default: return hipErrorInvalidValue;
         }
     } else {
         switch (bpm) {
-#define C16(B) case B: return launch_b16<B>(th, td, ntasks, grid, wmax, s);
+#define C16(B) case B: return launch_b16<B>(th, td, ntasks, grid, wmax, tag, s);
             MLFFT_BP16(C16)
 #undef C16
             default: return hipErrorInvalidValue;

@@ -20,19 +20,45 @@
 #include "internal.h"
 #include "fft_codelets.h"
 
+#include <algorithm>
+
 namespace mlfft {
 
-#define MLFFT_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) \
-    X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) \
-    X(29) X(30) X(31) X(32)
+// Transform lengths are grouped in classes, one kernel instantiation per class,
+// so that the register allocation of a kernel is set by the largest codelet of
+// its own class only: class 0 = 1..16, class 1 = the composite lengths 17..32,
+// class 2 = the primes 17..31 (direct DFTs with the most live values).
+#define MLFFT_CASES0(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#define MLFFT_CASES1(X) X(18) X(20) X(21) X(22) X(24) X(25) X(26) X(27) X(28) X(30) X(32)
+#define MLFFT_CASES2(X) X(17) X(19) X(23) X(29) X(31)
 
-template<template<typename, int> class F, typename C, typename... A>
+__host__ __device__ constexpr int len_class(int n) {
+    return n <= 16 ? 0 : (n == 17 || n == 19 || n == 23 || n == 29 || n == 31) ? 2 : 1;
+}
+
+template<template<typename, int> class F, typename C, int CLS, typename... A>
 __device__ __forceinline__ void dispatch_n(int n, A... a) {
     switch (n) {
 #define MLFFT_CASE(N) case N: F<C, N>::run(a...); break;
-        MLFFT_CASES(MLFFT_CASE)
+        MLFFT_CASES0(MLFFT_CASE)
 #undef MLFFT_CASE
         default: break;
+    }
+    if (CLS >= 1) {
+        switch (n) {
+#define MLFFT_CASE(N) case N: F<C, N>::run(a...); break;
+            MLFFT_CASES1(MLFFT_CASE)
+#undef MLFFT_CASE
+            default: break;
+        }
+    }
+    if (CLS >= 2) {
+        switch (n) {
+#define MLFFT_CASE(N) case N: F<C, N>::run(a...); break;
+            MLFFT_CASES2(MLFFT_CASE)
+#undef MLFFT_CASE
+            default: break;
+        }
     }
 }
 
@@ -108,11 +134,12 @@ struct FwdX {
     }
 };
 
-template<typename C>
+template<typename C, int CLS, int PAD>
 __global__ void __launch_bounds__(512) fft_fwd_kernel(FftTask t0, const FftTask* tasks, int ntasks) {
     extern __shared__ unsigned char smem_raw[];
     C* tile = reinterpret_cast<C*>(smem_raw);
-    const FftTask tl = ntasks > 0 ? *find_task(tasks, ntasks) : t0;
+    FftTask tl = ntasks > 0 ? *find_task(tasks, ntasks) : t0;
+    tl.pad = PAD;
     const FftTask* t = &tl;
     const int local = blockIdx.x - t->block_begin;
     Work wk;
@@ -120,15 +147,17 @@ __global__ void __launch_bounds__(512) fft_fwd_kernel(FftTask t0, const FftTask*
     const int mc = local - wk.w * t->nmc;
     wk.m0 = mc * t->cm;
     wk.mlen = min(t->cm, t->b - wk.m0);
-    dispatch_n<FwdY, C>(t->Ny, tl, wk, tile);
+    dispatch_n<FwdY, C, CLS>(t->Ny, tl, wk, tile);
     __syncthreads();
-    dispatch_n<FwdX, C>(t->Nx, tl, wk, (const C*)tile);
+    dispatch_n<FwdX, C, CLS>(t->Nx, tl, wk, (const C*)tile);
 }
 
 // ---------------------------------------------------------------- inverse
 
 template<typename C, int NX>
 struct InvX {
+    // The even-kx half is written to the LDS tile and the odd half added to it,
+    // so only one length-NX vector is live in registers.
     static __device__ __forceinline__ void run(const FftTask& tt, Work wk, C* tile) {
         const FftTask* t = &tt;
         const int cm = t->cm, b = t->b, W = t->W;
@@ -140,7 +169,7 @@ struct InvX {
         if (mi >= wk.mlen) return;
         const C* __restrict__ src = static_cast<const C*>(t->in) + (size_t)wk.w * b + wk.m0 + mi;
         const size_t ks = (size_t)W * b;
-        C acc[NX];
+        C* row = tile + ky * NX * cm + mi;
         for (int g = 0; g < H; ++g) {
             C v[NX];
 #pragma unroll
@@ -152,20 +181,20 @@ struct InvX {
             if (g) {
                 Fft<C, NX, 1>::tw2(v);
 #pragma unroll
-                for (int ix = 0; ix < NX; ++ix) acc[ix] = cadd(acc[ix], v[ix]);
+                for (int ix = 0; ix < NX; ++ix) row[ix * cm] = cadd(row[ix * cm], v[ix]);
             } else {
 #pragma unroll
-                for (int ix = 0; ix < NX; ++ix) acc[ix] = v[ix];
+                for (int ix = 0; ix < NX; ++ix) row[ix * cm] = v[ix];
             }
         }
-#pragma unroll
-        for (int ix = 0; ix < NX; ++ix) tile[(ky * NX + ix) * cm + mi] = acc[ix];
     }
 };
 
 template<typename C, int NY>
 struct InvY {
-    static __device__ __forceinline__ void run(const FftTask& tt, Work wk, const C* tile) {
+    // Each thread owns the tile column (ix, mi): the even-ky half's transform is
+    // parked in the even rows of that column while the odd half is transformed.
+    static __device__ __forceinline__ void run(const FftTask& tt, Work wk, C* tile) {
         const FftTask* t = &tt;
         typedef typename CTraits<C>::real R;
         const int Nx = t->Nx, cm = t->cm, b = t->b;
@@ -174,23 +203,21 @@ struct InvY {
         if (tid >= Nx * cm) return;
         const int ix = tid / cm, mi = tid - ix * cm;
         if (mi >= wk.mlen) return;
-        C acc[NY];
-        for (int h = 0; h < H; ++h) {
-            C v[NY];
+        C* col = tile + ix * cm + mi;
+        const int rs = Nx * cm;
+        C v[NY];
 #pragma unroll
-            for (int j = 0; j < NY; ++j) {
-                const int ky = t->pad ? 2 * j + h : j;
-                v[j] = tile[(ky * Nx + ix) * cm + mi];
-            }
+        for (int j = 0; j < NY; ++j) v[j] = col[(t->pad ? 2 * j : j) * rs];
+        Fft<C, NY, 1>::run(v);
+        if (H == 2) {
+#pragma unroll
+            for (int j = 0; j < NY; ++j) col[2 * j * rs] = v[j];
+#pragma unroll
+            for (int j = 0; j < NY; ++j) v[j] = col[(2 * j + 1) * rs];
             Fft<C, NY, 1>::run(v);
-            if (h) {
-                Fft<C, NY, 1>::tw2(v);
+            Fft<C, NY, 1>::tw2(v);
 #pragma unroll
-                for (int iy = 0; iy < NY; ++iy) acc[iy] = cadd(acc[iy], v[iy]);
-            } else {
-#pragma unroll
-                for (int iy = 0; iy < NY; ++iy) acc[iy] = v[iy];
-            }
+            for (int iy = 0; iy < NY; ++iy) v[iy] = cadd(v[iy], col[2 * iy * rs]);
         }
         const size_t off = ((size_t)wk.w * NY * Nx + ix) * b + wk.m0 + mi;
         const size_t ys = (size_t)Nx * b;
@@ -202,20 +229,21 @@ struct InvY {
 #pragma unroll
             for (int iy = 0; iy < NY; ++iy) {
                 const C a = add[iy * ys];
-                dst[iy * ys] = cmake<C>(acc[iy].x * alpha + a.x * beta, acc[iy].y * alpha + a.y * beta);
+                dst[iy * ys] = cmake<C>(v[iy].x * alpha + a.x * beta, v[iy].y * alpha + a.y * beta);
             }
         } else {
 #pragma unroll
-            for (int iy = 0; iy < NY; ++iy) dst[iy * ys] = cscale(acc[iy], alpha);
+            for (int iy = 0; iy < NY; ++iy) dst[iy * ys] = cscale(v[iy], alpha);
         }
     }
 };
 
-template<typename C>
+template<typename C, int CLS, int PAD>
 __global__ void __launch_bounds__(512) fft_inv_kernel(FftTask t0, const FftTask* tasks, int ntasks) {
     extern __shared__ unsigned char smem_raw[];
     C* tile = reinterpret_cast<C*>(smem_raw);
-    const FftTask tl = ntasks > 0 ? *find_task(tasks, ntasks) : t0;
+    FftTask tl = ntasks > 0 ? *find_task(tasks, ntasks) : t0;
+    tl.pad = PAD;
     const FftTask* t = &tl;
     const int local = blockIdx.x - t->block_begin;
     Work wk;
@@ -223,9 +251,9 @@ __global__ void __launch_bounds__(512) fft_inv_kernel(FftTask t0, const FftTask*
     const int mc = local - wk.w * t->nmc;
     wk.m0 = mc * t->cm;
     wk.mlen = min(t->cm, t->b - wk.m0);
-    dispatch_n<InvX, C>(t->Nx, tl, wk, tile);
+    dispatch_n<InvX, C, CLS>(t->Nx, tl, wk, tile);
     __syncthreads();
-    dispatch_n<InvY, C>(t->Ny, tl, wk, (const C*)tile);
+    dispatch_n<InvY, C, CLS>(t->Ny, tl, wk, tile);
 }
 
 // ---------------------------------------------------------------- host side
@@ -262,68 +290,51 @@ void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block,
     *lds = l;
 }
 
-template<typename C>
-static hipError_t launch_fwd_t(const FftTask* th, const FftTask* td, int ntasks, hipStream_t s) {
+typedef void (*FftKernel)(FftTask, const FftTask*, int);
+
+template<typename C, int INV>
+static FftKernel pick_kernel(int cls, int pad) {
+#define PICK(CL, PD) if (cls == CL && pad == PD) { \
+        FftKernel k = INV ? (FftKernel)fft_inv_kernel<C, CL, PD> : (FftKernel)fft_fwd_kernel<C, CL, PD>; \
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget); \
+        return k; }
+    PICK(0, 0) PICK(0, 1) PICK(1, 0) PICK(1, 1) PICK(2, 0) PICK(2, 1)
+#undef PICK
+    return nullptr;
+}
+
+template<typename C, int INV>
+static hipError_t launch_t(const FftTask* th, const FftTask* td, int ntasks, hipStream_t s) {
     // the host copy is already planned (cm, nmc, block_begin filled)
-    int grid = 0, block = 64;
+    int grid = 0, block = 64, cls = 0;
     size_t lds = 0;
     const int eb = sizeof(C);
     for (int i = 0; i < ntasks; ++i) {
         const FftTask& t = th[i];
+        if (t.pad != th[0].pad) return hipErrorInvalidValue;
         const int H = t.pad ? 2 : 1, Py = H * t.Ny;
         grid = t.block_begin + t.nmc * t.W > grid ? t.block_begin + t.nmc * t.W : grid;
         int thr = ((Py > t.Nx ? Py : t.Nx) * t.cm + 63) / 64 * 64;
         if (thr > block) block = thr;
         size_t ll = (size_t)Py * t.Nx * t.cm * eb;
         if (ll > lds) lds = ll;
+        cls = std::max(cls, std::max(len_class(t.Nx), len_class(t.Ny)));
     }
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(fft_fwd_kernel<C>, dim3(grid), dim3(block), lds, s, th[0],
-                       ntasks > 1 ? td : nullptr, ntasks > 1 ? ntasks : 0);
+    FftKernel k = pick_kernel<C, INV>(cls, th[0].pad);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, s, th[0], ntasks > 1 ? td : nullptr, ntasks > 1 ? ntasks : 0);
     return hipGetLastError();
-}
-
-template<typename C>
-static hipError_t launch_inv_t(const FftTask* th, const FftTask* td, int ntasks, hipStream_t s) {
-    int grid = 0, block = 64;
-    size_t lds = 0;
-    const int eb = sizeof(C);
-    for (int i = 0; i < ntasks; ++i) {
-        const FftTask& t = th[i];
-        const int H = t.pad ? 2 : 1, Py = H * t.Ny;
-        grid = t.block_begin + t.nmc * t.W > grid ? t.block_begin + t.nmc * t.W : grid;
-        int thr = ((Py > t.Nx ? Py : t.Nx) * t.cm + 63) / 64 * 64;
-        if (thr > block) block = thr;
-        size_t ll = (size_t)Py * t.Nx * t.cm * eb;
-        if (ll > lds) lds = ll;
-    }
-    if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(fft_inv_kernel<C>, dim3(grid), dim3(block), lds, s, th[0],
-                       ntasks > 1 ? td : nullptr, ntasks > 1 ? ntasks : 0);
-    return hipGetLastError();
-}
-
-static bool lds_attr_done[2] = {false, false};
-
-static void set_lds_attr() {
-    if (lds_attr_done[0]) return;
-    (void)hipFuncSetAttribute((const void*)fft_fwd_kernel<float2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
-    (void)hipFuncSetAttribute((const void*)fft_fwd_kernel<double2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
-    (void)hipFuncSetAttribute((const void*)fft_inv_kernel<float2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
-    (void)hipFuncSetAttribute((const void*)fft_inv_kernel<double2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
-    lds_attr_done[0] = true;
 }
 
 hipError_t launch_fft_fwd(int prec, const FftTask* th, const FftTask* td, int ntasks, hipStream_t s) {
-    set_lds_attr();
-    if (prec == P64) return launch_fwd_t<double2>(th, td, ntasks, s);
-    return launch_fwd_t<float2>(th, td, ntasks, s);
+    if (prec == P64) return launch_t<double2, 0>(th, td, ntasks, s);
+    return launch_t<float2, 0>(th, td, ntasks, s);
 }
 
 hipError_t launch_fft_inv(int prec, const FftTask* th, const FftTask* td, int ntasks, hipStream_t s) {
-    set_lds_attr();
-    if (prec == P64) return launch_inv_t<double2>(th, td, ntasks, s);
-    return launch_inv_t<float2>(th, td, ntasks, s);
+    if (prec == P64) return launch_t<double2, 1>(th, td, ntasks, s);
+    return launch_t<float2, 1>(th, td, ntasks, s);
 }
 
 }  // namespace mlfft

@@ -51,7 +51,8 @@ hipError_t launch_fft_inv(int prec, const FftTask* tasks_host, const FftTask* ta
 // block size / dynamic LDS bytes the grouped launch needs
 void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block, size_t* lds);
 
-hipError_t launch_bgemm(int prec, const GemmTask* tasks_host, const GemmTask* tasks_dev, int ntasks,
+// tag 0: MLFFT spectra, 1: preconditioner (separate kernel symbols for profilers)
+hipError_t launch_bgemm(int prec, const GemmTask* tasks_host, const GemmTask* tasks_dev, int ntasks, int tag,
                         hipStream_t s);
 void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int* grid, int* bp_max);
 int gemm_bp(int prec, int b);

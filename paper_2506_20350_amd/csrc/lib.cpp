@@ -45,6 +45,32 @@ void Buf::release() {
     n = 0;
 }
 
+int Ctx::prof_begin(int kind, int prec, double bytes, double flops) {
+    if (!prof) return -1;
+    while (prof_pool.size() < prof_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        prof_pool.push_back(e);
+    }
+    ProfRec r{kind, prec, prof_pool[prof_used], prof_pool[prof_used + 1], bytes, flops};
+    prof_used += 2;
+    (void)hipEventRecord(r.a, stream);
+    prof_recs.push_back(r);
+    return (int)prof_recs.size() - 1;
+}
+
+void Ctx::prof_end(int rec) {
+    if (rec < 0) return;
+    (void)hipEventRecord(prof_recs[rec].b, stream);
+}
+
+void Ctx::prof_release() {
+    for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
+    prof_pool.clear();
+    prof_recs.clear();
+    prof_used = 0;
+}
+
 int* Ctx::pinned_state(int n) {
     if (n > pinned_n) {
         if (pinned) (void)hipHostFree(pinned);
@@ -157,9 +183,26 @@ mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec) {
         if (st != MLFFT_OK) return st;
         dfw = d; div = (char*)d + sf; dgm = (char*)d + 2 * sf;
     }
+    // algorithmic bytes / flops of the three launches (s: bytes per complex of the data, sg: of the spectra)
+    double bf = 0, bg = 0, bi = 0, fl = 0;
+    const double s = eb, sg = prec == P64 ? 16 : prec == P32 ? 8 : 4;
+    for (int i = 0; i < nt; ++i) {
+        const Array* a = items[i].arr;
+        const double N = (double)a->Nx * a->Ny * a->b * items[i].W, KB = (double)a->K * a->b * items[i].W;
+        bf += s * (N + KB);
+        bg += s * 2 * KB + sg * (double)a->K * a->b * a->b;
+        bi += s * (KB + N + (items[i].addend ? N : 0));
+        fl += 8.0 * a->K * (double)a->b * a->b * items[i].W;
+    }
+    int pr = prof_begin(PK_FFT_FWD, prec, bf, 0);
     HIPCHK(launch_fft_fwd(prec, fw.data(), (const FftTask*)dfw, nt, stream), "forward MLFFT launch");
-    HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, stream), "block product launch");
+    prof_end(pr);
+    pr = prof_begin(PK_GEMM, prec, bg, fl);
+    HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, 0, stream), "block product launch");
+    prof_end(pr);
+    pr = prof_begin(PK_FFT_INV, prec, bi, 0);
     HIPCHK(launch_fft_inv(prec, iv.data(), (const FftTask*)div, nt, stream), "inverse MLFFT launch");
+    prof_end(pr);
     return MLFFT_OK;
 }
 
@@ -188,7 +231,7 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
             mlfft_status st = upload_tasks(gm.data(), sizeof(GemmTask) * nt, &dgm);
             if (st != MLFFT_OK) return st;
         }
-        HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, stream), "self-block apply launch");
+        HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, 1, stream), "self-block apply launch");
         return MLFFT_OK;
     }
     size_t need = 0;
@@ -240,9 +283,24 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
         if (st != MLFFT_OK) return st;
         dfw = d; div = (char*)d + sf; dgm = (char*)d + 2 * sf;
     }
+    double bf = 0, bg = 0, fl = 0;
+    const double s = eb, sg = prec == P64 ? 16 : prec == P32 ? 8 : 4;
+    for (int i = 0; i < nt; ++i) {
+        const Array* a = items[i].arr;
+        const double N = (double)a->Nx * a->Ny * a->b * items[i].W;
+        bf += s * 2 * N;
+        bg += s * 2 * N + sg * (double)a->Nx * a->Ny * a->b * a->b;
+        fl += 8.0 * a->Nx * a->Ny * (double)a->b * a->b * items[i].W;
+    }
+    int pr = prof_begin(PK_PC_FFT_FWD, prec, bf, 0);
     HIPCHK(launch_fft_fwd(prec, fw.data(), (const FftTask*)dfw, nt, stream), "preconditioner FFT launch");
-    HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, stream), "preconditioner product launch");
+    prof_end(pr);
+    pr = prof_begin(PK_PC_GEMM, prec, bg, fl);
+    HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, 1, stream), "preconditioner product launch");
+    prof_end(pr);
+    pr = prof_begin(PK_PC_FFT_INV, prec, bf, 0);
     HIPCHK(launch_fft_inv(prec, iv.data(), (const FftTask*)div, nt, stream), "preconditioner IFFT launch");
+    prof_end(pr);
     return MLFFT_OK;
 }
 
@@ -442,6 +500,48 @@ mlfft_status mlfft_array_info(mlfft_ctx ctx, int array_id, mlfft_array_info_t* o
     out->pc_fallbacks = a->pc_fallbacks;
     out->pc_min_rcond = a->pc_min_rcond;
     out->device_bytes = a->bytes();
+    return MLFFT_OK;
+}
+
+static const char* kProfNames[PK_COUNT] = {"mlfft_fwd_fft", "block_gemm", "mlfft_inv_fft", "precond_fwd_fft",
+                                           "precond_gemm", "precond_inv_fft", "arnoldi", "net_forward",
+                                           "net_backward"};
+
+mlfft_status mlfft_profile_enable(mlfft_ctx ctx, int enable) {
+    if (!ctx) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    HIPCHK(hipStreamSynchronize(c->stream), "profile");
+    c->prof_recs.clear();
+    c->prof_used = 0;
+    c->prof = enable != 0;
+    return MLFFT_OK;
+}
+
+mlfft_status mlfft_profile_read(mlfft_ctx ctx, mlfft_kernel_stat* out, int max_out, int* n_out) {
+    if (!ctx || !n_out || (max_out > 0 && !out)) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    HIPCHK(hipStreamSynchronize(c->stream), "profile");
+    std::vector<mlfft_kernel_stat> agg;
+    for (const ProfRec& r : c->prof_recs) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b), "profile event");
+        mlfft_kernel_stat* hit = nullptr;
+        for (auto& s : agg)
+            if (strcmp(s.name, kProfNames[r.kind]) == 0 && s.prec == r.prec) hit = &s;
+        if (!hit) {
+            mlfft_kernel_stat s{};
+            snprintf(s.name, sizeof s.name, "%s", kProfNames[r.kind]);
+            s.prec = r.prec;
+            agg.push_back(s);
+            hit = &agg.back();
+        }
+        hit->launches += 1;
+        hit->ms += ms;
+        hit->bytes += r.bytes;
+        hit->flops += r.flops;
+    }
+    *n_out = (int)agg.size();
+    for (int i = 0; i < (int)agg.size() && i < max_out; ++i) out[i] = agg[i];
     return MLFFT_OK;
 }
 

@@ -49,6 +49,19 @@ struct MatvecItem {
 
 }  // namespace mlfft
 
+namespace mlfft {
+// One profiled launch: HIP events recorded on the context's stream around it,
+// with the algorithmic bytes and flops of that launch.
+struct ProfRec {
+    int kind;
+    int prec;
+    hipEvent_t a, b;
+    double bytes, flops;
+};
+enum ProfKind { PK_FFT_FWD = 0, PK_GEMM, PK_FFT_INV, PK_PC_FFT_FWD, PK_PC_GEMM, PK_PC_FFT_INV, PK_ARNOLDI,
+                PK_NET_FWD, PK_NET_BWD, PK_COUNT };
+}  // namespace mlfft
+
 struct mlfft_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -61,6 +74,15 @@ struct mlfft_ctx_s {
     int* pinned = nullptr;         // pinned host buffer for per-column state read-back
     int pinned_n = 0;
     struct Net* net = nullptr;     // learned preconditioner (netapi.cpp)
+
+    bool prof = false;
+    std::vector<mlfft::ProfRec> prof_recs;
+    std::vector<hipEvent_t> prof_pool;
+    size_t prof_used = 0;
+    // start / stop a profiled launch (no-ops unless profiling is enabled)
+    int prof_begin(int kind, int prec, double bytes, double flops);
+    void prof_end(int rec);
+    void prof_release();
 
     int* pinned_state(int n);
     bool net_ready() const;
@@ -80,6 +102,7 @@ struct mlfft_ctx_s {
         pinned = nullptr;
         pinned_n = 0;
         net_release();
+        prof_release();
     }
 };
 

@@ -73,7 +73,7 @@ extern "C" mlfft_status mlfft_solve_default_opts(mlfft_solve_opts* o) {
     o->max_restarts = 100;
     o->tol = 1e-6;
     o->inner_prec = MLFFT_FP32;
-    o->inner_tol = 1e-4;
+    o->inner_tol = 0.0;     // automatic: the accuracy floor of the inner precision
     o->max_outer = 10;
     o->precond = 1;
     o->orth = 2;
@@ -89,8 +89,8 @@ static mlfft_status check_opts(Ctx* c, const mlfft_solve_opts& o) {
     if (!(o.tol > 0.0) || !(o.tol < 1.0)) return c->fail(MLFFT_E_ARG, "tol must be in (0, 1)");
     if (o.inner_prec < MLFFT_FP64 || o.inner_prec > MLFFT_FP32_BF16GEMM)
         return c->fail(MLFFT_E_ARG, "invalid inner precision");
-    if (o.inner_prec != MLFFT_FP64 && (!(o.inner_tol > 0.0) || !(o.inner_tol < 1.0)))
-        return c->fail(MLFFT_E_ARG, "inner_tol must be in (0, 1)");
+    if (o.inner_prec != MLFFT_FP64 && (!(o.inner_tol >= 0.0) || !(o.inner_tol < 1.0)))
+        return c->fail(MLFFT_E_ARG, "inner_tol must be in [0, 1)");
     if (o.max_outer < 1) return c->fail(MLFFT_E_ARG, "max_outer must be >= 1");
     if (o.precond < 0 || o.precond > 3) return c->fail(MLFFT_E_ARG, "precond must be 0, 1, 2 or 3");
     if (o.orth != 1 && o.orth != 2) return c->fail(MLFFT_E_ARG, "orth must be 1 or 2");
@@ -167,7 +167,10 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
             }
             STCHK(batch_matvec(c, segs, zsrc, vnext, nullptr, 1.0, 0.0, prec));
             if (info) info->matvecs_inner += 1;
+            // algorithmic traffic of one step: (orth + 1) passes over the j+2 vectors, one write
+            const int pr = c->prof_begin(PK_ARNOLDI, prec, (double)eb * w.S * ((o.orth + 1) * (j + 2) + 1), 0);
             HIPCHK(k_arnoldi<C>(w.Vb, j, cols, w.H, m, w.state, o.orth, s), "arnoldi");
+            c->prof_end(pr);
             HIPCHK(k_givens(w.H, w.cs, w.sn, w.g, j, m, Wt, w.state, w.target, w.kcyc, w.iters, w.est,
                             o.record_history ? w.hist : nullptr, info ? info->history_len : 0, w.rnorm, s),
                    "givens");
@@ -277,6 +280,12 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     std::vector<double> hv(Wt), hr(Wt), ht(Wt);
     std::vector<int> hstate(Wt), outer_used(Wt, 0);
     HIPCHK(hipMemcpyAsync(hv.data(), w.vnorm, Wt * sizeof(double), hipMemcpyDeviceToHost, s), "norms");
+    // Accuracy floor of an inner solve.  An FP32 solve can drive the residual
+    // estimate to a few 1e-7 of its right-hand side before FP32 rounding of the
+    // basis and of the product dominates; the bf16-input block product rounds
+    // every transformed vector to 8 significant bits, which makes the inner
+    // operator inexact at the 1e-3 level, so its solve is stopped at 1e-2.
+    const double inner_floor = o.inner_tol > 0.0 ? o.inner_tol : (prec == PBF16 ? 1e-2 : 3e-7);
     bool r_current = false;     // r64 holds V - Z x64 for the current x64
     for (int outer = 0; outer < o.max_outer; ++outer) {
         if (outer == 0 && !o.x0_given) {
@@ -296,7 +305,7 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
             active += !done;
             // inner target, relative to the unit-norm inner right-hand side
             const double need = done ? 1.0 : 0.9 * o.tol * hv[i] / hr[i];
-            ht[i] = prec == P64 ? need : std::max(o.inner_tol, need);
+            ht[i] = prec == P64 ? need : std::max(inner_floor, need);
             if (!done) outer_used[i] = outer + 1;
         }
         if (active == 0) { r_current = true; break; }
