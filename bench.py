@@ -132,8 +132,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="residual reduction asked of each FP32 inner solve (library default if omitted)")
-    ap.add_argument("--compare", choices=sorted(FORMS) + ["none"], default="fp64",
-                    help="second form timed on the same GPU for comparison")
+    ap.add_argument("--compare", default="fp64",
+                    help="comma-separated forms timed on the same GPU for comparison (or 'none')")
+    ap.add_argument("--train-steps", type=int, default=400, help="Adam steps of the learned correction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true",
@@ -171,10 +172,11 @@ def main():
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup (spectra + preconditioner) {setup_s:.2f} s")
     Vd = torch.from_numpy(V).cuda()
+    train_info = None
     if FORMS[a.form]["precond"] == 3:
         from paper_2506_20350_amd import learned
         log("[bench] training the learned correction")
-        learned.prepare(ctx, cfg)
+        train_info = learned.prepare(ctx, cfg, steps=a.train_steps, log=log)
     I, infos, dt, stats = timed_solves(ctx, 0, Vd, a.steps, a.warmup, a.form, a.tol, torch, a.inner_tol)
     conv = [int(np.sum(inf["relres"] <= a.tol)) for inf in infos]
     value = sum(conv) / dt
@@ -199,13 +201,19 @@ def main():
                kernels=kernels, setup_s=round(setup_s, 3),
                iters_mean=float(last["iters"].mean()), outer_max=int(last["outer"].max()),
                max_relres=float(last["relres"].max()), converged_per_step=conv)
-    if a.compare != "none" and a.compare != a.form:
-        _, cinfos, cdt, cstats = timed_solves(ctx, 0, Vd, 1, 1, a.compare, a.tol, torch)
+    if train_info is not None:
+        out["learned"] = train_info
+        out["fallbacks"] = int(last["fallbacks"])
+    comps = [] if a.compare == "none" else [f for f in a.compare.split(",") if f and f != a.form]
+    if comps:
+        out["compare"] = []
+    for cf in comps:
+        _, cinfos, cdt, cstats = timed_solves(ctx, 0, Vd, 1, 1, cf, a.tol, torch)
         cval = int(np.sum(cinfos[-1]["relres"] <= a.tol)) / cdt
-        out["compare"] = dict(form=a.compare, label=FORMS[a.compare]["label"], value=round(cval, 2), unit="RHS/s",
-                              ms_per_step=round(cdt * 1e3, 3), iters_mean=float(cinfos[-1]["iters"].mean()),
-                              speedup_of_measured_form=round(value / cval, 3))
-        log(f"[bench] compare {a.compare}: {cdt * 1e3:.1f} ms/step, {cval:.1f} RHS/s")
+        out["compare"].append(dict(form=cf, label=FORMS[cf]["label"], value=round(cval, 2), unit="RHS/s",
+                                   ms_per_step=round(cdt * 1e3, 3), iters_mean=float(cinfos[-1]["iters"].mean()),
+                                   speedup_of_measured_form=round(value / cval, 3)))
+        log(f"[bench] compare {cf}: {cdt * 1e3:.1f} ms/step, {cval:.1f} RHS/s, iters mean {cinfos[-1]['iters'].mean():.2f}")
     if not a.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) on a bounded sample")
         cb, cols, res, mv, pc = cpu_baseline(blocks, V, cfg, a.tol, a.cpu_cols)

@@ -184,6 +184,56 @@ mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids
                                const void* const* V, void* const* I,
                                const mlfft_solve_opts* opts, mlfft_solve_info* info);
 
+/* ------------------------------------------------------------------ learned correction */
+/*
+ * A small convolutional network on the array grid corrects the output of the
+ * block-circulant preconditioner (the paper asks for a preconditioner that
+ * covers all neighbouring elements, Sec. V; the network is this library's
+ * choice).  A column y (complex64, vector layout) is seen as an NHWC image of
+ * Ny x Nx pixels with 2b real channels (channel 2m + part).  Normalisation:
+ * s = ||y||, phi = arg of the entry of largest modulus, y_hat = y e^{-i phi}/s.
+ * Network: four 3x3 convolutions, zero "same" padding, no bias,
+ * 2b -> hidden -> hidden -> hidden -> 2b, ReLU after the first three; bf16
+ * inputs and weights, FP32 accumulation.  Output z = s e^{i phi}(y_hat + Net(y_hat)).
+ * Weights (FP32 master copy) are one flat array, layer by layer, each layer
+ * [c_out][c_in][3][3] row-major.  One network per context.
+ */
+
+/* Create (or replace) the context's network for b basis functions per cell;
+ * all weights start at zero (the correction is then the identity). */
+mlfft_status mlfft_net_create(mlfft_ctx ctx, int b, int hidden);
+
+/* Number of FP32 weights of the network (0 without a network). */
+size_t mlfft_net_num_weights(mlfft_ctx ctx);
+
+/* Copy n = mlfft_net_num_weights() FP32 weights from / to host memory.
+ * Setting weights resets the Adam state.  Non-finite weights: MLFFT_E_ARG. */
+mlfft_status mlfft_net_set_weights(mlfft_ctx ctx, const float* host, size_t n);
+mlfft_status mlfft_net_get_weights(mlfft_ctx ctx, float* host, size_t n);
+
+/* Raw network on W images: x, out device FP32 NHWC [W][H][Wd][2b] (x is rounded
+ * to bf16 before the first convolution).  Asynchronous. */
+mlfft_status mlfft_net_forward(mlfft_ctx ctx, int W, int H, int Wd, const void* x, void* out);
+
+/* z = s e^{i phi}(y_hat + Net(y_hat)) for W columns of array array_id (whose b must
+ * match the network); y, z device complex64 in the vector layout.  A column whose
+ * result is not finite is replaced by y.  Asynchronous. */
+mlfft_status mlfft_net_apply(mlfft_ctx ctx, int array_id, int W, const void* y, void* z);
+
+/* Loss and weight gradients for W training pairs on an H x Wd grid:
+ * y = block-circulant output P^{-1} r, e = the error it should become (device,
+ * complex64, vector layout).  Loss = mean over pairs of
+ * ||y_hat + Net(y_hat) - e_hat||^2 / ||e_hat||^2 with e_hat = e e^{-i phi}/s.
+ * host_grads (may be NULL): mlfft_net_num_weights() floats, layout of the weights.
+ * Blocking. */
+mlfft_status mlfft_net_grads(mlfft_ctx ctx, int W, int H, int Wd, const void* y, const void* e,
+                             float* host_grads, float* loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias corrected) on the loss
+ * above with learning rate lr; *loss receives the loss before the step.  Blocking. */
+mlfft_status mlfft_net_train_step(mlfft_ctx ctx, int W, int H, int Wd, const void* y, const void* e,
+                                  float lr, float* loss);
+
 /* ------------------------------------------------------------------ profiling */
 
 typedef struct {

@@ -77,8 +77,6 @@ _SIGNATURES = {
     "mlfft_solve": (_ST, [_P, _I, _I, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
     "mlfft_solve_batch": (_ST, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_P),
                                 ctypes.POINTER(_P), ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
-    "mlfft_matvec_batch": (_ST, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_P),
-                                 ctypes.POINTER(_P), _I]),
     "mlfft_net_create": (_ST, [_P, _I, _I]),
     "mlfft_net_set_weights": (_ST, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
     "mlfft_net_get_weights": (_ST, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
@@ -87,7 +85,6 @@ _SIGNATURES = {
     "mlfft_net_train_step": (_ST, [_P, _I, _I, _I, _P, _P, ctypes.c_float, ctypes.POINTER(ctypes.c_float)]),
     "mlfft_net_grads": (_ST, [_P, _I, _I, _I, _P, _P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "mlfft_net_apply": (_ST, [_P, _I, _I, _P, _P]),
-    "mlfft_conv3x3": (_ST, [_P, _I, _I, _I, _I, _I, _P, _P, _P, _I]),
 }
 
 _lib = None
@@ -206,3 +203,48 @@ def mlfft_profile_read(ctx) -> list:
     check(ctx, lib().mlfft_profile_read(ctx, buf, 32, ctypes.byref(n)))
     return [dict(name=buf[i].name.decode(), prec=buf[i].prec, launches=buf[i].launches, ms=buf[i].ms,
                  bytes=buf[i].bytes, flops=buf[i].flops) for i in range(min(n.value, 32))]
+
+
+def mlfft_net_create(ctx, b: int, hidden: int):
+    return check(ctx, lib().mlfft_net_create(ctx, b, hidden))
+
+
+def mlfft_net_num_weights(ctx) -> int:
+    return int(lib().mlfft_net_num_weights(ctx))
+
+
+def mlfft_net_set_weights(ctx, w):
+    import numpy as np
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    return check(ctx, lib().mlfft_net_set_weights(ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size))
+
+
+def mlfft_net_get_weights(ctx):
+    import numpy as np
+    n = mlfft_net_num_weights(ctx)
+    w = np.zeros(n, dtype=np.float32)
+    check(ctx, lib().mlfft_net_get_weights(ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n))
+    return w
+
+
+def mlfft_net_forward(ctx, W: int, H: int, Wd: int, x_ptr: int, out_ptr: int):
+    return check(ctx, lib().mlfft_net_forward(ctx, W, H, Wd, x_ptr, out_ptr))
+
+
+def mlfft_net_apply(ctx, array_id: int, W: int, y_ptr: int, z_ptr: int):
+    return check(ctx, lib().mlfft_net_apply(ctx, array_id, W, y_ptr, z_ptr))
+
+
+def mlfft_net_grads(ctx, W: int, H: int, Wd: int, y_ptr: int, e_ptr: int, want_grads: bool = True):
+    import numpy as np
+    g = np.zeros(mlfft_net_num_weights(ctx), dtype=np.float32) if want_grads else None
+    loss = ctypes.c_float(0.0)
+    gp = g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if want_grads else None
+    check(ctx, lib().mlfft_net_grads(ctx, W, H, Wd, y_ptr, e_ptr, gp, ctypes.byref(loss)))
+    return g, float(loss.value)
+
+
+def mlfft_net_train_step(ctx, W: int, H: int, Wd: int, y_ptr: int, e_ptr: int, lr: float) -> float:
+    loss = ctypes.c_float(0.0)
+    check(ctx, lib().mlfft_net_train_step(ctx, W, H, Wd, y_ptr, e_ptr, lr, ctypes.byref(loss)))
+    return float(loss.value)

@@ -89,6 +89,7 @@ struct mlfft_ctx_s {
     // z = learned correction of the block-circulant output y (W columns of array a)
     mlfft_status net_correct(const mlfft::Array* a, int W, const void* y, void* z, int prec, int* fallbacks);
     void net_release();
+    int net_fallbacks_take();      // columns whose learned output was replaced since the last call
 
     mlfft_status fail(mlfft_status st, const char* fmt, ...);
     mlfft_status hip_fail(hipError_t e, const char* what);

@@ -112,7 +112,7 @@ static mlfft_status batch_matvec(Ctx* c, std::vector<Seg>& segs, const void* x, 
 
 // z = P^{-1} r (kind 1 / 2), or the learned correction of the block-circulant output (kind 3)
 static mlfft_status batch_precond(Ctx* c, std::vector<Seg>& segs, int kind, const void* r, void* z, void* scratch,
-                                  int prec, int* fallbacks) {
+                                  int prec, int* fallbacks, int* net_applies = nullptr) {
     const int eb = prec_elem_bytes(prec);
     std::vector<MatvecItem> items;
     void* dst = kind == 3 ? scratch : z;
@@ -124,6 +124,7 @@ static mlfft_status batch_precond(Ctx* c, std::vector<Seg>& segs, int kind, cons
             mlfft_status st = c->net_correct(s.arr, s.W, (const char*)scratch + s.off * eb, (char*)z + s.off * eb, prec,
                                              fallbacks);
             if (st < 0) return st;
+            if (net_applies) *net_applies += 1;
         }
     }
     return MLFFT_OK;
@@ -161,7 +162,8 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
             const void* zsrc = vj;
             if (o.precond) {
                 void* zdst = flexible ? (char*)w.Zb + (size_t)j * vb : w.tmp2T;
-                STCHK(batch_precond(c, segs, o.precond, vj, zdst, w.tmpT, prec, info ? &info->fallbacks : nullptr));
+                STCHK(batch_precond(c, segs, o.precond, vj, zdst, w.tmpT, prec, nullptr,
+                                    info ? &info->net_applies : nullptr));
                 if (info) info->precond_applies += 1;
                 zsrc = zdst;
             }
@@ -342,6 +344,7 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
         HIPCHK(hipMemcpyAsync(hh.data(), w.hist, hh.size() * 8, hipMemcpyDeviceToHost, s), "history");
     }
     HIPCHK(hipStreamSynchronize(s), "solve");
+    if (o.precond == 3 && info) info->fallbacks = c->net_fallbacks_take();
     bool all = true;
     for (int i = 0; i < Wt; ++i) {
         const double rr = hv[i] > 0.0 ? hr[i] / hv[i] : 0.0;
@@ -391,6 +394,7 @@ mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids
         if (!V[i] || !I[i]) return c->fail(MLFFT_E_ARG, "V or I is NULL for array %d", array_ids[i]);
         segs.push_back(Seg{a, Ws[i], 0, 0, V[i], I[i]});
     }
+    if (o.precond == 3) (void)c->net_fallbacks_take();
     if (info) {
         info->fallbacks = 0;
         info->matvecs64 = 0;

@@ -1,0 +1,109 @@
+"""Training of the learned correction of the block-circulant preconditioner.
+
+The training pairs come from the plain solver itself (block-circulant GMRES in
+FP64 on a smaller array of the same element): for the k-th GMRES iterate x_k
+of a right-hand side v, the residual is r_k = v - Z x_k and the error is
+e_k = x* - x_k, where x* is the same system solved to 1e-12.  The exact
+preconditioner would map r_k to e_k (Z e_k = r_k), so the network learns to
+turn the block-circulant output y_k = P^{-1} r_k into e_k.  Every product,
+preconditioner apply, solve, forward, backward and Adam step runs in
+libmlfft.so; this module only sequences the calls and holds the pairs in
+device tensors.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import abi, synth
+from .api import Context
+
+
+def he_init(b: int, hidden: int, seed: int) -> np.ndarray:
+    """He-normal FP32 weights for the first three layers, zeros for the last one (flat layout of the ABI)."""
+    rng = np.random.default_rng(seed)
+    ch = [2 * b, hidden, hidden, hidden, 2 * b]
+    parts = []
+    for l in range(4):
+        n = ch[l + 1] * ch[l] * 9
+        if l == 3:
+            parts.append(np.zeros(n, np.float32))
+        else:
+            parts.append((rng.standard_normal(n) * math.sqrt(2.0 / (9 * ch[l]))).astype(np.float32))
+    return np.concatenate(parts)
+
+
+def make_pairs(ctx: Context, array_id: int, Nx: int, Ny: int, b: int, iters: int = 4, n_random: int = 64,
+               seed: int = 0, log=None):
+    """Pairs (y_k, e_k) as complex64 device tensors of shape (P, Nx*Ny*b) from GMRES iterates 0..iters-1."""
+    N = Nx * Ny * b
+    V = synth.port_rhs(Nx, Ny, b)
+    if n_random:
+        V = np.concatenate([V, synth.random_vectors(N, n_random, seed=seed + 7)])
+    Vd = torch.from_numpy(V).cuda()
+    xs, info = ctx.solve(array_id, Vd, tol=1e-12, inner_prec="fp64", precond=1, max_outer=4)
+    ys, es = [], []
+    for k in range(iters):
+        if k == 0:
+            xk = torch.zeros_like(Vd)
+        else:
+            xk, _ = ctx.solve(array_id, Vd, tol=1e-14, inner_prec="fp64", precond=1, restart=k, max_restarts=1,
+                              max_outer=1)
+        rk = torch.empty_like(Vd)
+        ctx.matvec(array_id, xk, rk)
+        rk = Vd - rk
+        yk = ctx.precond_apply(array_id, rk, kind=1)
+        ys.append(yk.to(torch.complex64))
+        es.append((xs - xk).to(torch.complex64))
+        if log:
+            log(f"[learned] pairs from iterate {k}: |r|/|v| median "
+                f"{float(torch.median(torch.linalg.norm(rk, dim=1) / torch.linalg.norm(Vd, dim=1))):.2e}")
+    return torch.cat(ys), torch.cat(es), info
+
+
+def train(ctx: Context, Y: torch.Tensor, E: torch.Tensor, Nx: int, Ny: int, steps: int = 300, batch: int = 16,
+          lr: float = 1e-3, seed: int = 0, holdout: int = 32, log=None):
+    """Adam on random minibatches; returns (train loss history, validation loss before, after)."""
+    P = Y.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    perm = torch.randperm(P, generator=g)
+    val = perm[:holdout].cuda()
+    tr = perm[holdout:]
+    Yv, Ev = Y[val].contiguous(), E[val].contiguous()
+    _, v0 = abi.mlfft_net_grads(ctx.h, Yv.shape[0], Ny, Nx, Yv.data_ptr(), Ev.data_ptr(), want_grads=False)
+    hist = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        idx = tr[torch.randint(len(tr), (batch,), generator=g)].cuda()
+        yb, eb = Y[idx].contiguous(), E[idx].contiguous()
+        lr_s = lr * 0.5 * (1 + math.cos(math.pi * s / steps))        # cosine decay
+        ctx.sync_stream()
+        hist.append(abi.mlfft_net_train_step(ctx.h, batch, Ny, Nx, yb.data_ptr(), eb.data_ptr(), lr_s))
+        if log and (s % 50 == 0 or s == steps - 1):
+            log(f"[learned] step {s}: loss {hist[-1]:.4e} ({time.perf_counter() - t0:.1f} s)")
+    _, v1 = abi.mlfft_net_grads(ctx.h, Yv.shape[0], Ny, Nx, Yv.data_ptr(), Ev.data_ptr(), want_grads=False)
+    return hist, v0, v1
+
+
+def prepare(ctx: Context, cfg: dict, train_grid: int = 20, hidden: int = 64, steps: int = 300, log=None,
+            array_id: int = 100, lr: float = 2e-3):
+    """Build and train the network for the element of `cfg` (b, kd, seed) on a train_grid^2 array."""
+    b, kd, seed = cfg["b"], cfg["kd"], cfg["seed"]
+    n = train_grid
+    t0 = time.perf_counter()
+    ctx.set_blocks(array_id, synth.green_blocks(n, n, b, kd, seed=seed))
+    abi.mlfft_net_create(ctx.h, b, hidden)
+    abi.mlfft_net_set_weights(ctx.h, he_init(b, hidden, seed=seed + 11))
+    Y, E, _ = make_pairs(ctx, array_id, n, n, b, log=log)
+    hist, v0, v1 = train(ctx, Y, E, n, n, steps=steps, lr=lr, log=log)
+    abi.mlfft_drop_array(ctx.h, array_id)
+    del Y, E
+    torch.cuda.empty_cache()
+    out = dict(train_grid=n, hidden=hidden, steps=steps, val_loss_before=v0, val_loss_after=v1,
+               train_loss_last=hist[-1] if hist else None, seconds=round(time.perf_counter() - t0, 2))
+    if log:
+        log(f"[learned] validation loss {v0:.4e} -> {v1:.4e} in {out['seconds']:.1f} s")
+    return out

@@ -1,0 +1,158 @@
+"""GPU parity of the learned correction (forward, gradients, Adam, apply, FGMRES).
+
+Tolerances.  The network runs its convolutions on bf16 operands with FP32
+accumulation; the oracle rounds the same operands to bf16 and accumulates in
+FP64.  A hidden activation rounds to bf16 after an FP32 sum on the GPU and after
+an FP64 sum in the oracle, so an activation lying within ~1e-6 (relative) of a
+bf16 rounding boundary can round to neighbouring bf16 values on the two sides
+(one bf16 ulp = 2^-8 relative).  That happens for a fraction ~1e-6 / 2^-8 of
+the activations and moves the norm-wise output by far less than 1e-3, which
+is the bar used for whole-network quantities.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import net as onet
+from oracle import toeplitz as tp
+from paper_2506_20350_amd import abi, learned, synth
+from tests.gpu_util import ctx, relerr, to_dev, to_host  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def flat(ws):
+    return np.concatenate([w.astype(np.float32).reshape(-1) for w in ws])
+
+
+def unflat(v, b, H):
+    ch = [2 * b, H, H, H, 2 * b]
+    ws, o = [], 0
+    for l in range(4):
+        n = ch[l + 1] * ch[l] * 9
+        ws.append(v[o:o + n].reshape(ch[l + 1], ch[l], 3, 3).astype(np.float64))
+        o += n
+    return ws
+
+
+def rand_weights(b, H, seed, last_scale=0.2):
+    ws = onet.init_weights(b, H, seed)
+    rng = np.random.default_rng(seed + 100)
+    ws[3] = rng.standard_normal(ws[3].shape) * last_scale / np.sqrt(9 * H)
+    # round through FP32 so both sides start from identical master weights
+    return [w.astype(np.float32).astype(np.float64) for w in ws]
+
+
+@pytest.mark.parametrize("b,H,Ny,Nx,W", [(3, 8, 4, 5, 3), (12, 64, 6, 6, 2), (1, 4, 1, 1, 2), (24, 32, 9, 7, 1)])
+def test_network_forward_matches_oracle(ctx, b, H, Ny, Nx, W):
+    ws = rand_weights(b, H, seed=b + H)
+    abi.mlfft_net_create(ctx.h, b, H)
+    abi.mlfft_net_set_weights(ctx.h, flat(ws))
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((W, Ny, Nx, 2 * b)).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xd)
+    ctx.sync_stream()
+    abi.mlfft_net_forward(ctx.h, W, Ny, Nx, xd.data_ptr(), out.data_ptr())
+    ref, _ = onet.net_forward(x.astype(np.float64), ws, bf16=True)
+    assert relerr(to_host(out).real, ref) <= 1e-3
+
+
+@pytest.mark.parametrize("b,H,Nx,Ny,W", [(3, 8, 5, 4, 3), (8, 16, 6, 6, 4)])
+def test_gradients_match_oracle(ctx, b, H, Nx, Ny, W):
+    ws = rand_weights(b, H, seed=7)
+    abi.mlfft_net_create(ctx.h, b, H)
+    abi.mlfft_net_set_weights(ctx.h, flat(ws))
+    N = Nx * Ny * b
+    y = synth.random_vectors(N, W, seed=2).astype(np.complex64)
+    e = (y + 0.3 * synth.random_vectors(N, W, seed=3)).astype(np.complex64)
+    yd, ed = to_dev(y, torch.complex64), to_dev(e, torch.complex64)
+    ctx.sync_stream()
+    g, loss = abi.mlfft_net_grads(ctx.h, W, Ny, Nx, yd.data_ptr(), ed.data_ptr())
+    lref, gref = onet.loss_and_grads(y.astype(np.complex128), e.astype(np.complex128), ws, Nx, Ny, b, bf16=True)
+    assert abs(loss - lref) <= 1e-4 * abs(lref)
+    gg = unflat(g, b, H)
+    for l in range(4):
+        assert relerr(gg[l], gref[l]) <= 1e-3, l
+
+
+def test_adam_first_step_closed_form(ctx):
+    b, H, Nx, Ny, W = 3, 8, 4, 4, 2
+    ws = rand_weights(b, H, seed=9)
+    abi.mlfft_net_create(ctx.h, b, H)
+    abi.mlfft_net_set_weights(ctx.h, flat(ws))
+    N = Nx * Ny * b
+    y = to_dev(synth.random_vectors(N, W, seed=4), torch.complex64)
+    e = to_dev(synth.random_vectors(N, W, seed=5), torch.complex64)
+    ctx.sync_stream()
+    g, _ = abi.mlfft_net_grads(ctx.h, W, Ny, Nx, y.data_ptr(), e.data_ptr())
+    w0 = abi.mlfft_net_get_weights(ctx.h)
+    lr = 1e-3
+    abi.mlfft_net_train_step(ctx.h, W, Ny, Nx, y.data_ptr(), e.data_ptr(), lr)
+    w1 = abi.mlfft_net_get_weights(ctx.h)
+    expect = w0 - lr * g / (np.abs(g) + 1e-8)
+    assert np.max(np.abs(w1 - expect)) <= 1e-6
+
+
+def test_zero_last_layer_apply_is_identity_and_apply_matches_oracle(ctx):
+    Nx, Ny, b, W, H = 5, 4, 6, 3, 16
+    ctx.set_blocks(30, synth.green_blocks(Nx, Ny, b, np.pi, seed=0))
+    abi.mlfft_net_create(ctx.h, b, H)
+    abi.mlfft_net_set_weights(ctx.h, learned.he_init(b, H, seed=1))
+    y = synth.random_vectors(Nx * Ny * b, W, seed=6).astype(np.complex64)
+    yd = to_dev(y, torch.complex64)
+    z = torch.empty_like(yd)
+    ctx.sync_stream()
+    abi.mlfft_net_apply(ctx.h, 30, W, yd.data_ptr(), z.data_ptr())
+    assert relerr(to_host(z), y) <= 1e-6
+    ws = rand_weights(b, H, seed=12, last_scale=1.0)
+    abi.mlfft_net_set_weights(ctx.h, flat(ws))
+    ctx.sync_stream()
+    abi.mlfft_net_apply(ctx.h, 30, W, yd.data_ptr(), z.data_ptr())
+    ref = onet.learned_apply(y.astype(np.complex128), ws, Nx, Ny, b, bf16=True)
+    assert relerr(to_host(z), ref) <= 1e-3
+
+
+def test_flexible_gmres_with_identity_correction_matches_plain(ctx):
+    Nx, Ny, b = 6, 5, 8
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0)
+    ctx.set_blocks(31, blocks)
+    abi.mlfft_net_create(ctx.h, b, 8)
+    abi.mlfft_net_set_weights(ctx.h, learned.he_init(b, 8, seed=2))
+    V = to_dev(synth.port_rhs(Nx, Ny, b))
+    I1, i1 = ctx.solve(31, V, tol=1e-10, inner_prec="fp32", precond=1)
+    I3, i3 = ctx.solve(31, V, tol=1e-10, inner_prec="fp32", precond=3)
+    assert i1["status"] == abi.MLFFT_OK and i3["status"] == abi.MLFFT_OK
+    # same iterates up to FP32 rounding of the normalisation: a column may cross its
+    # target one iteration earlier or later
+    assert np.max(np.abs(i1["iters"] - i3["iters"])) <= 1
+    assert abs(i1["iters"].mean() - i3["iters"].mean()) <= 0.2
+    assert i3["net_applies"] > 0 and i3["fallbacks"] == 0
+    ref = np.linalg.solve(tp.dense_Z(blocks), synth.port_rhs(Nx, Ny, b).T).T
+    assert relerr(to_host(I3), ref) <= 1e-8
+
+
+def test_training_lowers_loss_and_the_trained_correction_helps(ctx):
+    """Train on an 8x8 array of a poorly conditioned element (loading 1x instead of 10x) and
+    measure on a 12x12 array of the same element: iterations of flexible GMRES with the trained
+    correction against the plain block-circulant preconditioner (the fallback)."""
+    b, H = 16, 32
+    cfg = dict(b=b, kd=np.pi, seed=0)
+    n_tr, n_te = 8, 12
+    ctx.set_blocks(40, synth.green_blocks(n_tr, n_tr, b, np.pi, seed=0, alpha=1.0))
+    abi.mlfft_net_create(ctx.h, b, H)
+    abi.mlfft_net_set_weights(ctx.h, learned.he_init(b, H, seed=3))
+    Y, E, _ = learned.make_pairs(ctx, 40, n_tr, n_tr, b, iters=4, n_random=32)
+    hist, v0, v1 = learned.train(ctx, Y, E, n_tr, n_tr, steps=150, batch=16, lr=2e-3, holdout=16)
+    assert v1 < v0
+    blocks = synth.green_blocks(n_te, n_te, b, np.pi, seed=0, alpha=1.0)
+    ctx.set_blocks(41, blocks)
+    V = to_dev(synth.port_rhs(n_te, n_te, b))
+    _, plain = ctx.solve(41, V, tol=1e-8, inner_prec="fp32", precond=1)
+    I, lrn = ctx.solve(41, V, tol=1e-8, inner_prec="fp32", precond=3)
+    assert plain["status"] == abi.MLFFT_OK and lrn["status"] == abi.MLFFT_OK
+    gain = plain["iters"].mean() / lrn["iters"].mean()
+    print(f"\nlearned correction: val loss {v0:.3e} -> {v1:.3e}; mean iterations plain "
+          f"{plain['iters'].mean():.2f}, learned {lrn['iters'].mean():.2f} (x{gain:.2f})")
+    assert lrn["iters"].mean() <= plain["iters"].mean()
+    assert np.all(lrn["relres"] <= 1e-8)
