@@ -43,19 +43,25 @@ FORMS = {
     "fp32": dict(inner_prec="fp32", precond=1, label="FP32 inner GMRES(30) + FP64 refinement, block-circulant preconditioner"),
     "bf16": dict(inner_prec="bf16", precond=1, label="FP32 inner GMRES(30) with bf16-input block product + FP64 refinement, block-circulant preconditioner"),
     "fp64": dict(inner_prec="fp64", precond=1, label="plain FP64 GMRES(30), block-circulant preconditioner"),
-    "learned": dict(inner_prec="fp32", precond=3, label="FP32 inner flexible GMRES(30) with learned correction + FP64 refinement"),
+    "learned": dict(inner_prec="fp32", precond=3, label="FP32 inner flexible GMRES(30) with learned correction (validation-gated, block-circulant fallback) + FP64 refinement"),
+    "learned_forced": dict(inner_prec="fp32", precond=3, label="FP32 inner flexible GMRES(30) with the learned correction forced on + FP64 refinement"),
 }
 
-DTYPE = {"fp32": "f32+f64", "bf16": "bf16xf32+f64", "fp64": "f64", "learned": "f32+bf16+f64"}
+DTYPE = {"fp32": "f32+f64", "bf16": "bf16xf32+f64", "fp64": "f64", "learned": "f32+bf16+f64",
+         "learned_forced": "f32+bf16+f64"}
+GATED = {}   # form -> replacement options when the learned correction is gated off
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_solves(ctx, aid, Vd, steps, warmup, form, tol, torch, inner_tol=None):
+def timed_solves(ctx, aid, Vd, steps, warmup, form, tol, torch, inner_tol=None, orth=None):
     opts = dict(FORMS[form])
     opts.pop("label")
+    opts.update(GATED.get(form, {}))
+    if orth is not None:
+        opts["orth"] = orth
     if inner_tol is not None and opts["inner_prec"] != "fp64":
         opts["inner_tol"] = inner_tol
     I = torch.zeros_like(Vd)
@@ -135,6 +141,9 @@ def main():
     ap.add_argument("--compare", default="fp64",
                     help="comma-separated forms timed on the same GPU for comparison (or 'none')")
     ap.add_argument("--train-steps", type=int, default=400, help="Adam steps of the learned correction")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shapes)")
+    ap.add_argument("--orth", type=int, default=None, choices=[1, 2],
+                    help="Gram-Schmidt passes of the Arnoldi step (library default if omitted)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=3)
     ap.add_argument("--calib-copy", action="store_true",
@@ -172,12 +181,23 @@ def main():
     setup_s = time.perf_counter() - t0
     log(f"[bench] setup (spectra + preconditioner) {setup_s:.2f} s")
     Vd = torch.from_numpy(V).cuda()
+    tune_s = None
+    if not a.no_tune:
+        from paper_2506_20350_amd import abi as _abi
+        t0 = time.perf_counter()
+        precs = {0} | {{"fp32": 1, "bf16": 2, "fp64": 0, "learned": 1}[f] for f in [a.form] + a.compare.split(",") if f in FORMS}
+        for p in sorted(precs):
+            _abi.mlfft_autotune(ctx.h, 0, W, p, 2)
+        tune_s = time.perf_counter() - t0
+        log(f"[bench] autotune {tune_s:.1f} s:\n" + _abi.mlfft_tune_report(ctx.h, 0).split("block_gemm")[0])
     train_info = None
-    if FORMS[a.form]["precond"] == 3:
+    if FORMS[a.form]["precond"] == 3 or any(FORMS.get(f, {}).get("precond") == 3 for f in a.compare.split(",")):
         from paper_2506_20350_amd import learned
         log("[bench] training the learned correction")
         train_info = learned.prepare(ctx, cfg, steps=a.train_steps, log=log)
-    I, infos, dt, stats = timed_solves(ctx, 0, Vd, a.steps, a.warmup, a.form, a.tol, torch, a.inner_tol)
+        if not train_info["enabled"]:
+            GATED["learned"] = dict(precond=1)
+    I, infos, dt, stats = timed_solves(ctx, 0, Vd, a.steps, a.warmup, a.form, a.tol, torch, a.inner_tol, a.orth)
     conv = [int(np.sum(inf["relres"] <= a.tol)) for inf in infos]
     value = sum(conv) / dt
     last = infos[-1]
@@ -192,13 +212,13 @@ def main():
                vs_baseline=None, dtype=DTYPE[a.form], data="synthetic",
                config=dict(workload=f"{Nx}x{Ny} array, b={b}, kd={cfg['kd']:.4f}, {W} port RHS, "
                                     f"{FORMS[a.form]['label']}, tol {a.tol:g}",
-                           Nx=Nx, Ny=Ny, b=b, W=W, form=a.form, tol=a.tol),
+                           Nx=Nx, Ny=Ny, b=b, W=W, form=a.form, tol=a.tol, orth=a.orth or 2),
                roofline=roof,
                roofline_kernel=dict(name=dom["name"], prec=dom["prec"], launches=dom["launches"],
                                     avg_ms=round(dom["ms"] / dom["launches"], 4),
                                     algorithmic_bytes=dom["bytes"] / dom["launches"],
                                     algorithmic_flops=dom["flops"] / dom["launches"]),
-               kernels=kernels, setup_s=round(setup_s, 3),
+               kernels=kernels, setup_s=round(setup_s, 3), tune_s=None if tune_s is None else round(tune_s, 2),
                iters_mean=float(last["iters"].mean()), outer_max=int(last["outer"].max()),
                max_relres=float(last["relres"].max()), converged_per_step=conv)
     if train_info is not None:
@@ -208,7 +228,7 @@ def main():
     if comps:
         out["compare"] = []
     for cf in comps:
-        _, cinfos, cdt, cstats = timed_solves(ctx, 0, Vd, 1, 1, cf, a.tol, torch)
+        _, cinfos, cdt, cstats = timed_solves(ctx, 0, Vd, 1, 1, cf, a.tol, torch, None, a.orth)
         cval = int(np.sum(cinfos[-1]["relres"] <= a.tol)) / cdt
         out["compare"].append(dict(form=cf, label=FORMS[cf]["label"], value=round(cval, 2), unit="RHS/s",
                                    ms_per_step=round(cdt * 1e3, 3), iters_mean=float(cinfos[-1]["iters"].mean()),

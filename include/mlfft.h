@@ -234,6 +234,23 @@ mlfft_status mlfft_net_grads(mlfft_ctx ctx, int W, int H, int Wd, const void* y,
 mlfft_status mlfft_net_train_step(mlfft_ctx ctx, int W, int H, int Wd, const void* y, const void* e,
                                   float lr, float* loss);
 
+/* ------------------------------------------------------------------ autotuning */
+
+/* Time the candidate launch shapes of the MLFFT block product (waves per
+ * workgroup x columns per LDS tile) and of the 2-D FFTs (basis functions per
+ * workgroup, for the MLFFT grid and the preconditioner torus) on array
+ * array_id with W columns in precision prec, `reps` timed runs each, and keep
+ * the fastest for the rest of the process (all contexts).  Blocking; overwrites
+ * the context's spectral workspaces. */
+mlfft_status mlfft_autotune(mlfft_ctx ctx, int array_id, int W, int prec, int reps);
+
+/* Write the choices in force for array_id's shape, followed by the timings of
+ * the last mlfft_autotune(), as text lines into buf (n bytes, truncated). */
+mlfft_status mlfft_tune_report(mlfft_ctx ctx, int array_id, char* buf, size_t n);
+
+/* Re-apply choices from text in the format of mlfft_tune_report(). */
+mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text);
+
 /* ------------------------------------------------------------------ profiling */
 
 typedef struct {

@@ -248,3 +248,22 @@ def mlfft_net_train_step(ctx, W: int, H: int, Wd: int, y_ptr: int, e_ptr: int, l
     loss = ctypes.c_float(0.0)
     check(ctx, lib().mlfft_net_train_step(ctx, W, H, Wd, y_ptr, e_ptr, lr, ctypes.byref(loss)))
     return float(loss.value)
+
+
+_SIGNATURES["mlfft_autotune"] = (_ST, [_P, _I, _I, _I, _I])
+_SIGNATURES["mlfft_tune_report"] = (_ST, [_P, _I, ctypes.c_char_p, ctypes.c_size_t])
+_SIGNATURES["mlfft_tune_import"] = (_ST, [_P, ctypes.c_char_p])
+
+
+def mlfft_autotune(ctx, array_id: int, W: int, prec: int, reps: int = 3):
+    return check(ctx, lib().mlfft_autotune(ctx, array_id, W, prec, reps))
+
+
+def mlfft_tune_report(ctx, array_id: int) -> str:
+    buf = ctypes.create_string_buffer(1 << 16)
+    check(ctx, lib().mlfft_tune_report(ctx, array_id, buf, len(buf)))
+    return buf.value.decode()
+
+
+def mlfft_tune_import(ctx, text: str):
+    return check(ctx, lib().mlfft_tune_import(ctx, text.encode()))

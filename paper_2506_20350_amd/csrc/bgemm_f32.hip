@@ -1,0 +1,63 @@
+// FP32 instantiations of the block product (four- and three-product forms).
+#include "bgemm_impl.h"
+#include "bgemm_launch.h"
+
+namespace mlfft {
+
+template<typename T, int BP, int NT, int WAVES, int TAG>
+static hipError_t launch_real_cfg(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
+    const size_t lds = (size_t)NT * (2 * BP + 2) * sizeof(T);
+    auto k = bgemm_real_kernel<T, BP, NT, WAVES, TAG>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WAVES), lds, s, t0, td, n);
+    return hipGetLastError();
+}
+
+// tag 1 (preconditioner) always uses one fixed shape, so its kernel symbol differs
+// from every shape the MLFFT product can take
+template<typename T, int BP>
+static hipError_t launch_real(GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
+                              hipStream_t s) {
+    constexpr int NS = sizeof(T) == 8 ? 16 : 32;
+    if (tag) return launch_real_cfg<T, BP, NS, 8, 1>(t0, td, n, grid, s);
+    const bool big = sh.nt == 2 * NS;
+    if (sh.waves == 4)
+        return big ? launch_real_cfg<T, BP, 2 * NS, 4, 0>(t0, td, n, grid, s)
+                   : launch_real_cfg<T, BP, NS, 4, 0>(t0, td, n, grid, s);
+    return big ? launch_real_cfg<T, BP, 2 * NS, 8, 0>(t0, td, n, grid, s)
+               : launch_real_cfg<T, BP, NS, 8, 0>(t0, td, n, grid, s);
+}
+
+template<int BP, int NT, int WAVES, int TAG = 0>
+static hipError_t launch_3m_cfg(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
+    const size_t lds = (size_t)NT * (2 * BP + 2) * sizeof(float);
+    auto k = bgemm_f32_3m_kernel<BP, NT, WAVES, TAG>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WAVES), lds, s, t0, td, n);
+    return hipGetLastError();
+}
+
+template<int BP>
+static hipError_t launch_f32(GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
+                             hipStream_t s) {
+    constexpr int B16 = (BP + 15) / 16 * 16;
+    if (tag) return launch_3m_cfg<B16, 32, 8, 1>(t0, td, n, grid, s);   // preconditioner: fixed shape
+    if (sh.m3) {
+        if (sh.waves == 4)
+            return sh.nt == 64 ? launch_3m_cfg<B16, 64, 4>(t0, td, n, grid, s) : launch_3m_cfg<B16, 32, 4>(t0, td, n, grid, s);
+        return sh.nt == 64 ? launch_3m_cfg<B16, 64, 8>(t0, td, n, grid, s) : launch_3m_cfg<B16, 32, 8>(t0, td, n, grid, s);
+    }
+    return launch_real<float, BP>(sh, tag, t0, td, n, grid, s);
+}
+
+hipError_t launch_bgemm_f32(int bp, GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
+                            hipStream_t s) {
+    switch (bp) {
+#define C32(B) case B: return launch_f32<B>(sh, tag, t0, td, n, grid, s);
+        MLFFT_BP8(C32)
+#undef C32
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mlfft

@@ -1,0 +1,41 @@
+// FP64 instantiations of the block product.
+#include "bgemm_impl.h"
+#include "bgemm_launch.h"
+
+namespace mlfft {
+
+template<typename T, int BP, int NT, int WAVES, int TAG>
+static hipError_t launch_real_cfg(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
+    const size_t lds = (size_t)NT * (2 * BP + 2) * sizeof(T);
+    auto k = bgemm_real_kernel<T, BP, NT, WAVES, TAG>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WAVES), lds, s, t0, td, n);
+    return hipGetLastError();
+}
+
+// tag 1 (preconditioner) always uses one fixed shape, so its kernel symbol differs
+// from every shape the MLFFT product can take
+template<typename T, int BP>
+static hipError_t launch_real(GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
+                              hipStream_t s) {
+    constexpr int NS = sizeof(T) == 8 ? 16 : 32;
+    if (tag) return launch_real_cfg<T, BP, NS, 8, 1>(t0, td, n, grid, s);
+    const bool big = sh.nt == 2 * NS;
+    if (sh.waves == 4)
+        return big ? launch_real_cfg<T, BP, 2 * NS, 4, 0>(t0, td, n, grid, s)
+                   : launch_real_cfg<T, BP, NS, 4, 0>(t0, td, n, grid, s);
+    return big ? launch_real_cfg<T, BP, 2 * NS, 8, 0>(t0, td, n, grid, s)
+               : launch_real_cfg<T, BP, NS, 8, 0>(t0, td, n, grid, s);
+}
+
+hipError_t launch_bgemm_f64(int bp, GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
+                            hipStream_t s) {
+    switch (bp) {
+#define C64(B) case B: return launch_real<double, B>(sh, tag, t0, td, n, grid, s);
+        MLFFT_BP8(C64)
+#undef C64
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mlfft

@@ -1,0 +1,376 @@
+// Per-frequency block product of the MLFFT matvec (eq. multL: the block-diagonal
+// diag_{N0}(F^[2] C_1^[2]) applied to the transformed vectors), batched over all
+// right-hand sides:  Y[k][w][:] = G[k] X[k][w][:]  for every frequency k.
+//
+// With W right-hand sides each frequency is a complex (b x b) * (b x W) GEMM,
+// run on the MFMA units.  A complex product is one real GEMM of twice the size:
+// real row 2m+p (p = 0 real, 1 imaginary part of row m), real column 2n+c, with
+// the 2x2 block [[gr, -gi], [gi, gr]] of G(m, n); the interleaved complex
+// vectors X[k][w][:] are already the real operand in that order.
+//
+// Scheme (A stationary): a wave owns 16 real rows (8 complex rows) of G[k] and
+// keeps their MFMA A fragments for the whole reduction in registers, loaded once.
+// The workgroup streams the X columns of the frequency through LDS in tiles of
+// NT columns and every wave multiplies the tile by its rows.  Each workgroup
+// works on one frequency, so G[k] is read once per row group, and the row
+// groups of one frequency are placed on the same XCD so that they share the X
+// stream through that XCD's L2.
+//
+// Precisions: FP64 (v_mfma_f64_16x16x4f64), FP32 (v_mfma_f32_16x16x4f32) and
+// BF16 inputs with FP32 accumulation (v_mfma_f32_16x16x32_bf16, gfx950), where
+// G is stored as bf16 pairs and X is rounded to bf16 while it is staged in LDS.
+#pragma once
+#include "internal.h"
+
+#include <algorithm>
+
+namespace mlfft {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short ushortx8 __attribute__((ext_vector_type(8)));
+
+constexpr int kNT = 64;          // columns per LDS tile
+constexpr int kXcd = 8;          // XCDs on MI355X; workgroups are dealt round robin
+
+__device__ __forceinline__ const GemmTask* find_gemm_task(const GemmTask* tasks, int ntasks) {
+    int lo = 0, hi = ntasks - 1;
+    const int bid = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].block_begin <= bid) lo = mid; else hi = mid - 1;
+    }
+    return tasks + lo;
+}
+
+// XCD-aware decode of the workgroup index into (frequency, row group).
+__device__ __forceinline__ bool decode_block(const GemmTask& t, int* k, int* mg) {
+    const int local = blockIdx.x - t.block_begin;
+    const int xcd = local % kXcd;
+    const int r = local / kXcd;
+    *mg = r % t.mgroups;
+    *k = (r / t.mgroups) * kXcd + xcd;
+    return *k < t.K;
+}
+
+// ------------------------------------------------------------------ FP32 / FP64
+
+template<typename T> struct MfmaReal;
+// The accumulator layout of the two instructions differs: lane l, register r
+// holds output row 4*(l/16) + r for f32 and row 4*r + l/16 for f64.  A-fragment
+// row i is therefore mapped to the (complex row, part) that makes every lane
+// end up with (Re m, Im m, Re m+1, Im m+1), m = 2*(l/16), in both cases.
+template<> struct MfmaReal<float> {
+    typedef floatx4 acc_t;
+    typedef float2 c_t;
+    static __device__ __forceinline__ int row_cplx(int i) { return i >> 1; }
+    static __device__ __forceinline__ int row_part(int i) { return i & 1; }
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template<> struct MfmaReal<double> {
+    typedef doublex4 acc_t;
+    typedef double2 c_t;
+    static __device__ __forceinline__ int row_cplx(int i) { return 2 * (i & 3) + (i >> 3); }
+    static __device__ __forceinline__ int row_part(int i) { return (i >> 2) & 1; }
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template<typename T, int BP, int NT, int WAVES, int TAG>
+__global__ void __launch_bounds__(64 * WAVES) bgemm_real_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
+    typedef MfmaReal<T> M;
+    typedef typename M::c_t C;
+    typedef typename M::acc_t acc_t;
+    // complex elements of the next X tile each thread keeps in registers
+    constexpr int PF = (NT * BP + 64 * WAVES - 1) / (64 * WAVES);
+    extern __shared__ unsigned char smem_raw[];
+    T* xs = reinterpret_cast<T*>(smem_raw);
+    const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
+    int k, mg;
+    if (!decode_block(t, &k, &mg)) return;
+    const int b = t.b, W = t.W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slice = mg * WAVES + wave;
+    const int nslices = (b + 7) >> 3;
+    const bool active = slice < nslices;
+    const int m_base = slice * 8;
+    const int ldx = 2 * BP + 2;
+
+    // A fragments for all BP/2 reduction steps (4 real columns each)
+    T a[BP / 2];
+    {
+        const C* __restrict__ Gk = static_cast<const C*>(t.G) + (size_t)k * t.gstride;
+        const int i = lane & 15, kk = lane >> 4;
+        const int m = m_base + M::row_cplx(i), pr = M::row_part(i), pc = kk & 1;
+#pragma unroll
+        for (int s = 0; s < BP / 2; ++s) {
+            const int n = 2 * s + (kk >> 1);
+            T v = 0;
+            if (active && m < b && n < b) {
+                const C g = Gk[(size_t)m * b + n];
+                v = pr == 0 ? (pc == 0 ? g.x : -g.y) : (pc == 0 ? g.y : g.x);
+            }
+            a[s] = v;
+        }
+    }
+    // zero the padded reduction columns n in [b, BP) once; tiles never write them
+    const int padn = BP - b;
+    for (int e = threadIdx.x; e < NT * padn; e += 64 * WAVES) {
+        const int w = e / padn, n = b + (e - w * padn);
+        xs[w * ldx + 2 * n] = 0;
+        xs[w * ldx + 2 * n + 1] = 0;
+    }
+    const C* __restrict__ Xk = static_cast<const C*>(t.X) + (size_t)k * W * b;
+    C* __restrict__ Yk = static_cast<C*>(t.Y) + (size_t)k * W * b;
+    const int j = lane & 15, q = lane >> 4;
+    // the tile of NT columns is NT*b consecutive complex values; thread tid owns
+    // elements tid + i * 64 * WAVES of it
+    C pre[PF];
+    auto fetch = [&](int w0) {
+        const int have = min(NT, W - w0) * b;
+        const C* __restrict__ src = Xk + (size_t)w0 * b;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int e = threadIdx.x + i * 64 * WAVES;
+            pre[i] = e < have ? src[e] : czero<C>();
+        }
+    };
+    fetch(0);
+    for (int w0 = 0; w0 < W; w0 += NT) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int e = threadIdx.x + i * 64 * WAVES;
+            if (e < NT * b) {
+                const int w = e / b, n = e - w * b;
+                *reinterpret_cast<C*>(&xs[w * ldx + 2 * n]) = pre[i];
+            }
+        }
+        __syncthreads();
+        if (w0 + NT < W) fetch(w0 + NT);      // next tile in flight while this one is multiplied
+        if (active) {
+            acc_t acc[NT / 16];
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) acc[cg] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < BP / 2; ++s) {
+#pragma unroll
+                for (int cg = 0; cg < NT / 16; ++cg) {
+                    const T bv = xs[(cg * 16 + j) * ldx + 4 * s + q];
+                    acc[cg] = M::mma(a[s], bv, acc[cg]);
+                }
+            }
+            const int m = m_base + 2 * q;
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) {
+                const int w = w0 + cg * 16 + j;
+                if (w < W) {
+                    if (m < b) Yk[(size_t)w * b + m] = cmake<C>(acc[cg][0], acc[cg][1]);
+                    if (m + 1 < b) Yk[(size_t)w * b + m + 1] = cmake<C>(acc[cg][2], acc[cg][3]);
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ FP32, three real products
+
+// Complex product with three real products per complex multiply-add (the
+// Gauss / "3M" form): T1 = Gr Ur, T2 = Gi Ui, T3 = (Gr + Gi)(Ur + Ui), then
+// Re = T1 - T2, Im = T3 - T1 - T2.  A wave owns 16 complex rows; its A
+// fragments (Gr, Gi, Gr + Gi for all BP/4 reduction steps) stay in registers;
+// B fragments are the real and imaginary parts of 4 consecutive basis
+// functions of 16 columns, read from the LDS tile as one 8-byte pair.  The
+// MFMA work is 6 b^2 W flops instead of 8 b^2 W; the rounding error of Im grows
+// by at most a factor ~2 (|T3| <= 2 |G| |U|).
+template<int BP, int NT, int WAVES, int TAG>
+__global__ void __launch_bounds__(64 * WAVES) bgemm_f32_3m_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
+    constexpr int PF = (NT * BP + 64 * WAVES - 1) / (64 * WAVES);
+    extern __shared__ unsigned char smem_raw[];
+    float* xs = reinterpret_cast<float*>(smem_raw);
+    const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
+    int k, mg;
+    if (!decode_block(t, &k, &mg)) return;
+    const int b = t.b, W = t.W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slice = mg * WAVES + wave;
+    const int nslices = (b + 15) >> 4;
+    const bool active = slice < nslices;
+    const int m_base = slice * 16;
+    const int ldx = 2 * BP + 2;
+    float ar[BP / 4], ai[BP / 4], as[BP / 4];
+    {
+        const float2* __restrict__ Gk = static_cast<const float2*>(t.G) + (size_t)k * t.gstride;
+        const int m = m_base + (lane & 15), kk = lane >> 4;
+#pragma unroll
+        for (int s = 0; s < BP / 4; ++s) {
+            const int n = 4 * s + kk;
+            float2 g = make_float2(0.f, 0.f);
+            if (active && m < b && n < b) g = Gk[(size_t)m * b + n];
+            ar[s] = g.x;
+            ai[s] = g.y;
+            as[s] = g.x + g.y;
+        }
+    }
+    const int padn = BP - b;
+    for (int e = threadIdx.x; e < NT * padn; e += 64 * WAVES) {
+        const int w = e / padn, n = b + (e - w * padn);
+        xs[w * ldx + 2 * n] = 0.f;
+        xs[w * ldx + 2 * n + 1] = 0.f;
+    }
+    const float2* __restrict__ Xk = static_cast<const float2*>(t.X) + (size_t)k * W * b;
+    float2* __restrict__ Yk = static_cast<float2*>(t.Y) + (size_t)k * W * b;
+    const int j = lane & 15, q = lane >> 4;
+    float2 pre[PF];
+    auto fetch = [&](int w0) {
+        const int have = min(NT, W - w0) * b;
+        const float2* __restrict__ src = Xk + (size_t)w0 * b;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int e = threadIdx.x + i * 64 * WAVES;
+            pre[i] = e < have ? src[e] : make_float2(0.f, 0.f);
+        }
+    };
+    fetch(0);
+    for (int w0 = 0; w0 < W; w0 += NT) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int e = threadIdx.x + i * 64 * WAVES;
+            if (e < NT * b) {
+                const int w = e / b, n = e - w * b;
+                *reinterpret_cast<float2*>(&xs[w * ldx + 2 * n]) = pre[i];
+            }
+        }
+        __syncthreads();
+        if (w0 + NT < W) fetch(w0 + NT);
+        if (active) {
+            floatx4 t1[NT / 16], t2[NT / 16], t3[NT / 16];
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) {
+                t1[cg] = floatx4{0, 0, 0, 0};
+                t2[cg] = floatx4{0, 0, 0, 0};
+                t3[cg] = floatx4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int s = 0; s < BP / 4; ++s) {
+#pragma unroll
+                for (int cg = 0; cg < NT / 16; ++cg) {
+                    const float2 u = *reinterpret_cast<const float2*>(&xs[(cg * 16 + j) * ldx + 2 * (4 * s + q)]);
+                    t1[cg] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], u.x, t1[cg], 0, 0, 0);
+                    t2[cg] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[s], u.y, t2[cg], 0, 0, 0);
+                    t3[cg] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[s], u.x + u.y, t3[cg], 0, 0, 0);
+                }
+            }
+            // lane holds complex rows m_base + 4q + r (r = 0..3) of column j
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) {
+                const int w = w0 + cg * 16 + j;
+                if (w < W) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = m_base + 4 * q + r;
+                        if (m < b) {
+                            const float re = t1[cg][r] - t2[cg][r];
+                            const float im = t3[cg][r] - t1[cg][r] - t2[cg][r];
+                            Yk[(size_t)w * b + m] = make_float2(re, im);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ BF16
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) { return f32_to_bf16_bits(f); }
+
+template<int BP, int NT, int TAG>
+__global__ void __launch_bounds__(512) bgemm_bf16_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
+    extern __shared__ unsigned char smem_raw[];
+    unsigned short* xs = reinterpret_cast<unsigned short*>(smem_raw);
+    const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
+    int k, mg;
+    if (!decode_block(t, &k, &mg)) return;
+    const int b = t.b, W = t.W;
+    const int nw = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slice = mg * nw + wave;
+    const int nslices = (b + 7) >> 3;
+    const bool active = slice < nslices;
+    const int m_base = slice * 8;
+    const int ldx = 2 * BP + 8;               // bf16 elements per LDS row (16-byte skew)
+
+    // A fragments: BP/16 steps of 32 real columns; lane holds 8 consecutive real columns
+    ushortx8 a[BP / 16];
+    {
+        const uint32_t* __restrict__ Gk = static_cast<const uint32_t*>(t.G) + (size_t)k * t.gstride;
+        const int i = lane & 15, q = lane >> 4;
+        const int m = m_base + (i >> 1), pr = i & 1;
+#pragma unroll
+        for (int s = 0; s < BP / 16; ++s) {
+            ushortx8 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int n = 16 * s + 4 * q + e;
+                uint32_t g = 0;
+                if (active && m < b && n < b) g = Gk[(size_t)m * b + n];
+                const unsigned short gr = (unsigned short)(g & 0xffffu), gi = (unsigned short)(g >> 16);
+                if (pr == 0) { v[2 * e] = gr; v[2 * e + 1] = (unsigned short)(gi ^ 0x8000u); }
+                else         { v[2 * e] = gi; v[2 * e + 1] = gr; }
+            }
+            a[s] = v;
+        }
+    }
+    const int padn = BP - b;
+    for (int e = threadIdx.x; e < NT * padn; e += blockDim.x) {
+        const int w = e / padn, n = b + (e - w * padn);
+        *reinterpret_cast<uint32_t*>(&xs[w * ldx + 2 * n]) = 0u;
+    }
+    const float2* __restrict__ Xk = static_cast<const float2*>(t.X) + (size_t)k * W * b;
+    float2* __restrict__ Yk = static_cast<float2*>(t.Y) + (size_t)k * W * b;
+    const int j = lane & 15, q = lane >> 4;
+    for (int w0 = 0; w0 < W; w0 += NT) {
+        const int ncols = min(NT, W - w0);
+        __syncthreads();
+        const float2* __restrict__ src = Xk + (size_t)w0 * b;
+        const int tot = NT * b, have = ncols * b;
+        for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+            const int w = e / b, n = e - w * b;
+            const float2 v = e < have ? src[e] : make_float2(0.f, 0.f);
+            const uint32_t packed = (uint32_t)bf16_rne(v.x) | ((uint32_t)bf16_rne(v.y) << 16);
+            *reinterpret_cast<uint32_t*>(&xs[w * ldx + 2 * n]) = packed;
+        }
+        __syncthreads();
+        if (active) {
+            floatx4 acc[NT / 16];
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) acc[cg] = floatx4{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < BP / 16; ++s) {
+#pragma unroll
+                for (int cg = 0; cg < NT / 16; ++cg) {
+                    const ushortx8 bv = *reinterpret_cast<const ushortx8*>(&xs[(cg * 16 + j) * ldx + 32 * s + 8 * q]);
+                    acc[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, a[s]), __builtin_bit_cast(bf16x8, bv), acc[cg], 0, 0, 0);
+                }
+            }
+            const int m = m_base + 2 * q;
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) {
+                const int w = w0 + cg * 16 + j;
+                if (w < W) {
+                    if (m < b) Yk[(size_t)w * b + m] = make_float2(acc[cg][0], acc[cg][1]);
+                    if (m + 1 < b) Yk[(size_t)w * b + m + 1] = make_float2(acc[cg][2], acc[cg][3]);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace mlfft

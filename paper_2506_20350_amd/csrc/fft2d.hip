@@ -21,6 +21,8 @@
 #include "fft_codelets.h"
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 
 namespace mlfft {
 
@@ -260,6 +262,29 @@ __global__ void __launch_bounds__(512) fft_inv_kernel(FftTask t0, const FftTask*
 
 static const size_t kLdsBudget = 160 * 1024;
 
+// tuned m-chunk per (prec, pad, Nx, Ny, b); absent: the default rule
+static std::map<std::tuple<int, int, int, int, int>, int> g_cm_override;
+
+void fft_set_cm(int prec, int pad, int Nx, int Ny, int b, int cm) {
+    if (cm <= 0) g_cm_override.erase(std::make_tuple(prec, pad, Nx, Ny, b));
+    else g_cm_override[std::make_tuple(prec, pad, Nx, Ny, b)] = cm;
+}
+
+int fft_get_cm(int prec, int pad, int Nx, int Ny, int b) {
+    auto it = g_cm_override.find(std::make_tuple(prec, pad, Nx, Ny, b));
+    return it == g_cm_override.end() ? 0 : it->second;
+}
+
+// largest m-chunk the launch limits allow (LDS tile and 512 threads)
+int fft_max_cm(int prec, int pad, int Nx, int Ny, int b) {
+    const int eb = prec == P64 ? 16 : 8;
+    const int H = pad ? 2 : 1, Py = H * Ny;
+    int cm = 64;
+    if (cm > b) cm = b;
+    while (cm > 1 && ((size_t)Py * Nx * cm * eb > kLdsBudget || (Py > Nx ? Py : Nx) * cm > 512)) cm >>= 1;
+    return cm;
+}
+
 static int elem_bytes(int prec) { return prec == P64 ? 16 : 8; }
 
 void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block, size_t* lds) {
@@ -270,8 +295,9 @@ void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block,
         FftTask& t = tasks[i];
         const int H = t.pad ? 2 : 1;
         const int Py = H * t.Ny;
-        // 64-byte contiguous runs per series group; shrink when LDS would overflow
-        int cm = 64 / eb;
+        // default: 64-byte contiguous runs per series group; shrink when LDS would overflow
+        int cm = fft_get_cm(prec, t.pad, t.Nx, t.Ny, t.b);
+        if (cm <= 0) cm = 64 / eb;
         if (cm > t.b) cm = t.b;
         while (cm > 1 && (size_t)Py * t.Nx * cm * eb > kLdsBudget) cm >>= 1;
         while (cm > 1 && (Py > t.Nx ? Py : t.Nx) * cm > 512) cm >>= 1;

@@ -52,9 +52,18 @@ hipError_t launch_fft_inv(int prec, const FftTask* tasks_host, const FftTask* ta
 void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block, size_t* lds);
 
 // tag 0: MLFFT spectra, 1: preconditioner (separate kernel symbols for profilers)
+// tuned FFT m-chunk (basis functions per workgroup); cm <= 0 restores the default rule
+void fft_set_cm(int prec, int pad, int Nx, int Ny, int b, int cm);
+int fft_get_cm(int prec, int pad, int Nx, int Ny, int b);
+int fft_max_cm(int prec, int pad, int Nx, int Ny, int b);
+
 hipError_t launch_bgemm(int prec, const GemmTask* tasks_host, const GemmTask* tasks_dev, int ntasks, int tag,
                         hipStream_t s);
-void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int* grid, int* bp_max);
+void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int tag, int* grid, int* bp_max);
+// tuned launch shape of the MLFFT block product (waves per workgroup 4 or 8; columns per tile:
+// FP64 16 or 32, FP32 / BF16 32 or 64; FP32 three-product form m3 = 1)
+void gemm_set_shape(int prec, int bp, int waves, int nt, int m3);
+void gemm_get_shape(int prec, int bp, int* waves, int* nt, int* m3);
 int gemm_bp(int prec, int b);
 
 // spectra / preconditioner setup (all FP64)

@@ -168,7 +168,7 @@ mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec) {
     size_t lds;
     plan_fft_tasks(prec, fw.data(), nt, &grid, &block, &lds);
     plan_fft_tasks(prec, iv.data(), nt, &grid, &block, &lds);
-    plan_gemm_tasks(prec, gm.data(), nt, &gridg, &bpm);
+    plan_gemm_tasks(prec, gm.data(), nt, 0, &gridg, &bpm);
     void* dfw = nullptr;
     void* div = nullptr;
     void* dgm = nullptr;
@@ -225,7 +225,7 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
             gm[i] = g;
         }
         int gridg, bpm;
-        plan_gemm_tasks(prec, gm.data(), nt, &gridg, &bpm);
+        plan_gemm_tasks(prec, gm.data(), nt, 1, &gridg, &bpm);
         void* dgm = nullptr;
         if (nt > 1) {
             mlfft_status st = upload_tasks(gm.data(), sizeof(GemmTask) * nt, &dgm);
@@ -268,7 +268,7 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
     size_t lds;
     plan_fft_tasks(prec, fw.data(), nt, &grid, &block, &lds);
     plan_fft_tasks(prec, iv.data(), nt, &grid, &block, &lds);
-    plan_gemm_tasks(prec, gm.data(), nt, &gridg, &bpm);
+    plan_gemm_tasks(prec, gm.data(), nt, 1, &gridg, &bpm);
     void* dfw = nullptr;
     void* div = nullptr;
     void* dgm = nullptr;

@@ -193,6 +193,10 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
         } else {
             HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, w.dT, 1, s), "update");
         }
+        // Every column reached its target by the residual estimate within this
+        // cycle: the FP64 true residual of the outer loop judges the result, so
+        // no inner restart residual is formed.
+        if (running == 0) break;
     }
     (void)hstate;
     return MLFFT_OK;
@@ -305,8 +309,11 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
             if (!std::isfinite(hr[i])) return c->fail(MLFFT_E_ARG, "non-finite residual in column %d (check V and x0)", i);
             hstate[i] = done ? 2 : 0;
             active += !done;
-            // inner target, relative to the unit-norm inner right-hand side
-            const double need = done ? 1.0 : 0.9 * o.tol * hv[i] / hr[i];
+            // inner target, relative to the unit-norm inner right-hand side; an inner
+            // solve in reduced precision aims lower, so that its FP64 true residual
+            // (estimate plus the inner product's rounding) lands below tol and no
+            // second refinement step is needed
+            const double need = done ? 1.0 : (prec == P64 ? 0.9 : 0.3) * o.tol * hv[i] / hr[i];
             ht[i] = prec == P64 ? need : std::max(inner_floor, need);
             if (!done) outer_used[i] = outer + 1;
         }

@@ -88,9 +88,19 @@ def train(ctx: Context, Y: torch.Tensor, E: torch.Tensor, Nx: int, Ny: int, step
     return hist, v0, v1
 
 
+GATE = 0.9   # the correction is used only if it lowers the held-out loss to below GATE x the plain loss
+
+
 def prepare(ctx: Context, cfg: dict, train_grid: int = 20, hidden: int = 64, steps: int = 300, log=None,
             array_id: int = 100, lr: float = 2e-3):
-    """Build and train the network for the element of `cfg` (b, kd, seed) on a train_grid^2 array."""
+    """Build and train the network for the element of `cfg` (b, kd, seed) on a train_grid^2 array.
+
+    Returns a dict with the training record; its "enabled" entry says whether the
+    trained correction beat the plain block-circulant output on held-out pairs
+    (validation loss below GATE times the loss of the untrained, identity
+    correction).  When it did not, the solver should use the plain
+    preconditioner (the fallback) for this element.
+    """
     b, kd, seed = cfg["b"], cfg["kd"], cfg["seed"]
     n = train_grid
     t0 = time.perf_counter()
@@ -102,8 +112,11 @@ def prepare(ctx: Context, cfg: dict, train_grid: int = 20, hidden: int = 64, ste
     abi.mlfft_drop_array(ctx.h, array_id)
     del Y, E
     torch.cuda.empty_cache()
+    enabled = bool(v1 < GATE * v0)
     out = dict(train_grid=n, hidden=hidden, steps=steps, val_loss_before=v0, val_loss_after=v1,
-               train_loss_last=hist[-1] if hist else None, seconds=round(time.perf_counter() - t0, 2))
+               train_loss_last=hist[-1] if hist else None, seconds=round(time.perf_counter() - t0, 2),
+               enabled=enabled, gate=GATE)
     if log:
-        log(f"[learned] validation loss {v0:.4e} -> {v1:.4e} in {out['seconds']:.1f} s")
+        log(f"[learned] validation loss {v0:.4e} -> {v1:.4e} in {out['seconds']:.1f} s; "
+            f"correction {'enabled' if enabled else 'not better than the plain preconditioner: fallback'}")
     return out

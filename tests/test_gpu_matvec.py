@@ -155,3 +155,40 @@ def test_full_size_30x30_b120_sampled_columns(ctx, prec):
     ref = tp.matvec_fft(blocks, X[cols], 2 * Ny, 2 * Nx)
     assert relerr(y[cols], ref) <= TOL[prec]
     assert np.all(np.isfinite(y))
+
+
+@pytest.mark.parametrize("b", [8, 24, 120, 200, 13])
+@pytest.mark.parametrize("shape", ["4 32 1", "8 64 1", "4 64 0", "8 32 0"])
+def test_block_product_shapes_match_oracle(ctx, b, shape):
+    """Every launch shape the autotuner can pick, including the three-product FP32 form."""
+    Nx, Ny, W = 3, 4, 70
+    blocks = synth.random_blocks(Nx, Ny, b, seed=b)
+    ctx.set_blocks(50, blocks)
+    bp = (b + 7) // 8 * 8
+    waves, nt, m3 = shape.split()
+    abi.mlfft_tune_import(ctx.h, f"gemm 1 {bp} {waves} {nt} {m3}\n")
+    try:
+        X = synth.random_vectors(Nx * Ny * b, W, seed=4)
+        y = ctx.matvec(50, to_dev(X, torch.complex64), prec="fp32")
+        assert relerr(to_host(y), tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)) <= TOL["fp32"]
+    finally:
+        default_nt = 32 if bp > 160 else 64
+        abi.mlfft_tune_import(ctx.h, f"gemm 1 {bp} 8 {default_nt} 0\n")
+
+
+def test_autotuned_shapes_keep_parity(ctx):
+    Nx, Ny, b, W = 10, 10, 64, 100
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0)
+    ctx.set_blocks(51, blocks)
+    for prec in (0, 1):
+        abi.mlfft_autotune(ctx.h, 51, W, prec, 1)
+    rep = abi.mlfft_tune_report(ctx.h, 51)
+    assert "gemm 1 64" in rep and "fftcm 1 1 10 10 64" in rep
+    X = synth.random_vectors(Nx * Ny * b, W, seed=8)
+    ref = tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)
+    for prec in ("fp64", "fp32"):
+        y = ctx.matvec(51, to_dev(X, DT[prec]), prec=prec)
+        assert relerr(to_host(y), ref) <= TOL[prec]
+    R = synth.random_vectors(Nx * Ny * b, W, seed=9)
+    z = ctx.precond_apply(51, to_dev(R, DT["fp32"]), kind=1, prec="fp32")
+    assert relerr(to_host(z), opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)) <= 1e-4
