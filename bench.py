@@ -7,8 +7,15 @@ batched MLFFT products, preconditioner applies, Krylov steps and FP64
 refinement all run inside the timed region; the block spectra and the
 preconditioner are built before it (setup, reported separately).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c5]
-                    [--form fp32|bf16|fp64|learned] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c3]
+                    [--form learned|fp32|bf16|fp64|learned_forced] [--compare f1,f2,...]
+                    [--no-cpu-baseline]
+
+Default: the 30x30 array with b = 200 and all 900 port excitations, the
+learned-corrected FP32 form with FP64 refinement (validation-gated, with the
+plain block-circulant preconditioner as fallback), compared on the same GPU
+with plain FP64 block-circulant GMRES, the FP32 form without the correction
+and the correction forced on.
 
 Prints one JSON line (see the keys below).  Only one GPU is used: --gpus N
 with N > 1 exits with a message.
@@ -128,17 +135,85 @@ def cpu_baseline(blocks, V, cfg, tol, n_cols):
                        f"host logical CPUs {os.cpu_count()}"), cols, res, mv, pc
 
 
+def bench_batch(a, torch):
+    """64 arrays with Nx, Ny in [4, 24], b in {24, 48, 64, 96}, kd in [pi/2, pi], all ports, one batched solve."""
+    from paper_2506_20350_amd import abi, synth
+    from paper_2506_20350_amd.api import Context
+    specs = synth.c4_arrays(64, master_seed=0)
+    ctx = Context(0)
+    ids, Vs, Wt, setup = [], [], 0, 0.0
+    log(f"[bench] uneven batch: {len(specs)} arrays; generating blocks")
+    for i, sp in enumerate(specs):
+        blocks = synth.green_blocks(sp["Nx"], sp["Ny"], sp["b"], sp["kd"], seed=sp["seed"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.set_blocks(i, blocks)
+        torch.cuda.synchronize()
+        setup += time.perf_counter() - t0
+        ids.append(i)
+        Vs.append(torch.from_numpy(synth.port_rhs(sp["Nx"], sp["Ny"], sp["b"])).cuda())
+        Wt += sp["Nx"] * sp["Ny"]
+    log(f"[bench] {Wt} right-hand sides; setup {setup:.2f} s")
+    form = a.form if a.form in ("fp32", "fp64", "bf16") else "fp32"
+    opts = dict(FORMS[form])
+    opts.pop("label")
+
+    def run(opts):
+        Is, info = ctx.solve_batch(ids, Vs, tol=a.tol, **opts)
+        return Is, info
+    for _ in range(a.warmup):
+        run(opts)
+    abi.mlfft_profile_enable(ctx.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [run(opts)[1] for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = abi.mlfft_profile_read(ctx.h)
+    abi.mlfft_profile_enable(ctx.h, False)
+    conv = [int(np.sum(i["relres"] <= a.tol)) for i in infos]
+    value = sum(conv) / dt
+    dom, roof = roofline_of(stats)
+    o64 = dict(FORMS["fp64"])
+    o64.pop("label")
+    run(o64)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, i64 = run(o64)
+    torch.cuda.synchronize()
+    d64 = time.perf_counter() - t1
+    log(f"[bench] batch {form}: {dt / a.steps * 1e3:.1f} ms/step, {value:.1f} RHS/s; fp64 {d64 * 1e3:.1f} ms")
+    out = dict(metric="solved RHS/s @ rel-res 1e-6 (uneven batch of 64 arrays)", value=round(value, 2),
+               unit="RHS/s", n_gpus=1, steps=a.steps, warmup=a.warmup, ms_per_step=round(dt / a.steps * 1e3, 3),
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype=DTYPE[form], data="synthetic",
+               config=dict(workload=f"64 arrays, Nx,Ny in [4,24], b in {{24,48,64,96}}, kd in [pi/2,pi], "
+                                    f"{Wt} port RHS in one batched solve, {FORMS[form]['label']}, tol {a.tol:g}",
+                           arrays=len(specs), W_total=Wt, form=form, tol=a.tol),
+               roofline=roof,
+               roofline_kernel=dict(name=dom["name"], prec=dom["prec"], launches=dom["launches"],
+                                    avg_ms=round(dom["ms"] / dom["launches"], 4)),
+               kernels=[dict(name=s["name"], prec=s["prec"], launches=s["launches"],
+                             avg_ms=round(s["ms"] / s["launches"], 4)) for s in sorted(stats, key=lambda s: -s["ms"])],
+               setup_s=round(setup, 3), iters_mean=float(infos[-1]["iters"].mean()),
+               max_relres=float(infos[-1]["relres"].max()),
+               compare=[dict(form="fp64", value=round(int(np.sum(i64["relres"] <= a.tol)) / d64, 2),
+                             ms_per_step=round(d64 * 1e3, 3))])
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
-    ap.add_argument("--form", choices=sorted(FORMS), default="fp32")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4"], default="c5",
+                    help="c5: 30x30 b=200; c3: 30x30 b=120; c4: 64 uneven arrays in one batched solve")
+    ap.add_argument("--form", choices=sorted(FORMS), default="learned")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="residual reduction asked of each FP32 inner solve (library default if omitted)")
-    ap.add_argument("--compare", default="fp64",
+    ap.add_argument("--compare", default="fp64,fp32,learned_forced",
                     help="comma-separated forms timed on the same GPU for comparison (or 'none')")
     ap.add_argument("--train-steps", type=int, default=400, help="Adam steps of the learned correction")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shapes)")
@@ -167,6 +242,8 @@ def main():
     from paper_2506_20350_amd import synth
     from paper_2506_20350_amd.api import Context
 
+    if a.workload == "c4":
+        return bench_batch(a, torch)
     cfg = WORKLOADS[a.workload]
     Nx, Ny, b = cfg["Nx"], cfg["Ny"], cfg["b"]
     W = Nx * Ny
@@ -185,7 +262,8 @@ def main():
     if not a.no_tune:
         from paper_2506_20350_amd import abi as _abi
         t0 = time.perf_counter()
-        precs = {0} | {{"fp32": 1, "bf16": 2, "fp64": 0, "learned": 1}[f] for f in [a.form] + a.compare.split(",") if f in FORMS}
+        pmap = {"fp64": 0, "fp32": 1, "bf16": 2}
+        precs = {0} | {pmap[FORMS[f]["inner_prec"]] for f in [a.form] + a.compare.split(",") if f in FORMS}
         for p in sorted(precs):
             _abi.mlfft_autotune(ctx.h, 0, W, p, 2)
         tune_s = time.perf_counter() - t0

@@ -82,6 +82,9 @@ __device__ __forceinline__ const FftTask* find_task(const FftTask* tasks, int nt
 
 template<typename C, int NY>
 struct FwdY {
+    // The column is read from HBM once: with pad = 1 it is parked in the odd rows
+    // of this thread's own tile column while the even half is transformed, then
+    // read back, twiddled and transformed into those odd rows.
     static __device__ __forceinline__ void run(const FftTask& tt, Work wk, C* tile) {
         const FftTask* t = &tt;
         const int Nx = t->Nx, cm = t->cm, b = t->b;
@@ -92,18 +95,27 @@ struct FwdY {
         const C* __restrict__ src = static_cast<const C*>(t->in)
             + ((size_t)wk.w * NY * Nx + ix) * b + wk.m0 + mi;
         const size_t ys = (size_t)Nx * b;
-        const int H = t->pad ? 2 : 1;
-        for (int h = 0; h < H; ++h) {
-            C v[NY];
+        C* col = tile + ix * cm + mi;
+        const int rs = Nx * cm;
+        C v[NY];
 #pragma unroll
-            for (int iy = 0; iy < NY; ++iy) v[iy] = src[iy * ys];
-            if (h) Fft<C, NY, -1>::tw2(v);
+        for (int iy = 0; iy < NY; ++iy) v[iy] = src[iy * ys];
+        if (t->pad) {
+#pragma unroll
+            for (int j = 0; j < NY; ++j) col[(2 * j + 1) * rs] = v[j];
             Fft<C, NY, -1>::run(v);
 #pragma unroll
-            for (int j = 0; j < NY; ++j) {
-                const int ky = t->pad ? 2 * j + h : j;
-                tile[(ky * Nx + ix) * cm + mi] = v[j];
-            }
+            for (int j = 0; j < NY; ++j) col[2 * j * rs] = v[j];
+#pragma unroll
+            for (int j = 0; j < NY; ++j) v[j] = col[(2 * j + 1) * rs];
+            Fft<C, NY, -1>::tw2(v);
+            Fft<C, NY, -1>::run(v);
+#pragma unroll
+            for (int j = 0; j < NY; ++j) col[(2 * j + 1) * rs] = v[j];
+        } else {
+            Fft<C, NY, -1>::run(v);
+#pragma unroll
+            for (int j = 0; j < NY; ++j) col[j * rs] = v[j];
         }
     }
 };

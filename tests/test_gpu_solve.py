@@ -159,3 +159,29 @@ def test_full_size_30x30_b120_sampled_columns(ctx, kd):
     pc = lambda X: precond.strang_apply(Sinv, X)
     ref = np.array([r.x for r in krylov.gmres_columns(mv, V[cols], pc, tol=1e-12)])
     assert relerr(out[cols], ref) <= 1e-6
+
+
+def test_uneven_batch_like_c4_sampled_against_oracle(ctx):
+    """The first 12 arrays of the uneven-batch recipe (Nx, Ny in [4, 24], b in {24, 48, 64, 96},
+    kd in [pi/2, pi]) in one batched FP32 + FP64-refined solve; one column of every third array is
+    checked against the oracle's FP64 GMRES solution at 1e-12."""
+    specs = synth.c4_arrays(12, master_seed=0)
+    ids, Vs, blocks_all = [], [], []
+    for i, sp in enumerate(specs):
+        blocks = synth.green_blocks(sp["Nx"], sp["Ny"], sp["b"], sp["kd"], seed=sp["seed"])
+        ctx.set_blocks(60 + i, blocks)
+        ids.append(60 + i)
+        Vs.append(to_dev(synth.port_rhs(sp["Nx"], sp["Ny"], sp["b"])))
+        blocks_all.append(blocks)
+    Is, info = ctx.solve_batch(ids, Vs, tol=1e-9, inner_prec="fp32", precond=1)
+    assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-9)
+    for i in range(0, len(specs), 3):
+        sp = specs[i]
+        Nx, Ny, b = sp["Nx"], sp["Ny"], sp["b"]
+        col = (Nx * Ny) // 2
+        V = synth.port_rhs(Nx, Ny, b, cols=[col])
+        mv = lambda X: tp.matvec_fft(blocks_all[i], X, 2 * Ny, 2 * Nx)
+        Sinv = precond.strang_inverse_spectrum(blocks_all[i])
+        ref = krylov.gmres_columns(mv, V, lambda X: precond.strang_apply(Sinv, X), tol=1e-12)[0].x
+        got = to_host(Is[i])[col]
+        assert relerr(got, ref) <= 1e-7, (i, sp)
