@@ -109,6 +109,38 @@ def roofline_of(stats):
                      frac=round(ach / PEAK_HBM_GBS, 4), traffic=None)
 
 
+def traffic_record(group, prec, workload, tune_text):
+    """HBM bytes per launch of a kernel group from a committed rocprofv3 counter record, or None.
+
+    A record (profiles/*_traffic.txt, "key: value" lines) applies only to the kernel
+    group, precision, workload and tuned launch shape it was taken on, and only
+    while the kernel sources it names hash to the recorded value.
+    """
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt"))):
+        rec = {}
+        for line in open(path):
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+        if (rec.get("kernel_group"), rec.get("prec"), rec.get("workload")) != (group, str(prec), workload):
+            continue
+        if rec.get("tune_line") and rec["tune_line"] not in (tune_text or ""):
+            continue
+        h = hashlib.sha256()
+        try:
+            for f in rec["sources"].split():
+                h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            continue
+        if h.hexdigest()[:16] != rec.get("source_sha256"):
+            continue
+        return float(rec["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(blocks, V, cfg, tol, n_cols):
     """The oracle (FP64 MLFFT GMRES(30), Strang block-circulant preconditioner) on host cores."""
     from oracle import krylov, precond
@@ -259,6 +291,7 @@ def main():
     log(f"[bench] setup (spectra + preconditioner) {setup_s:.2f} s")
     Vd = torch.from_numpy(V).cuda()
     tune_s = None
+    tune_text = ""
     if not a.no_tune:
         from paper_2506_20350_amd import abi as _abi
         t0 = time.perf_counter()
@@ -267,7 +300,8 @@ def main():
         for p in sorted(precs):
             _abi.mlfft_autotune(ctx.h, 0, W, p, 2)
         tune_s = time.perf_counter() - t0
-        log(f"[bench] autotune {tune_s:.1f} s:\n" + _abi.mlfft_tune_report(ctx.h, 0).split("block_gemm")[0])
+        tune_text = _abi.mlfft_tune_report(ctx.h, 0)
+        log(f"[bench] autotune {tune_s:.1f} s:\n" + tune_text.split("block_gemm")[0])
     train_info = None
     if FORMS[a.form]["precond"] == 3 or any(FORMS.get(f, {}).get("precond") == 3 for f in a.compare.split(",")):
         from paper_2506_20350_amd import learned
@@ -282,6 +316,9 @@ def main():
     log(f"[bench] {a.form}: {dt / a.steps * 1e3:.1f} ms/step, {value:.1f} RHS/s, "
         f"iters mean {last['iters'].mean():.2f}, max relres {last['relres'].max():.2e}")
     dom, roof = roofline_of(stats)
+    tb = traffic_record(dom["name"], dom["prec"], a.workload, tune_text)
+    if tb is not None:
+        roof["traffic"] = tb
     kernels = [dict(name=s["name"], prec=s["prec"], launches=s["launches"], avg_ms=round(s["ms"] / s["launches"], 4),
                     total_ms=round(s["ms"], 3)) for s in sorted(stats, key=lambda s: -s["ms"])]
     out = dict(metric="solved RHS/s @ rel-res 1e-6 (30x30 array); MLFFT matvec % HBM/MFMA peak",
