@@ -214,7 +214,20 @@ def bench_batch(a, torch):
     _, i64 = run(o64)
     torch.cuda.synchronize()
     d64 = time.perf_counter() - t1
-    log(f"[bench] batch {form}: {dt / a.steps * 1e3:.1f} ms/step, {value:.1f} RHS/s; fp64 {d64 * 1e3:.1f} ms")
+    # the same solve with every Krylov step replayed from a captured HIP graph (side stream)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        og = dict(opts, use_graph=1)
+        for _ in range(2):                       # eager pass, then the capture pass
+            run(og)
+        side.synchronize()
+        t2 = time.perf_counter()
+        ginfos = [run(og)[1] for _ in range(a.steps)]
+        side.synchronize()
+        dg = time.perf_counter() - t2
+    gval = sum(int(np.sum(i["relres"] <= a.tol)) for i in ginfos) / dg
+    log(f"[bench] batch {form}: {dt / a.steps * 1e3:.1f} ms/step, {value:.1f} RHS/s; with graphs "
+        f"{dg / a.steps * 1e3:.1f} ms/step; fp64 {d64 * 1e3:.1f} ms")
     out = dict(metric="solved RHS/s @ rel-res 1e-6 (uneven batch of 64 arrays)", value=round(value, 2),
                unit="RHS/s", n_gpus=1, steps=a.steps, warmup=a.warmup, ms_per_step=round(dt / a.steps * 1e3, 3),
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype=DTYPE[form], data="synthetic",
@@ -229,7 +242,66 @@ def bench_batch(a, torch):
                setup_s=round(setup, 3), iters_mean=float(infos[-1]["iters"].mean()),
                max_relres=float(infos[-1]["relres"].max()),
                compare=[dict(form="fp64", value=round(int(np.sum(i64["relres"] <= a.tol)) / d64, 2),
-                             ms_per_step=round(d64 * 1e3, 3))])
+                             ms_per_step=round(d64 * 1e3, 3)),
+                        dict(form=form + "+graph", value=round(gval, 2), ms_per_step=round(dg / a.steps * 1e3, 3),
+                             note="Krylov steps replayed from captured HIP graphs; not profiled")])
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+SMALL = {
+    # 4x4 array, b = 24, kd = pi, the centre port, plain FP64 GMRES(30) without preconditioner, tol 1e-8
+    "c1": dict(Nx=4, Ny=4, b=24, kd=math.pi, seed=0, cols="centre", inner_prec="fp64", precond=0, tol=1e-8),
+    # 10x10 array, b = 64, all 100 ports, FP32 inner + FP64 refinement, block-circulant, tol 1e-8
+    "c2": dict(Nx=10, Ny=10, b=64, kd=math.pi, seed=0, cols="all", inner_prec="fp32", precond=1, tol=1e-8),
+}
+
+
+def bench_small(a, torch):
+    """Latency of the small cases, whose kernels take microseconds: eager launches against
+    Krylov steps replayed from captured HIP graphs (both on a side stream)."""
+    from paper_2506_20350_amd import abi, synth
+    from paper_2506_20350_amd.api import Context
+    cfg = SMALL[a.workload]
+    Nx, Ny, b = cfg["Nx"], cfg["Ny"], cfg["b"]
+    blocks = synth.green_blocks(Nx, Ny, b, cfg["kd"], seed=cfg["seed"])
+    V = synth.port_rhs(Nx, Ny, b, cols=[synth.centre_element(Nx, Ny)] if cfg["cols"] == "centre" else None)
+    side = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(side):
+        ctx = Context(0)
+        ctx.set_blocks(0, blocks)
+        Vd = torch.from_numpy(V).cuda()
+        for graph in (0, 1):
+            opts = dict(inner_prec=cfg["inner_prec"], precond=cfg["precond"], tol=cfg["tol"], use_graph=graph)
+            for _ in range(max(a.warmup, 2)):
+                ctx.solve(0, Vd, **opts)
+            reps = max(a.steps, 20)
+            side.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                I, info = ctx.solve(0, Vd, **opts)
+            side.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            its = float(info["iters"].max())
+            res[graph] = dict(us_per_solve=round(dt * 1e6, 1), us_per_iteration=round(dt * 1e6 / max(its, 1), 2),
+                              iters=its, outer=int(info["outer"].max()), max_relres=float(info["relres"].max()))
+            log(f"[bench] {a.workload} use_graph={graph}: {dt * 1e6:.1f} us/solve, {its:.0f} iterations")
+    from oracle import direct
+    from oracle import toeplitz as tp
+    err = float(np.linalg.norm(I.cpu().numpy() - direct.lu_solve(tp.dense_Z(blocks), V)) /
+                np.linalg.norm(direct.lu_solve(tp.dense_Z(blocks), V)))
+    W = V.shape[0]
+    g = res[1]
+    out = dict(metric=f"us per solve ({a.workload}: {Nx}x{Ny} array, b={b}, {W} RHS, tol {cfg['tol']:g})",
+               value=g["us_per_solve"], unit="us", n_gpus=1, steps=max(a.steps, 20), warmup=max(a.warmup, 2),
+               ms_per_step=round(g["us_per_solve"] / 1e3, 4), higher_is_better=False, scaling="weak",
+               vs_baseline=None, dtype="f64" if cfg["inner_prec"] == "fp64" else "f32+f64", data="synthetic",
+               config=dict(workload=f"{Nx}x{Ny} array, b={b}, kd={cfg['kd']:.4f}, {W} port RHS, "
+                                    f"inner {cfg['inner_prec']}, preconditioner {cfg['precond']}, tol {cfg['tol']:g}, "
+                                    "Krylov steps replayed from HIP graphs", Nx=Nx, Ny=Ny, b=b, W=W),
+               graph=res[1], eager=res[0], err_vs_lu=err,
+               note="latency-bound case: no roofline claim")
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -239,8 +311,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4"], default="c5",
-                    help="c5: 30x30 b=200; c3: 30x30 b=120; c4: 64 uneven arrays in one batched solve")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4"] + sorted(SMALL), default="c5",
+                    help="c5: 30x30 b=200; c3: 30x30 b=120; c4: 64 uneven arrays in one batched solve; "
+                         "c1, c2: latency of the small cases, eager and with graph-captured Krylov steps")
     ap.add_argument("--form", choices=sorted(FORMS), default="learned")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--inner-tol", type=float, default=None,
@@ -276,6 +349,8 @@ def main():
 
     if a.workload == "c4":
         return bench_batch(a, torch)
+    if a.workload in SMALL:
+        return bench_small(a, torch)
     cfg = WORKLOADS[a.workload]
     Nx, Ny, b = cfg["Nx"], cfg["Ny"], cfg["b"]
     W = Nx * Ny

@@ -135,7 +135,7 @@ typedef struct {
     int inner_prec;      /* mlfft_prec of the inner GMRES (default MLFFT_FP32).  MLFFT_FP64 = plain FP64 GMRES:
                             the outer loop then only confirms the true residual */
     double inner_tol;    /* floor of the residual reduction asked of each FP32 / BF16 inner solve; every inner
-                            solve aims at max(inner_tol, 0.9 * tol * ||V_w|| / ||r_w||).  0 (default) = automatic:
+                            solve aims at max(inner_tol, 0.3 * tol * ||V_w|| / ||r_w||).  0 (default) = automatic:
                             3e-7 for MLFFT_FP32, 1e-2 for MLFFT_FP32_BF16GEMM; ignored for MLFFT_FP64 */
     int max_outer;       /* FP64 refinement steps (default 10) */
     int precond;         /* 0 none, 1 block circulant (default), 2 self block (Kindt), 3 learned correction of the
@@ -143,7 +143,16 @@ typedef struct {
     int orth;            /* 1 classical Gram-Schmidt, 2 classical Gram-Schmidt applied twice (default); FP64 sums */
     int x0_given;        /* 1: I holds the initial guess on entry; 0: start from zero (default) */
     int record_history;  /* 1: fill info->history */
-    int use_graph;       /* reserved, must be 0 */
+    int use_graph;       /* 1: run the Krylov steps (preconditioner, product, orthogonalisation,
+                            rotation) four at a time as HIP graphs, captured the second time their
+                            launch configuration occurs and replayed afterwards; the host reads the
+                            column states once per graph instead of once per step.  Solutions,
+                            iteration counts and residuals are identical to use_graph = 0; steps
+                            after the last column retires inside a graph are spent (and counted
+                            in matvecs_inner).  Needs a context stream other than the NULL stream
+                            (else the steps run eagerly, one at a time).  Graphs are dropped
+                            whenever a library buffer is reallocated.  Profiling does not see
+                            captured launches. */
 } mlfft_solve_opts;
 
 typedef struct {

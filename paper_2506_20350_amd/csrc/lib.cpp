@@ -29,10 +29,13 @@ mlfft_status Ctx::hip_fail(hipError_t e, const char* what) {
     return fail(MLFFT_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+unsigned long mlfft::g_mem_epoch = 1;
+
 hipError_t Buf::ensure(size_t bytes) {
     if (n >= bytes && p) return hipSuccess;
     release();
     if (bytes == 0) return hipSuccess;
+    ++g_mem_epoch;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) { p = nullptr; n = 0; return e; }
     n = bytes;
@@ -40,13 +43,16 @@ hipError_t Buf::ensure(size_t bytes) {
 }
 
 void Buf::release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+        ++g_mem_epoch;
+        (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
 }
 
 int Ctx::prof_begin(int kind, int prec, double bytes, double flops) {
-    if (!prof) return -1;
+    if (!prof || capturing) return -1;
     while (prof_pool.size() < prof_used + 2) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return -1;
@@ -74,6 +80,7 @@ void Ctx::prof_release() {
 int* Ctx::pinned_state(int n) {
     if (n > pinned_n) {
         if (pinned) (void)hipHostFree(pinned);
+        ++g_mem_epoch;
         pinned = nullptr;
         pinned_n = 0;
         if (hipHostMalloc((void**)&pinned, (size_t)n * sizeof(int), hipHostMallocDefault) != hipSuccess) return nullptr;
@@ -115,6 +122,8 @@ mlfft_status Ctx::upload_tasks(const void* host, size_t bytes, void** dev) {
     std::string key((const char*)host, bytes);
     for (auto& e : task_cache)
         if (e.first == key) { *dev = e.second.p; return MLFFT_OK; }
+    // a graph capture replays only launches whose tables are already resident
+    if (capturing) return fail(MLFFT_E_STATE, "task table not resident during graph capture");
     if (task_cache.size() >= 64) {
         HIPCHK(hipStreamSynchronize(stream), "task cache flush");
         task_cache.clear();

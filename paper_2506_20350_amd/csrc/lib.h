@@ -9,6 +9,10 @@
 
 namespace mlfft {
 
+// Incremented whenever any library buffer is allocated or freed: a captured
+// graph holds raw device addresses and is valid only while this is unchanged.
+extern unsigned long g_mem_epoch;
+
 struct Buf {
     void* p = nullptr;
     size_t n = 0;
@@ -75,6 +79,18 @@ struct mlfft_ctx_s {
     int pinned_n = 0;
     struct Net* net = nullptr;     // learned preconditioner (netapi.cpp)
 
+    // Krylov steps captured as HIP graphs (solve option use_graph), keyed by the
+    // step's launch configuration; all dropped when g_mem_epoch moves.
+    std::map<std::string, hipGraphExec_t> graphs;
+    std::map<std::string, int> graph_seen;
+    unsigned long graph_epoch = 0;
+    bool capturing = false;
+    void graphs_release() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+        graph_seen.clear();
+    }
+
     bool prof = false;
     std::vector<mlfft::ProfRec> prof_recs;
     std::vector<hipEvent_t> prof_pool;
@@ -98,6 +114,7 @@ struct mlfft_ctx_s {
     mlfft_status matvec_group(const std::vector<mlfft::MatvecItem>& items, int prec);
     mlfft_status precond_group(const std::vector<mlfft::MatvecItem>& items, int kind, int prec);
     void release_workspaces() {
+        graphs_release();
         spec_a.release(); spec_b.release(); task_cache.clear(); solve_ws.release(); solve_ws2.release();
         if (pinned) (void)hipHostFree(pinned);
         pinned = nullptr;

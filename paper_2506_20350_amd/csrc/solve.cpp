@@ -130,6 +130,80 @@ static mlfft_status batch_precond(Ctx* c, std::vector<Seg>& segs, int kind, cons
     return MLFFT_OK;
 }
 
+// Krylov steps per captured graph (use_graph = 1).
+static const int kGraphSteps = 4;
+
+// Launch configuration of one Krylov step: everything its captured kernels and
+// copies depend on (the arrays, the column layout, the workspace addresses and
+// the options).  Buffers that move bump g_mem_epoch, which drops every graph.
+static std::string graph_key(Ctx* c, const std::vector<Seg>& segs, const Work& w, const mlfft_solve_opts& o,
+                             int prec, int j, const mlfft_solve_info* info) {
+    std::string k;
+    auto put = [&k](const void* p, size_t n) { k.append((const char*)p, n); };
+    const int hl = (info && o.record_history) ? info->history_len : 0;
+    const int ints[] = {j, prec, o.precond, o.orth, o.restart, w.Wt, hl};
+    put(ints, sizeof ints);
+    const void* ptrs[] = {c->solve_ws.p, c->solve_ws2.p, c->pinned, c->spec_a.p, c->spec_b.p};
+    put(ptrs, sizeof ptrs);
+    put(&w.S, sizeof w.S);
+    for (const Seg& sg : segs) {
+        put(&sg.arr, sizeof sg.arr);
+        put(&sg.W, sizeof sg.W);
+    }
+    return k;
+}
+
+// Run one Krylov step through a HIP graph.  The first time a configuration is
+// met the step runs eagerly (making every task table and workspace resident);
+// the second time it is captured (relaxed mode: no launch is executed while
+// capturing), instantiated and launched; afterwards the cached executable
+// graph is launched.  The step contains kernels and one device-to-host copy
+// into pinned memory, no memset.
+template<typename F>
+static mlfft_status graph_step(Ctx* c, const std::string& key, F&& step) {
+    hipStream_t s = c->stream;
+    if (s == nullptr) return step();        // the legacy NULL stream cannot be captured
+    if (c->graph_epoch != g_mem_epoch) {
+        HIPCHK(hipStreamSynchronize(s), "graph cache");
+        c->graphs_release();
+        c->graph_epoch = g_mem_epoch;
+    }
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+        HIPCHK(hipGraphLaunch(it->second, s), "graph launch");
+        return MLFFT_OK;
+    }
+    if (!c->graph_seen.count(key)) {
+        c->graph_seen[key] = 1;
+        return step();
+    }
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed), "begin capture");
+    c->capturing = true;
+    const mlfft_status st = step();
+    c->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st < 0 || e != hipSuccess) {
+        // nothing was executed while capturing: run the step eagerly instead
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        c->err.clear();
+        return step();
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(ei, "graph instantiate");
+    HIPCHK(hipGraphLaunch(ex, s), "graph launch");
+    if (c->graph_epoch == g_mem_epoch) {
+        c->graphs[key] = ex;
+    } else {
+        HIPCHK(hipStreamSynchronize(s), "graph");
+        (void)hipGraphExecDestroy(ex);
+    }
+    return MLFFT_OK;
+}
+
 template<typename C>
 static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const Cols& cols, const mlfft_solve_opts& o,
                                 int prec, mlfft_solve_info* info, std::vector<int>& hstate) {
@@ -156,27 +230,48 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
         int running = 0;
         for (int i = 0; i < Wt; ++i) running += pinned_state[i] == 0;
         if (running == 0) break;
-        for (int j = 0; j < m; ++j) {
-            void* vj = (char*)w.Vb + (size_t)j * vb;
-            void* vnext = (char*)w.Vb + (size_t)(j + 1) * vb;
-            const void* zsrc = vj;
-            if (o.precond) {
-                void* zdst = flexible ? (char*)w.Zb + (size_t)j * vb : w.tmp2T;
-                STCHK(batch_precond(c, segs, o.precond, vj, zdst, w.tmpT, prec, nullptr,
-                                    info ? &info->net_applies : nullptr));
-                if (info) info->precond_applies += 1;
-                zsrc = zdst;
+        for (int j = 0; j < m;) {
+            // one Krylov step: z_q = P^{-1} v_q, u = Z z_q, orthogonalise, rotate
+            auto step = [&](int q) -> mlfft_status {
+                void* vq = (char*)w.Vb + (size_t)q * vb;
+                void* vnext = (char*)w.Vb + (size_t)(q + 1) * vb;
+                const void* zsrc = vq;
+                if (o.precond) {
+                    void* zdst = flexible ? (char*)w.Zb + (size_t)q * vb : w.tmp2T;
+                    STCHK(batch_precond(c, segs, o.precond, vq, zdst, w.tmpT, prec, nullptr, nullptr));
+                    zsrc = zdst;
+                }
+                STCHK(batch_matvec(c, segs, zsrc, vnext, nullptr, 1.0, 0.0, prec));
+                // algorithmic traffic of one step: (orth + 1) passes over the q+2 vectors, one write
+                const int pr = c->prof_begin(PK_ARNOLDI, prec, (double)eb * w.S * ((o.orth + 1) * (q + 2) + 1), 0);
+                HIPCHK(k_arnoldi<C>(w.Vb, q, cols, w.H, m, w.state, o.orth, s), "arnoldi");
+                c->prof_end(pr);
+                HIPCHK(k_givens(w.H, w.cs, w.sn, w.g, q, m, Wt, w.state, w.target, w.kcyc, w.iters, w.est,
+                                o.record_history ? w.hist : nullptr, info ? info->history_len : 0, w.rnorm, s),
+                       "givens");
+                return MLFFT_OK;
+            };
+            // Eagerly the host checks the column states after every step.  With graphs,
+            // kGraphSteps steps form one graph and the host checks once per graph: a
+            // column that retires inside it is skipped by the remaining steps (their
+            // batched product still spends its work on it).
+            const int nstep = o.use_graph ? std::min(kGraphSteps, m - j) : 1;
+            auto steps = [&]() -> mlfft_status {
+                for (int q = j; q < j + nstep; ++q) STCHK(step(q));
+                HIPCHK(hipMemcpyAsync(pinned_state, w.state, Wt * sizeof(int), hipMemcpyDeviceToHost, s), "state");
+                return MLFFT_OK;
+            };
+            if (o.use_graph) {
+                STCHK(graph_step(c, graph_key(c, segs, w, o, prec, j, info), steps));
+            } else {
+                STCHK(steps());
             }
-            STCHK(batch_matvec(c, segs, zsrc, vnext, nullptr, 1.0, 0.0, prec));
-            if (info) info->matvecs_inner += 1;
-            // algorithmic traffic of one step: (orth + 1) passes over the j+2 vectors, one write
-            const int pr = c->prof_begin(PK_ARNOLDI, prec, (double)eb * w.S * ((o.orth + 1) * (j + 2) + 1), 0);
-            HIPCHK(k_arnoldi<C>(w.Vb, j, cols, w.H, m, w.state, o.orth, s), "arnoldi");
-            c->prof_end(pr);
-            HIPCHK(k_givens(w.H, w.cs, w.sn, w.g, j, m, Wt, w.state, w.target, w.kcyc, w.iters, w.est,
-                            o.record_history ? w.hist : nullptr, info ? info->history_len : 0, w.rnorm, s),
-                   "givens");
-            HIPCHK(hipMemcpyAsync(pinned_state, w.state, Wt * sizeof(int), hipMemcpyDeviceToHost, s), "state");
+            if (info) {
+                if (o.precond) info->precond_applies += nstep;
+                if (flexible) info->net_applies += nstep * (int)segs.size();
+                info->matvecs_inner += nstep;
+            }
+            j += nstep;
             HIPCHK(hipStreamSynchronize(s), "iteration");
             running = 0;
             for (int i = 0; i < Wt; ++i) running += pinned_state[i] == 0;

@@ -12,7 +12,7 @@ import torch
 
 from oracle import direct, krylov, precond
 from oracle import toeplitz as tp
-from paper_2506_20350_amd import abi, synth
+from paper_2506_20350_amd import abi, learned, synth
 from tests.gpu_util import ctx, relerr, to_dev, to_host  # noqa: F401
 
 pytestmark = pytest.mark.gpu
@@ -185,3 +185,59 @@ def test_uneven_batch_like_c4_sampled_against_oracle(ctx):
         ref = krylov.gmres_columns(mv, V, lambda X: precond.strang_apply(Sinv, X), tol=1e-12)[0].x
         got = to_host(Is[i])[col]
         assert relerr(got, ref) <= 1e-7, (i, sp)
+
+
+def _graph_case(ctx, aid, precond, seed):
+    Nx, Ny, b = 6, 5, 24
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=seed)
+    ctx.set_blocks(aid, blocks)
+    return blocks, to_dev(synth.port_rhs(Nx, Ny, b))
+
+
+@pytest.mark.parametrize("precond", [1, 3])
+def test_graph_captured_steps_match_eager_on_every_replay(ctx, precond):
+    """use_graph = 1 on a side stream: the first solve runs eagerly, the second captures every
+    Krylov step, the later ones replay the graphs.  Eager library work and host synchronisations
+    run between the solves; every solve must equal the eager solve bit for bit."""
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        if precond == 3:
+            abi.mlfft_net_create(ctx.h, 24, 16)
+            ws = learned.he_init(24, 16, seed=4)
+            ws[-16 * 48 * 9:] = np.random.default_rng(5).standard_normal(16 * 48 * 9).astype(np.float32) * 0.01
+            abi.mlfft_net_set_weights(ctx.h, ws)
+        blocks, V = _graph_case(ctx, 70, precond, seed=6)
+        I0, info0 = ctx.solve(70, V, tol=1e-10, inner_prec="fp32", precond=precond)
+        assert info0["status"] == abi.MLFFT_OK
+        for rep in range(4):
+            I, info = ctx.solve(70, V, tol=1e-10, inner_prec="fp32", precond=precond, use_graph=1)
+            y = ctx.matvec(70, I)                  # eager work between the replays
+            side.synchronize()
+            assert info["status"] == abi.MLFFT_OK, rep
+            assert torch.equal(I, I0), rep
+            assert np.array_equal(info["iters"], info0["iters"]) and np.array_equal(info["relres"], info0["relres"])
+            assert relerr(to_host(y), to_host(V)) <= 1e-9
+    ref = direct.lu_solve(tp.dense_Z(blocks), to_host(V))
+    assert relerr(to_host(I0), ref) <= 1e-8
+
+
+def test_graph_batch_matches_eager_and_null_stream_runs_eagerly(ctx):
+    shapes = [(4, 6, 24, 0.6 * np.pi), (7, 3, 16, np.pi)]
+    ids, Vs = [], []
+    for i, (Nx, Ny, b, kd) in enumerate(shapes):
+        ctx.set_blocks(72 + i, synth.green_blocks(Nx, Ny, b, kd, seed=1100 + i))
+        ids.append(72 + i)
+        Vs.append(to_dev(synth.port_rhs(Nx, Ny, b)))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        Is0, info0 = ctx.solve_batch(ids, Vs, tol=1e-10, inner_prec="fp32", precond=1)
+        for rep in range(3):
+            Is, info = ctx.solve_batch(ids, Vs, tol=1e-10, inner_prec="fp32", precond=1, use_graph=1)
+            side.synchronize()
+            assert all(torch.equal(a, b) for a, b in zip(Is, Is0)), rep
+            assert np.array_equal(info["iters"], info0["iters"])
+    # on the NULL stream the option is accepted and the steps run eagerly
+    torch.cuda.synchronize()
+    Is, info = ctx.solve_batch(ids, Vs, tol=1e-10, inner_prec="fp32", precond=1, use_graph=1)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(Is, Is0))
