@@ -68,9 +68,21 @@ struct Work {
     int w, m0, mlen;
 };
 
-__device__ __forceinline__ const FftTask* find_task(const FftTask* tasks, int ntasks) {
+// XCD-aware order of the work items.  Workgroups are dealt to the 8 XCDs round
+// robin, so consecutive workgroup indices land on different XCDs (and L2s).
+// Consecutive work items are the neighbouring basis-function chunks of one
+// column, whose global segments share 128-byte lines when a chunk is 64 bytes;
+// giving each XCD a contiguous range of work items lets the two halves of a line
+// meet in the same L2 instead of being fetched twice.
+__device__ __forceinline__ int work_index() {
+    const int bid = blockIdx.x, G = gridDim.x;
+    const int per = G >> 3;
+    if (bid >= per * 8) return bid;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+__device__ __forceinline__ const FftTask* find_task(const FftTask* tasks, int ntasks, int bid) {
     int lo = 0, hi = ntasks - 1;
-    const int bid = blockIdx.x;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (tasks[mid].block_begin <= bid) lo = mid; else hi = mid - 1;
@@ -152,10 +164,11 @@ template<typename C, int CLS, int PAD>
 __global__ void __launch_bounds__(512) fft_fwd_kernel(FftTask t0, const FftTask* tasks, int ntasks) {
     extern __shared__ unsigned char smem_raw[];
     C* tile = reinterpret_cast<C*>(smem_raw);
-    FftTask tl = ntasks > 0 ? *find_task(tasks, ntasks) : t0;
+    const int bid = work_index();
+    FftTask tl = ntasks > 0 ? *find_task(tasks, ntasks, bid) : t0;
     tl.pad = PAD;
     const FftTask* t = &tl;
-    const int local = blockIdx.x - t->block_begin;
+    const int local = bid - t->block_begin;
     Work wk;
     wk.w = local / t->nmc;
     const int mc = local - wk.w * t->nmc;
@@ -256,10 +269,11 @@ template<typename C, int CLS, int PAD>
 __global__ void __launch_bounds__(512) fft_inv_kernel(FftTask t0, const FftTask* tasks, int ntasks) {
     extern __shared__ unsigned char smem_raw[];
     C* tile = reinterpret_cast<C*>(smem_raw);
-    FftTask tl = ntasks > 0 ? *find_task(tasks, ntasks) : t0;
+    const int bid = work_index();
+    FftTask tl = ntasks > 0 ? *find_task(tasks, ntasks, bid) : t0;
     tl.pad = PAD;
     const FftTask* t = &tl;
-    const int local = blockIdx.x - t->block_begin;
+    const int local = bid - t->block_begin;
     Work wk;
     wk.w = local / t->nmc;
     const int mc = local - wk.w * t->nmc;

@@ -13,7 +13,17 @@ struct Cols {
     int W;
     size_t S;
     size_t maxN;
+    // Arnoldi chunking: column w owns chunks choff[w] .. choff[w+1]-1 (device,
+    // W+1 entries, arnoldi_chunks(N[w]) each), nch chunks in all; part1 / part2
+    // hold nch rows of 2m+3 doubles of partial sums (device)
+    const int* choff = nullptr;
+    int nch = 0;
+    double* part1 = nullptr;
+    double* part2 = nullptr;
 };
+
+// chunks of kArnChunk entries one column of N entries is cut into by k_arnoldi
+int arnoldi_chunks(size_t N);
 
 template<typename C> hipError_t k_colnorm(const void* x, const Cols& c, double* out, hipStream_t s);
 template<typename C> hipError_t k_arnoldi(void* Vb, int j, const Cols& c, double2* H, int m, const int* state,

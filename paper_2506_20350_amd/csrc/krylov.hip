@@ -73,91 +73,150 @@ __global__ void __launch_bounds__(256) colnorm_kernel(const C* __restrict__ x, c
 // One Arnoldi step for every iterating column: orthogonalise u = Vb[j+1] against
 // Vb[0..j] (classical Gram-Schmidt, applied twice when orth == 2), store the
 // coefficients in H[:, j] and u / ||u|| in Vb[j+1].
-template<typename C, int MAXJ>
-__global__ void __launch_bounds__(256) arnoldi_kernel(C* __restrict__ Vb, int j, size_t vstride,
-                                                      const size_t* __restrict__ coff, const int* __restrict__ cN,
-                                                      double2* __restrict__ H, int m, const int* __restrict__ state,
-                                                      int orth) {
+//
+// A column is cut into chunks of kArnChunk entries, one workgroup each, so that
+// a launch has many more workgroups than the chip has CUs whatever W is.  Three
+// passes over the j+2 vectors:
+//   dots (pass 1)  per chunk: Vᴴu and ||u||² partial sums
+//   dots (pass 2)  per chunk: h1 = sum of the pass-1 partials of the column, then
+//                  Vᴴu' and ||u'||² partials with u' = u - V h1 (u' is not stored)
+//   update         h = h1 + h2, beta² = ||u'||² - ||h2||², v_{j+1} = (u - V h) / beta
+// Every workgroup of a column reduces that column's partials itself, in the same
+// order, so the result does not depend on scheduling.  Partial rows have
+// `stride` doubles: 2 (j+1) for the coefficients, then the squared norm.
+constexpr int kArnT = 256;
+constexpr int kArnE = 32;
+constexpr int kArnChunk = kArnT * kArnE;
+
+__device__ __forceinline__ int chunk_column(const int* __restrict__ choff, int W, int c) {
+    int lo = 0, hi = W - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (choff[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// out[i] = sum over the column's chunks of part[chunk][i], i < cnt (fixed order)
+__device__ __forceinline__ void reduce_parts(const double* __restrict__ part, int c0, int nch, int stride, int cnt,
+                                             double* out) {
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < nch; ++q) s += part[(size_t)(c0 + q) * stride + i];
+        out[i] = s;
+    }
+}
+
+template<typename C, int MAXJ, int PASS>
+__global__ void __launch_bounds__(256) arnoldi_dots_kernel(const C* __restrict__ Vb, int j, size_t vstride,
+                                                           const size_t* __restrict__ coff, const int* __restrict__ cN,
+                                                           const int* __restrict__ choff, int W,
+                                                           const int* __restrict__ state,
+                                                           const double* __restrict__ part1,
+                                                           double* __restrict__ out, int stride) {
     __shared__ double red[4 * 72];
     __shared__ double sh[2 * MAXJ + 1];
-    __shared__ double h1[2 * MAXJ + 2];
-    const int w = blockIdx.x;
+    __shared__ double h1[2 * MAXJ + 1];
+    const int c = blockIdx.x;
+    const int w = chunk_column(choff, W, c);
+    if (state[w] != 0) return;
+    const int c0 = choff[w], nch = choff[w + 1] - c0;
     const size_t N = cN[w];
+    const size_t n0 = (size_t)(c - c0) * kArnChunk;
+    const C* __restrict__ V = Vb + coff[w];
+    const C* __restrict__ u = Vb + (size_t)(j + 1) * vstride + coff[w];
+    if (PASS == 2) {
+        reduce_parts(part1, c0, nch, stride, 2 * (j + 1), h1);
+        __syncthreads();
+    }
+    double vals[2 * MAXJ + 1];
+#pragma unroll
+    for (int i = 0; i < 2 * MAXJ + 1; ++i) vals[i] = 0.0;
+    for (int k = 0; k < kArnE; ++k) {
+        const size_t n = n0 + (size_t)k * kArnT + threadIdx.x;
+        if (n >= N) break;
+        double2 x = Acc<C>::w(u[n]);
+        double2 vv[MAXJ];
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i) {
+            if (i <= j) {
+                vv[i] = Acc<C>::w(V[(size_t)i * vstride + n]);
+                if (PASS == 2) {
+                    const double hr = h1[2 * i], hi = h1[2 * i + 1];
+                    x.x -= hr * vv[i].x - hi * vv[i].y;
+                    x.y -= hr * vv[i].y + hi * vv[i].x;
+                }
+            }
+        }
+        vals[2 * MAXJ] = fma(x.x, x.x, fma(x.y, x.y, vals[2 * MAXJ]));
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i) {
+            if (i <= j) {
+                vals[2 * i] = fma(vv[i].x, x.x, fma(vv[i].y, x.y, vals[2 * i]));
+                vals[2 * i + 1] = fma(vv[i].x, x.y, fma(-vv[i].y, x.x, vals[2 * i + 1]));
+            }
+        }
+    }
+    block_sum<2 * MAXJ + 1>(vals, 2 * (j + 1), red, sh);
+    double* o = out + (size_t)c * stride;
+    for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) o[i] = sh[i];
+    if (threadIdx.x == 0) o[2 * (j + 1)] = sh[2 * MAXJ];
+}
+
+template<typename C, int MAXJ>
+__global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb, int j, size_t vstride,
+                                                             const size_t* __restrict__ coff,
+                                                             const int* __restrict__ cN,
+                                                             const int* __restrict__ choff, int W,
+                                                             double2* __restrict__ H, int m,
+                                                             const int* __restrict__ state, int orth,
+                                                             const double* __restrict__ part1,
+                                                             const double* __restrict__ part2, int stride) {
+    __shared__ double h1[2 * MAXJ + 1];
+    __shared__ double h2[2 * MAXJ + 1];
+    const int c = blockIdx.x;
+    const int w = chunk_column(choff, W, c);
+    const int c0 = choff[w], nch = choff[w + 1] - c0;
+    const size_t N = cN[w];
+    const size_t n0 = (size_t)(c - c0) * kArnChunk;
     const C* __restrict__ V = Vb + coff[w];
     C* __restrict__ u = Vb + (size_t)(j + 1) * vstride + coff[w];
     if (state[w] != 0) {
         // retired column: keep its unused basis slot at zero so repeated products stay finite
-        for (size_t n = threadIdx.x; n < N; n += blockDim.x) u[n] = narrow<C>(make_double2(0.0, 0.0));
+        for (int k = 0; k < kArnE; ++k) {
+            const size_t n = n0 + (size_t)k * kArnT + threadIdx.x;
+            if (n >= N) break;
+            u[n] = narrow<C>(make_double2(0.0, 0.0));
+        }
         return;
     }
-    double vals[2 * MAXJ + 1];
-    // pass 1: h1 = V^H u and ||u||^2
-#pragma unroll
-    for (int i = 0; i < 2 * MAXJ + 1; ++i) vals[i] = 0.0;
-    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
-        const double2 un = Acc<C>::w(u[n]);
-        vals[2 * MAXJ] = fma(un.x, un.x, fma(un.y, un.y, vals[2 * MAXJ]));
-#pragma unroll
-        for (int i = 0; i < MAXJ; ++i) {
-            if (i <= j) {
-                const double2 v = Acc<C>::w(V[(size_t)i * vstride + n]);
-                vals[2 * i] = fma(v.x, un.x, fma(v.y, un.y, vals[2 * i]));
-                vals[2 * i + 1] = fma(v.x, un.y, fma(-v.y, un.x, vals[2 * i + 1]));
-            }
-        }
-    }
-    // reduce the j+1 coefficients and the norm (kept in the last slot)
-    block_sum<2 * MAXJ + 1>(vals, 2 * (j + 1), red, sh);
-    for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) h1[i] = sh[i];
-    if (threadIdx.x == 0) h1[2 * (j + 1)] = sh[2 * MAXJ];
+    const int cnt = 2 * (j + 1) + 1;
+    reduce_parts(part1, c0, nch, stride, cnt, h1);
+    if (orth == 2) reduce_parts(part2, c0, nch, stride, cnt, h2);
     __syncthreads();
+    const double unorm2 = h1[2 * (j + 1)];
     double beta2;
     if (orth == 2) {
-        // pass 2: h2 = V^H u' and ||u'||^2 with u' = u - V h1 (u' is not stored)
-#pragma unroll
-        for (int i = 0; i < 2 * MAXJ + 1; ++i) vals[i] = 0.0;
-        for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
-            double2 up = Acc<C>::w(u[n]);
-            double2 vv[MAXJ];
-#pragma unroll
-            for (int i = 0; i < MAXJ; ++i) {
-                if (i <= j) {
-                    vv[i] = Acc<C>::w(V[(size_t)i * vstride + n]);
-                    const double hr = h1[2 * i], hi = h1[2 * i + 1];
-                    up.x -= hr * vv[i].x - hi * vv[i].y;
-                    up.y -= hr * vv[i].y + hi * vv[i].x;
-                }
-            }
-            vals[2 * MAXJ] = fma(up.x, up.x, fma(up.y, up.y, vals[2 * MAXJ]));
-#pragma unroll
-            for (int i = 0; i < MAXJ; ++i) {
-                if (i <= j) {
-                    vals[2 * i] = fma(vv[i].x, up.x, fma(vv[i].y, up.y, vals[2 * i]));
-                    vals[2 * i + 1] = fma(vv[i].x, up.y, fma(-vv[i].y, up.x, vals[2 * i + 1]));
-                }
-            }
-        }
-        block_sum<2 * MAXJ + 1>(vals, 2 * (j + 1), red, sh);
         // ||u''||^2 = ||u'||^2 - ||h2||^2 (h2 is at rounding level; the subtraction is benign)
         double hn = 0.0;
-        for (int i = 0; i <= j; ++i) hn += sh[2 * i] * sh[2 * i] + sh[2 * i + 1] * sh[2 * i + 1];
-        beta2 = sh[2 * MAXJ] - hn;
+        for (int i = 0; i <= j; ++i) hn += h2[2 * i] * h2[2 * i] + h2[2 * i + 1] * h2[2 * i + 1];
+        beta2 = h2[2 * (j + 1)] - hn;
         __syncthreads();
-        for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) h1[i] += sh[i];
+        for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) h1[i] += h2[i];
         __syncthreads();
     } else {
         double hn = 0.0;
         for (int i = 0; i <= j; ++i) hn += h1[2 * i] * h1[2 * i] + h1[2 * i + 1] * h1[2 * i + 1];
-        beta2 = h1[2 * (j + 1)] - hn;
+        beta2 = unorm2 - hn;
     }
-    const double unorm2 = h1[2 * (j + 1)];
     double beta = beta2 > 0.0 ? sqrt(beta2) : 0.0;
     // happy breakdown: the new direction vanishes relative to the matvec output
     const bool brk = !(beta > 1e-14 * sqrt(unorm2)) || !(beta > 1e-300);
     if (brk) beta = 0.0;
     const double inv = brk ? 0.0 : 1.0 / beta;
-    // pass 3: v_{j+1} = (u - V h) / beta, in place
-    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+    for (int k = 0; k < kArnE; ++k) {
+        const size_t n = n0 + (size_t)k * kArnT + threadIdx.x;
+        if (n >= N) break;
         double2 up = Acc<C>::w(u[n]);
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i) {
@@ -170,10 +229,11 @@ __global__ void __launch_bounds__(256) arnoldi_kernel(C* __restrict__ Vb, int j,
         }
         u[n] = narrow<C>(make_double2(up.x * inv, up.y * inv));
     }
-    if (threadIdx.x <= j) {
-        H[((size_t)w * (m + 1) + threadIdx.x) * m + j] = make_double2(h1[2 * threadIdx.x], h1[2 * threadIdx.x + 1]);
+    if (c == c0) {
+        if (threadIdx.x <= j)
+            H[((size_t)w * (m + 1) + threadIdx.x) * m + j] = make_double2(h1[2 * threadIdx.x], h1[2 * threadIdx.x + 1]);
+        if (threadIdx.x == 0) H[((size_t)w * (m + 1) + j + 1) * m + j] = make_double2(beta, 0.0);
     }
-    if (threadIdx.x == 0) H[((size_t)w * (m + 1) + j + 1) * m + j] = make_double2(beta, 0.0);
 }
 
 // Apply the earlier rotations to H[:, j], build rotation j, update g, record
@@ -364,16 +424,34 @@ hipError_t k_colnorm(const void* x, const Cols& c, double* out, hipStream_t s) {
     return hipGetLastError();
 }
 
+int arnoldi_chunks(size_t N) { return (int)((N + kArnChunk - 1) / kArnChunk); }
+
+template<typename C, int MAXJ>
+static hipError_t arnoldi_t(C* Vb, int j, const Cols& c, double2* H, int m, const int* state, int orth,
+                            hipStream_t s) {
+    const int stride = 2 * m + 3;
+    const dim3 grid((unsigned)c.nch);
+    hipLaunchKernelGGL((arnoldi_dots_kernel<C, MAXJ, 1>), grid, dim3(kArnT), 0, s, (const C*)Vb, j, c.S, c.off, c.N,
+                       c.choff, c.W, state, (const double*)nullptr, c.part1, stride);
+    if (orth == 2)
+        hipLaunchKernelGGL((arnoldi_dots_kernel<C, MAXJ, 2>), grid, dim3(kArnT), 0, s, (const C*)Vb, j, c.S, c.off,
+                           c.N, c.choff, c.W, state, (const double*)c.part1, c.part2, stride);
+    hipLaunchKernelGGL((arnoldi_update_kernel<C, MAXJ>), grid, dim3(kArnT), 0, s, Vb, j, c.S, c.off, c.N, c.choff,
+                       c.W, H, m, state, orth, (const double*)c.part1, (const double*)c.part2, stride);
+    return hipGetLastError();
+}
+
 template<typename C>
 hipError_t k_arnoldi(void* Vb, int j, const Cols& c, double2* H, int m, const int* state, int orth, hipStream_t s) {
+    if (c.nch <= 0 || !c.choff || !c.part1 || (orth == 2 && !c.part2)) return hipErrorInvalidValue;
+    if (j + 1 > m || m > 31) return hipErrorInvalidValue;
     const int need = j + 1;
-    const size_t S = c.S;
-    if (need <= 4)       hipLaunchKernelGGL((arnoldi_kernel<C, 4>), dim3(c.W), dim3(256), 0, s, (C*)Vb, j, S, c.off, c.N, H, m, state, orth);
-    else if (need <= 8)  hipLaunchKernelGGL((arnoldi_kernel<C, 8>), dim3(c.W), dim3(256), 0, s, (C*)Vb, j, S, c.off, c.N, H, m, state, orth);
-    else if (need <= 16) hipLaunchKernelGGL((arnoldi_kernel<C, 16>), dim3(c.W), dim3(256), 0, s, (C*)Vb, j, S, c.off, c.N, H, m, state, orth);
-    else if (need <= 32) hipLaunchKernelGGL((arnoldi_kernel<C, 32>), dim3(c.W), dim3(256), 0, s, (C*)Vb, j, S, c.off, c.N, H, m, state, orth);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
+    C* V = (C*)Vb;
+    if (need <= 4) return arnoldi_t<C, 4>(V, j, c, H, m, state, orth, s);
+    if (need <= 8) return arnoldi_t<C, 8>(V, j, c, H, m, state, orth, s);
+    if (need <= 16) return arnoldi_t<C, 16>(V, j, c, H, m, state, orth, s);
+    if (need <= 32) return arnoldi_t<C, 32>(V, j, c, H, m, state, orth, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t k_givens(double2* H, double* cs, double2* sn, double2* g, int j, int m, int W, int* state,

@@ -329,7 +329,12 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     const size_t v64b = align_up(S * 16), vTb = align_up(S * eb);
     size_t big = 3 * v64b + 4 * vTb + (size_t)(m + 1) * vTb + (flexible ? (size_t)m * vTb : 0);
     const int hist_len = (info && o.record_history) ? info->history_len : 0;
-    size_t small = align_up(Wt * sizeof(size_t)) + 5 * align_up(Wt * sizeof(int)) +
+    // Arnoldi chunks of every column and their partial-sum rows
+    std::vector<int> hchoff(Wt + 1, 0);
+    for (int i = 0; i < Wt; ++i) hchoff[i + 1] = hchoff[i] + arnoldi_chunks((size_t)hN[i]);
+    const int nch = hchoff[Wt];
+    const size_t partb = align_up((size_t)nch * (2 * m + 3) * sizeof(double));
+    size_t small = align_up((Wt + 1) * sizeof(int)) + 2 * partb + align_up(Wt * sizeof(size_t)) + 5 * align_up(Wt * sizeof(int)) +
                    6 * align_up(Wt * sizeof(double)) + align_up((size_t)Wt * (m + 1) * m * 16) +
                    align_up((size_t)Wt * (m + 1) * 16) + 2 * align_up((size_t)Wt * m * 16) +
                    align_up((size_t)Wt * m * 8) + align_up((size_t)std::max(hist_len, 1) * Wt * 8);
@@ -346,6 +351,9 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     w.Vb = p; p += (size_t)(m + 1) * vTb;
     w.Zb = flexible ? (void*)p : nullptr;
     char* q = (char*)c->solve_ws2.p;
+    int* choff = (int*)q; q += align_up((Wt + 1) * sizeof(int));
+    double* part1 = (double*)q; q += partb;
+    double* part2 = (double*)q; q += partb;
     w.coff = (size_t*)q; q += align_up(Wt * sizeof(size_t));
     w.cN = (int*)q; q += align_up(Wt * sizeof(int));
     w.state = (int*)q; q += align_up(Wt * sizeof(int));
@@ -366,6 +374,11 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     w.hist = (double*)q;
     (void)scratch_d;
     Cols cols{w.coff, w.cN, Wt, S, w.maxN};
+    cols.choff = choff;
+    cols.nch = nch;
+    cols.part1 = part1;
+    cols.part2 = part2;
+    HIPCHK(hipMemcpyAsync(choff, hchoff.data(), (Wt + 1) * sizeof(int), hipMemcpyHostToDevice, s), "columns");
     HIPCHK(hipMemcpyAsync(w.coff, hoff.data(), Wt * sizeof(size_t), hipMemcpyHostToDevice, s), "columns");
     HIPCHK(hipMemcpyAsync(w.cN, hN.data(), Wt * sizeof(int), hipMemcpyHostToDevice, s), "columns");
     HIPCHK(hipMemsetAsync(w.iters, 0, Wt * sizeof(int), s), "iters");
