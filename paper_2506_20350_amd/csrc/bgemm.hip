@@ -23,7 +23,7 @@ static GemmShape default_shape(int prec, int bp) {
 }
 
 GemmShape gemm_shape(int prec, int bp, int tag) {
-    if (tag) return GemmShape{8, prec == P64 ? 16 : prec == P32 ? 32 : 64, prec == P32 ? 1 : 0};
+    if (tag) return GemmShape{8, prec == P64 ? 16 : prec == P32 ? 32 : 64, prec == P32 ? 2 : 0};
     const GemmShape& o = g_shape_override[prec][bp / 8];
     return o.waves ? o : default_shape(prec, bp);
 }
@@ -46,17 +46,39 @@ static int bp_max_of(int prec, const GemmTask* tasks, int ntasks) {
     return bpm;
 }
 
+// workgroups of one task: one per (frequency, row group), frequencies padded to a
+// multiple of the XCD count; the flat three-product kernel (m3 == 2) deals the
+// K * ceil(b/16) (frequency, slice) items to eight waves per workgroup
+static int task_blocks(const GemmTask& t, const GemmShape& sh) {
+    if (sh.m3 == 2) return (t.K * ((t.b + 15) / 16) + 7) / 8;
+    return ((t.K + kXcd - 1) / kXcd) * kXcd * t.mgroups;
+}
+
+// The flat kernel stages at most two frequencies per workgroup, which holds when
+// eight consecutive slices never cover three frequencies: ceil(b / 16) >= 7 for
+// every task of the launch.  Otherwise the three-product kernel with one
+// workgroup per row group is used.
+static GemmShape launch_shape(int prec, const GemmTask* tasks, int ntasks, int tag, int bpm) {
+    GemmShape sh = gemm_shape(prec, bpm, tag);
+    if (sh.m3 == 2) {
+        int bmin = 1 << 30;
+        for (int i = 0; i < ntasks; ++i) bmin = std::min(bmin, tasks[i].b);
+        if ((bmin + 15) / 16 < 7) sh = GemmShape{8, 32, 1};
+    }
+    return sh;
+}
+
 void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int tag, int* grid, int* bp_max) {
     int g = 0;
     const int bpm = bp_max_of(prec, tasks, ntasks);
-    const GemmShape sh = gemm_shape(prec, bpm, tag);
+    const GemmShape sh = launch_shape(prec, tasks, ntasks, tag, bpm);
     const int rows = sh.m3 ? 16 : 8;
     for (int i = 0; i < ntasks; ++i) {
         GemmTask& t = tasks[i];
         const int nslices = (t.b + rows - 1) / rows;
         t.mgroups = (nslices + sh.waves - 1) / sh.waves;
         t.block_begin = g;
-        g += ((t.K + kXcd - 1) / kXcd) * kXcd * t.mgroups;
+        g += task_blocks(t, sh);
     }
     *grid = g;
     *bp_max = bpm;
@@ -65,13 +87,13 @@ void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int tag, int* grid, 
 hipError_t launch_bgemm(int prec, const GemmTask* th, const GemmTask* td, int ntasks, int tag, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
     int grid = 0;
+    const int bpm = bp_max_of(prec, th, ntasks);
+    const GemmShape sh = launch_shape(prec, th, ntasks, tag, bpm);
     for (int i = 0; i < ntasks; ++i) {
-        const int end = th[i].block_begin + ((th[i].K + kXcd - 1) / kXcd) * kXcd * th[i].mgroups;
+        const int end = th[i].block_begin + task_blocks(th[i], sh);
         if (end > grid) grid = end;
     }
     if (grid == 0) return hipSuccess;
-    const int bpm = bp_max_of(prec, th, ntasks);
-    const GemmShape sh = gemm_shape(prec, bpm, tag);
     const GemmTask* dt = ntasks > 1 ? td : nullptr;
     const int n = ntasks > 1 ? ntasks : 0;
     if (prec == P64) return launch_bgemm_f64(bpm, sh, tag, th[0], dt, n, grid, s);
