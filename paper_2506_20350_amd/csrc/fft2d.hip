@@ -108,7 +108,7 @@ struct FwdY {
             + ((size_t)wk.w * NY * Nx + ix) * b + wk.m0 + mi;
         const size_t ys = (size_t)Nx * b;
         C* col = tile + ix * cm + mi;
-        const int rs = Nx * cm;
+        const int rs = t->rs;
         C v[NY];
 #pragma unroll
         for (int iy = 0; iy < NY; ++iy) v[iy] = src[iy * ys];
@@ -148,7 +148,7 @@ struct FwdX {
         for (int g = 0; g < H; ++g) {
             C v[NX];
 #pragma unroll
-            for (int ix = 0; ix < NX; ++ix) v[ix] = tile[(ky * NX + ix) * cm + mi];
+            for (int ix = 0; ix < NX; ++ix) v[ix] = tile[ky * t->rs + ix * cm + mi];
             if (g) Fft<C, NX, -1>::tw2(v);
             Fft<C, NX, -1>::run(v);
 #pragma unroll
@@ -196,7 +196,7 @@ struct InvX {
         if (mi >= wk.mlen) return;
         const C* __restrict__ src = static_cast<const C*>(t->in) + (size_t)wk.w * b + wk.m0 + mi;
         const size_t ks = (size_t)W * b;
-        C* row = tile + ky * NX * cm + mi;
+        C* row = tile + ky * t->rs + mi;
         for (int g = 0; g < H; ++g) {
             C v[NX];
 #pragma unroll
@@ -231,7 +231,7 @@ struct InvY {
         const int ix = tid / cm, mi = tid - ix * cm;
         if (mi >= wk.mlen) return;
         C* col = tile + ix * cm + mi;
-        const int rs = Nx * cm;
+        const int rs = t->rs;
         C v[NY];
 #pragma unroll
         for (int j = 0; j < NY; ++j) v[j] = col[(t->pad ? 2 * j : j) * rs];
@@ -302,12 +302,27 @@ int fft_get_cm(int prec, int pad, int Nx, int Ny, int b) {
 }
 
 // largest m-chunk the launch limits allow (LDS tile and 512 threads)
+// LDS rows of a tile
+static int tile_rows(int prec, int pad, int Ny) { (void)prec; return (pad ? 2 : 1) * Ny; }
+
+// Row stride of a tile in elements.  A wave reads 64 / cm rows of cm consecutive
+// elements each (the x-transforms); with the stride a multiple of the segment
+// width plus one segment modulo the 256-byte LDS bank period, the rows fall on
+// successive banks instead of all on the same ones.
+static int tile_stride(int eb, int Nx, int cm) {
+    int rs = Nx * cm;
+    if (cm * eb >= 256) return rs;
+    while (((rs - cm) * eb) % 256 != 0) ++rs;
+    return rs;
+}
+
 int fft_max_cm(int prec, int pad, int Nx, int Ny, int b) {
     const int eb = prec == P64 ? 16 : 8;
-    const int H = pad ? 2 : 1, Py = H * Ny;
+    const int Py = tile_rows(prec, pad, Ny);
     int cm = 64;
     if (cm > b) cm = b;
-    while (cm > 1 && ((size_t)Py * Nx * cm * eb > kLdsBudget || (Py > Nx ? Py : Nx) * cm > 512)) cm >>= 1;
+    while (cm > 1 && ((size_t)Py * tile_stride(eb, Nx, cm) * eb > kLdsBudget || (Py > Nx ? Py : Nx) * cm > 512))
+        cm >>= 1;
     return cm;
 }
 
@@ -319,13 +334,12 @@ void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block,
     size_t l = 0;
     for (int i = 0; i < ntasks; ++i) {
         FftTask& t = tasks[i];
-        const int H = t.pad ? 2 : 1;
-        const int Py = H * t.Ny;
+        const int Py = tile_rows(prec, t.pad, t.Ny);
         // default: 64-byte contiguous runs per series group; shrink when LDS would overflow
         int cm = fft_get_cm(prec, t.pad, t.Nx, t.Ny, t.b);
         if (cm <= 0) cm = 64 / eb;
         if (cm > t.b) cm = t.b;
-        while (cm > 1 && (size_t)Py * t.Nx * cm * eb > kLdsBudget) cm >>= 1;
+        while (cm > 1 && (size_t)Py * tile_stride(eb, t.Nx, cm) * eb > kLdsBudget) cm >>= 1;
         while (cm > 1 && (Py > t.Nx ? Py : t.Nx) * cm > 512) cm >>= 1;
         t.cm = cm;
         t.nmc = (t.b + cm - 1) / cm;
@@ -334,7 +348,8 @@ void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block,
         int thr = (Py > t.Nx ? Py : t.Nx) * cm;
         thr = (thr + 63) / 64 * 64;
         if (thr > blk) blk = thr;
-        const size_t ll = (size_t)Py * t.Nx * cm * eb;
+        t.rs = tile_stride(eb, t.Nx, cm);
+        const size_t ll = (size_t)Py * t.rs * eb;
         if (ll > l) l = ll;
     }
     *grid = g;
@@ -361,14 +376,15 @@ static hipError_t launch_t(const FftTask* th, const FftTask* td, int ntasks, hip
     int grid = 0, block = 64, cls = 0;
     size_t lds = 0;
     const int eb = sizeof(C);
+    const int prec = sizeof(C) == 16 ? P64 : P32;
     for (int i = 0; i < ntasks; ++i) {
         const FftTask& t = th[i];
         if (t.pad != th[0].pad) return hipErrorInvalidValue;
-        const int H = t.pad ? 2 : 1, Py = H * t.Ny;
+        const int Py = tile_rows(prec, t.pad, t.Ny);
         grid = t.block_begin + t.nmc * t.W > grid ? t.block_begin + t.nmc * t.W : grid;
         int thr = ((Py > t.Nx ? Py : t.Nx) * t.cm + 63) / 64 * 64;
         if (thr > block) block = thr;
-        size_t ll = (size_t)Py * t.Nx * t.cm * eb;
+        size_t ll = (size_t)Py * t.rs * eb;
         if (ll > lds) lds = ll;
         cls = std::max(cls, std::max(len_class(t.Nx), len_class(t.Ny)));
     }

@@ -23,6 +23,7 @@ struct FftTask {
     double beta;
     int Nx, Ny, b, W;
     int cm;                 // basis functions per workgroup (m chunk)
+    int rs;                 // row stride of the LDS tile in elements (>= Nx * cm)
     int nmc;                // number of m chunks
     int block_begin;        // first workgroup of this task in the grouped grid
     int pad;
