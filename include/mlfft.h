@@ -153,6 +153,15 @@ typedef struct {
                             (else the steps run eagerly, one at a time).  Graphs are dropped
                             whenever a library buffer is reallocated.  Profiling does not see
                             captured launches. */
+    int mode;            /* 0 (default): one Krylov space per right-hand side (the paper's split
+                            mode with all columns batched); 1: global GMRES (eq. ZIVvec), one
+                            Krylov space for all W columns (of all arrays of a batch) with
+                            Frobenius inner products; each inner solve aims at
+                            ||R||_F <= f * tol * ||V||_F.  The outer FP64 loop still requires
+                            every column's own relres <= tol and repeats the global inner solve
+                            until it holds; info->iters and info->history then report the
+                            global iteration for every column.  MLFFT_E_ARG if the batch has
+                            more than 2^31-1 unknowns in all. */
 } mlfft_solve_opts;
 
 typedef struct {

@@ -48,7 +48,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_restarts", ctypes.c_int), ("tol", ctypes.c_double),
                 ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("precond", ctypes.c_int), ("orth", ctypes.c_int), ("x0_given", ctypes.c_int),
-                ("record_history", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("record_history", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("mode", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -56,6 +56,7 @@ struct Work {
     size_t* coff;
     int* cN;
     double *vnorm, *rnorm, *target, *est, *hist;
+    const double* kscale;         // norm of each Krylov column's unscaled right-hand side
     int *state, *kcyc, *iters, *mask;
     double2 *H, *g, *sn, *y;
     double* cs;
@@ -80,6 +81,7 @@ extern "C" mlfft_status mlfft_solve_default_opts(mlfft_solve_opts* o) {
     o->x0_given = 0;
     o->record_history = 0;
     o->use_graph = 0;
+    o->mode = 0;
     return MLFFT_OK;
 }
 
@@ -95,6 +97,7 @@ static mlfft_status check_opts(Ctx* c, const mlfft_solve_opts& o) {
     if (o.precond < 0 || o.precond > 3) return c->fail(MLFFT_E_ARG, "precond must be 0, 1, 2 or 3");
     if (o.orth != 1 && o.orth != 2) return c->fail(MLFFT_E_ARG, "orth must be 1 or 2");
     if (o.use_graph != 0 && o.use_graph != 1) return c->fail(MLFFT_E_ARG, "use_graph must be 0 or 1");
+    if (o.mode != 0 && o.mode != 1) return c->fail(MLFFT_E_ARG, "mode must be 0 (per right-hand side) or 1 (global)");
     if (o.precond == 3 && !c->net_ready()) return c->fail(MLFFT_E_STATE, "learned preconditioner requested but no network is loaded");
     return MLFFT_OK;
 }
@@ -141,7 +144,7 @@ static std::string graph_key(Ctx* c, const std::vector<Seg>& segs, const Work& w
     std::string k;
     auto put = [&k](const void* p, size_t n) { k.append((const char*)p, n); };
     const int hl = (info && o.record_history) ? info->history_len : 0;
-    const int ints[] = {j, prec, o.precond, o.orth, o.restart, w.Wt, hl};
+    const int ints[] = {j, prec, o.precond, o.orth, o.restart, w.Wt, hl, o.mode};
     put(ints, sizeof ints);
     const void* ptrs[] = {c->solve_ws.p, c->solve_ws2.p, c->pinned, c->spec_a.p, c->spec_b.p};
     put(ptrs, sizeof ptrs);
@@ -212,7 +215,7 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
     const int eb = prec_elem_bytes(prec);
     const size_t vb = w.S * eb;
     const bool flexible = o.precond == 3;
-    const int Wt = w.Wt;
+    const int Wt = cols.W;      // Krylov columns (1 in the global mode)
     int* pinned_state = c->pinned_state(Wt);
     if (!pinned_state) return c->fail(MLFFT_E_NOMEM, "pinned host buffer");
     HIPCHK(hipMemsetAsync(w.dT, 0, vb, s), "zero d");
@@ -247,7 +250,7 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
                 HIPCHK(k_arnoldi<C>(w.Vb, q, cols, w.H, m, w.state, o.orth, s), "arnoldi");
                 c->prof_end(pr);
                 HIPCHK(k_givens(w.H, w.cs, w.sn, w.g, q, m, Wt, w.state, w.target, w.kcyc, w.iters, w.est,
-                                o.record_history ? w.hist : nullptr, info ? info->history_len : 0, w.rnorm, s),
+                                o.record_history ? w.hist : nullptr, info ? info->history_len : 0, w.kscale, s),
                        "givens");
                 return MLFFT_OK;
             };
@@ -325,16 +328,24 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     const int Wt = w.Wt;
     if (Wt == 0) return MLFFT_OK;
     const bool flexible = o.precond == 3;
+    // Krylov columns: one per right-hand side, or in the global mode (eq. ZIVvec)
+    // a single column made of all right-hand sides, with Frobenius inner products
+    const bool global = o.mode == 1;
+    if (global && S > (size_t)0x7fffffff) return c->fail(MLFFT_E_ARG, "global mode: more than 2^31-1 unknowns in all");
+    const int Wk = global ? 1 : Wt;
+    std::vector<size_t> hkoff = global ? std::vector<size_t>{0} : hoff;
+    std::vector<int> hkN = global ? std::vector<int>{(int)S} : hN;
     // carve the workspaces
     const size_t v64b = align_up(S * 16), vTb = align_up(S * eb);
     size_t big = 3 * v64b + 4 * vTb + (size_t)(m + 1) * vTb + (flexible ? (size_t)m * vTb : 0);
     const int hist_len = (info && o.record_history) ? info->history_len : 0;
     // Arnoldi chunks of every column and their partial-sum rows
-    std::vector<int> hchoff(Wt + 1, 0);
-    for (int i = 0; i < Wt; ++i) hchoff[i + 1] = hchoff[i] + arnoldi_chunks((size_t)hN[i]);
-    const int nch = hchoff[Wt];
+    std::vector<int> hchoff(Wk + 1, 0);
+    for (int i = 0; i < Wk; ++i) hchoff[i + 1] = hchoff[i] + arnoldi_chunks((size_t)hkN[i]);
+    const int nch = hchoff[Wk];
     const size_t partb = align_up((size_t)nch * (2 * m + 3) * sizeof(double));
-    size_t small = align_up((Wt + 1) * sizeof(int)) + 2 * partb + align_up(Wt * sizeof(size_t)) + 5 * align_up(Wt * sizeof(int)) +
+    size_t small = align_up((Wt + 1) * sizeof(int)) + 2 * partb + align_up(sizeof(size_t)) + align_up(sizeof(int)) +
+                   align_up(Wt * sizeof(double)) + align_up(Wt * sizeof(size_t)) + 5 * align_up(Wt * sizeof(int)) +
                    6 * align_up(Wt * sizeof(double)) + align_up((size_t)Wt * (m + 1) * m * 16) +
                    align_up((size_t)Wt * (m + 1) * 16) + 2 * align_up((size_t)Wt * m * 16) +
                    align_up((size_t)Wt * m * 8) + align_up((size_t)std::max(hist_len, 1) * Wt * 8);
@@ -354,6 +365,9 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     int* choff = (int*)q; q += align_up((Wt + 1) * sizeof(int));
     double* part1 = (double*)q; q += partb;
     double* part2 = (double*)q; q += partb;
+    size_t* gkoff = (size_t*)q; q += align_up(sizeof(size_t));
+    int* gkN = (int*)q; q += align_up(sizeof(int));
+    double* gscale = (double*)q; q += align_up(Wt * sizeof(double));
     w.coff = (size_t*)q; q += align_up(Wt * sizeof(size_t));
     w.cN = (int*)q; q += align_up(Wt * sizeof(int));
     w.state = (int*)q; q += align_up(Wt * sizeof(int));
@@ -374,11 +388,16 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     w.hist = (double*)q;
     (void)scratch_d;
     Cols cols{w.coff, w.cN, Wt, S, w.maxN};
-    cols.choff = choff;
-    cols.nch = nch;
-    cols.part1 = part1;
-    cols.part2 = part2;
-    HIPCHK(hipMemcpyAsync(choff, hchoff.data(), (Wt + 1) * sizeof(int), hipMemcpyHostToDevice, s), "columns");
+    Cols kc = global ? Cols{gkoff, gkN, 1, S, S} : cols;
+    kc.choff = choff;
+    kc.nch = nch;
+    kc.part1 = part1;
+    kc.part2 = part2;
+    HIPCHK(hipMemcpyAsync(choff, hchoff.data(), (Wk + 1) * sizeof(int), hipMemcpyHostToDevice, s), "columns");
+    if (global) {
+        HIPCHK(hipMemcpyAsync(gkoff, hkoff.data(), sizeof(size_t), hipMemcpyHostToDevice, s), "columns");
+        HIPCHK(hipMemcpyAsync(gkN, hkN.data(), sizeof(int), hipMemcpyHostToDevice, s), "columns");
+    }
     HIPCHK(hipMemcpyAsync(w.coff, hoff.data(), Wt * sizeof(size_t), hipMemcpyHostToDevice, s), "columns");
     HIPCHK(hipMemcpyAsync(w.cN, hN.data(), Wt * sizeof(int), hipMemcpyHostToDevice, s), "columns");
     HIPCHK(hipMemsetAsync(w.iters, 0, Wt * sizeof(int), s), "iters");
@@ -426,21 +445,38 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
             if (!done) outer_used[i] = outer + 1;
         }
         if (active == 0) { r_current = true; break; }
-        HIPCHK(hipMemcpyAsync(w.state, hstate.data(), Wt * sizeof(int), hipMemcpyHostToDevice, s), "state");
-        HIPCHK(hipMemcpyAsync(w.target, ht.data(), Wt * sizeof(double), hipMemcpyHostToDevice, s), "targets");
-        for (int i = 0; i < Wt; ++i) hstate[i] = hstate[i] == 0;
+        const double* scale = w.rnorm;
+        if (global) {
+            // one inner solve of Z D = R / ||R||_F over all columns, to the Frobenius target
+            double v2 = 0.0, r2 = 0.0;
+            for (int i = 0; i < Wt; ++i) { v2 += hv[i] * hv[i]; r2 += hr[i] * hr[i]; }
+            const double need = (prec == P64 ? 0.9 : 0.3) * o.tol * std::sqrt(v2 / r2);
+            ht[0] = prec == P64 ? need : std::max(inner_floor, need);
+            hstate[0] = 0;
+            std::vector<double> hg(Wt, std::sqrt(r2));
+            HIPCHK(hipMemcpyAsync(gscale, hg.data(), Wt * sizeof(double), hipMemcpyHostToDevice, s), "scale");
+            HIPCHK(hipStreamSynchronize(s), "scale");
+            scale = gscale;
+        }
+        w.kscale = scale;
+        HIPCHK(hipMemcpyAsync(w.state, hstate.data(), Wk * sizeof(int), hipMemcpyHostToDevice, s), "state");
+        HIPCHK(hipMemcpyAsync(w.target, ht.data(), Wk * sizeof(double), hipMemcpyHostToDevice, s), "targets");
+        HIPCHK(hipStreamSynchronize(s), "state");
+        // update mask: the columns that were solved (all of them in the global mode)
+        for (int i = 0; i < Wt; ++i) hstate[i] = global ? 1 : hstate[i] == 0;
         HIPCHK(hipMemcpyAsync(w.mask, hstate.data(), Wt * sizeof(int), hipMemcpyHostToDevice, s), "mask");
         if (prec == P64)
-            HIPCHK((k_scale_cols<double2, double2>(w.r64, w.rT, cols, w.rnorm, 1, s)), "scale r");
+            HIPCHK((k_scale_cols<double2, double2>(w.r64, w.rT, cols, scale, 1, s)), "scale r");
         else
-            HIPCHK((k_scale_cols<double2, float2>(w.r64, w.rT, cols, w.rnorm, 1, s)), "scale r");
-        mlfft_status st = prec == P64 ? inner_solve<double2>(c, segs, w, cols, o, prec, info, hstate)
-                                      : inner_solve<float2>(c, segs, w, cols, o, prec, info, hstate);
+            HIPCHK((k_scale_cols<double2, float2>(w.r64, w.rT, cols, scale, 1, s)), "scale r");
+        mlfft_status st = prec == P64 ? inner_solve<double2>(c, segs, w, kc, o, prec, info, hstate)
+                                      : inner_solve<float2>(c, segs, w, kc, o, prec, info, hstate);
         if (st < 0) return st;
         if (prec == P64)
-            HIPCHK(k_axpy_cols<double2>(w.x64, w.dT, cols, w.rnorm, w.mask, s), "update x");
+            HIPCHK(k_axpy_cols<double2>(w.x64, w.dT, cols, scale, w.mask, s), "update x");
         else
-            HIPCHK(k_axpy_cols<float2>(w.x64, w.dT, cols, w.rnorm, w.mask, s), "update x");
+            HIPCHK(k_axpy_cols<float2>(w.x64, w.dT, cols, scale, w.mask, s), "update x");
+        HIPCHK(hipStreamSynchronize(s), "update x");      // host vectors above are reused next step
     }
     // final true FP64 residual (already at hand when the loop stopped on convergence)
     if (!r_current) {
@@ -449,13 +485,13 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     }
     HIPCHK(k_colnorm<double2>(w.r64, cols, w.rnorm, s), "norms");
     HIPCHK(hipMemcpyAsync(hr.data(), w.rnorm, Wt * sizeof(double), hipMemcpyDeviceToHost, s), "norms");
-    std::vector<int> hit(Wt);
-    HIPCHK(hipMemcpyAsync(hit.data(), w.iters, Wt * sizeof(int), hipMemcpyDeviceToHost, s), "iters");
+    std::vector<int> hit(Wk);
+    HIPCHK(hipMemcpyAsync(hit.data(), w.iters, Wk * sizeof(int), hipMemcpyDeviceToHost, s), "iters");
     for (auto& sg : segs)
         HIPCHK(hipMemcpyAsync(sg.I, w.x64 + sg.off, sg.N * sg.W * 16, hipMemcpyDeviceToDevice, s), "scatter x");
     std::vector<double> hh;
     if (hist_len) {
-        hh.resize((size_t)hist_len * Wt);
+        hh.resize((size_t)hist_len * Wk);
         HIPCHK(hipMemcpyAsync(hh.data(), w.hist, hh.size() * 8, hipMemcpyDeviceToHost, s), "history");
     }
     HIPCHK(hipStreamSynchronize(s), "solve");
@@ -468,15 +504,21 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
         if (info) {
             if (info->relres) info->relres[i] = rr;
             if (info->converged) info->converged[i] = ok;
-            if (info->iters) info->iters[i] = hit[i];
+            if (info->iters) info->iters[i] = hit[global ? 0 : i];
             if (info->outer) info->outer[i] = outer_used[i];
         }
     }
     if (info && info->history && hist_len) {
-        // history[it][w]: residual estimate relative to ||V_w||
+        // history[it][w]: residual estimate relative to ||V_w|| (global mode: ||R||_F / ||V||_F
+        // for every column)
+        double v2 = 0.0;
+        for (int i = 0; i < Wt; ++i) v2 += hv[i] * hv[i];
         for (int it = 0; it < hist_len; ++it)
-            for (int i = 0; i < Wt; ++i)
-                info->history[(size_t)it * Wt + i] = hv[i] > 0.0 ? hh[(size_t)it * Wt + i] / hv[i] : 0.0;
+            for (int i = 0; i < Wt; ++i) {
+                const double e = hh[(size_t)it * Wk + (global ? 0 : i)];
+                const double d = global ? std::sqrt(v2) : hv[i];
+                info->history[(size_t)it * Wt + i] = d > 0.0 ? e / d : 0.0;
+            }
     }
     return all ? MLFFT_OK : MLFFT_NOT_CONVERGED;
 }

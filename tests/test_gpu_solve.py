@@ -241,3 +241,51 @@ def test_graph_batch_matches_eager_and_null_stream_runs_eagerly(ctx):
     Is, info = ctx.solve_batch(ids, Vs, tol=1e-10, inner_prec="fp32", precond=1, use_graph=1)
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(Is, Is0))
+
+
+@pytest.mark.parametrize("pc", [0, 1])
+def test_global_mode_matches_oracle_global_gmres(ctx, pc):
+    """mode = 1: one Krylov space for all port columns (eq. ZIVvec).  The FP64 residual history of
+    the first inner solve equals the oracle's global GMRES history; the solution matches LU."""
+    Nx, Ny, b = 5, 4, 6
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=2)
+    ctx.set_blocks(80, blocks)
+    V = synth.port_rhs(Nx, Ny, b)
+    I, info = ctx.solve(80, to_dev(V), tol=1e-10, inner_prec="fp64", precond=pc, mode=1, history_len=60)
+    assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-10)
+    mv = lambda X: tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)
+    pcf = None
+    if pc:
+        Sinv = precond.strang_inverse_spectrum(blocks)
+        pcf = lambda X: precond.strang_apply(Sinv, X)
+    ores = krylov.gmres_global(mv, V, pcf, tol=0.9e-10)
+    k = ores.iters
+    assert np.all(info["iters"] >= k)
+    np.testing.assert_allclose(info["history"][:k, 0], ores.history, rtol=1e-6)
+    assert np.all(info["history"][:k] == info["history"][:k, :1])      # one history for all columns
+    assert relerr(to_host(I), direct.lu_solve(tp.dense_Z(blocks), V)) <= 1e-8
+
+
+def test_global_mode_fp32_refined_batch_matches_lu(ctx):
+    shapes = [(6, 5, 24, np.pi), (4, 7, 16, 0.7 * np.pi)]
+    ids, Vs, refs = [], [], []
+    for i, (Nx, Ny, b, kd) in enumerate(shapes):
+        blocks = synth.green_blocks(Nx, Ny, b, kd, seed=1200 + i)
+        ctx.set_blocks(82 + i, blocks)
+        V = synth.port_rhs(Nx, Ny, b)
+        ids.append(82 + i)
+        Vs.append(to_dev(V))
+        refs.append(direct.lu_solve(tp.dense_Z(blocks), V))
+    Is, info = ctx.solve_batch(ids, Vs, tol=1e-9, inner_prec="fp32", precond=1, mode=1)
+    assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-9)
+    for I, ref in zip(Is, refs):
+        assert relerr(to_host(I), ref) <= 1e-7
+    assert len(set(info["iters"].tolist())) == 1
+
+
+def test_mode_rejects_unknown_value(ctx):
+    Nx, Ny, b = 3, 3, 4
+    ctx.set_blocks(84, synth.green_blocks(Nx, Ny, b, np.pi, seed=0))
+    with pytest.raises(abi.MlfftError) as e:
+        ctx.solve(84, to_dev(synth.port_rhs(Nx, Ny, b)), mode=2)
+    assert e.value.status == abi.MLFFT_E_ARG
