@@ -23,7 +23,10 @@ static GemmShape default_shape(int prec, int bp) {
 }
 
 GemmShape gemm_shape(int prec, int bp, int tag) {
-    if (tag) return GemmShape{8, prec == P64 ? 16 : prec == P32 ? 32 : 64, prec == P32 ? 2 : 0};
+    if (tag) {
+        if (prec == P64) return GemmShape{4, 16, 2};
+        return GemmShape{8, prec == P32 ? 32 : 64, prec == P32 ? 2 : 0};
+    }
     const GemmShape& o = g_shape_override[prec][bp / 8];
     return o.waves ? o : default_shape(prec, bp);
 }
@@ -50,7 +53,7 @@ static int bp_max_of(int prec, const GemmTask* tasks, int ntasks) {
 // multiple of the XCD count; the flat three-product kernel (m3 == 2) deals the
 // K * ceil(b/16) (frequency, slice) items to eight waves per workgroup
 static int task_blocks(const GemmTask& t, const GemmShape& sh) {
-    if (sh.m3 == 2) return (t.K * ((t.b + 15) / 16) + 7) / 8;
+    if (sh.m3 == 2) return (t.K * ((t.b + 15) / 16) + sh.waves - 1) / sh.waves;
     return ((t.K + kXcd - 1) / kXcd) * kXcd * t.mgroups;
 }
 
@@ -63,7 +66,9 @@ static GemmShape launch_shape(int prec, const GemmTask* tasks, int ntasks, int t
     if (sh.m3 == 2) {
         int bmin = 1 << 30;
         for (int i = 0; i < ntasks; ++i) bmin = std::min(bmin, tasks[i].b);
-        if ((bmin + 15) / 16 < 7) sh = GemmShape{8, 32, 1};
+        // waves - 1 consecutive slices must not reach a third frequency
+        if ((bmin + 15) / 16 < sh.waves - 1)
+            sh = prec == P32 ? GemmShape{8, 32, 1} : GemmShape{8, bpm > 128 ? 16 : 32, 0};
     }
     return sh;
 }

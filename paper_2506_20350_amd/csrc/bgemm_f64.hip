@@ -13,6 +13,15 @@ static hipError_t launch_real_cfg(const GemmTask& t0, const GemmTask* td, int n,
     return hipGetLastError();
 }
 
+template<int BP, int NT, int TAG = 0>
+static hipError_t launch_3m_flat_cfg(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
+    const size_t lds = (size_t)2 * NT * (2 * BP + 2) * sizeof(double);
+    auto k = bgemm_f64_3m_flat_kernel<BP, NT, TAG>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, t0, td, n);
+    return hipGetLastError();
+}
+
 // tag 1 (preconditioner) always uses one fixed shape, so its kernel symbol differs
 // from every shape the MLFFT product can take
 template<typename T, int BP>
@@ -28,10 +37,19 @@ static hipError_t launch_real(GemmShape sh, int tag, const GemmTask& t0, const G
                : launch_real_cfg<T, BP, NS, 8, 0>(t0, td, n, grid, s);
 }
 
+template<int BP>
+static hipError_t launch_f64(GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
+                             hipStream_t s) {
+    constexpr int B16 = (BP + 15) / 16 * 16;
+    if (sh.m3 == 2)
+        return tag ? launch_3m_flat_cfg<B16, 16, 1>(t0, td, n, grid, s) : launch_3m_flat_cfg<B16, 16>(t0, td, n, grid, s);
+    return launch_real<double, BP>(sh, tag, t0, td, n, grid, s);
+}
+
 hipError_t launch_bgemm_f64(int bp, GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
                             hipStream_t s) {
     switch (bp) {
-#define C64(B) case B: return launch_real<double, B>(sh, tag, t0, td, n, grid, s);
+#define C64(B) case B: return launch_f64<B>(sh, tag, t0, td, n, grid, s);
         MLFFT_BP8(C64)
 #undef C64
         default: return hipErrorInvalidValue;

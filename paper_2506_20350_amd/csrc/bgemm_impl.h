@@ -407,6 +407,125 @@ __global__ void __launch_bounds__(512) bgemm_f32_3m_flat_kernel(GemmTask t0, con
     }
 }
 
+// FP64 three-product form with the flat assignment, four waves per workgroup.
+// Same scheme as the FP32 kernel above with v_mfma_f64_16x16x4f64, whose
+// accumulator holds row 4r + l/16 of column l%16 in register r.  Four waves of
+// one slice each keep Gr and Gi (BP/2 doubles per lane) in registers, one wave
+// per SIMD; four consecutive slices span at most two frequencies when
+// ceil(b/16) >= 3.
+template<int BP, int NT, int TAG>
+__global__ void __launch_bounds__(256) bgemm_f64_3m_flat_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
+    constexpr int WAVES = 4, NTH = 64 * WAVES;
+    constexpr int PF = (NT * BP + NTH - 1) / NTH;
+    extern __shared__ unsigned char smem_raw[];
+    double* xs = reinterpret_cast<double*>(smem_raw);     // [panel][NT][ldx]
+    const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
+    const int b = t.b, W = t.W, K = t.K;
+    const int ns = (b + 15) >> 4;
+    const int total = K * ns;
+    const int nwg = (total + WAVES - 1) / WAVES;
+    const int local = blockIdx.x - t.block_begin;
+    const int per = nwg >> 3;
+    const int grp = local < per * 8 ? (local & 7) * per + (local >> 3) : local;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gs0 = grp * WAVES;
+    const int kA = gs0 / ns;
+    const int kB = min((gs0 + WAVES - 1) / ns, K - 1);
+    const int npan = kB != kA ? 2 : 1;
+    const int gs = gs0 + wave;
+    const bool active = gs < total;
+    const int kw = active ? gs / ns : kA;
+    const int m_base = (gs - kw * ns) * 16;
+    const int pan = kw - kA;
+    const int ldx = 2 * BP + 2;
+    double ar[BP / 4], ai[BP / 4];
+    {
+        const double2* __restrict__ Gk = static_cast<const double2*>(t.G) + (size_t)kw * t.gstride;
+        const int m = m_base + (lane & 15), kk = lane >> 4;
+#pragma unroll
+        for (int s = 0; s < BP / 4; ++s) {
+            const int n = 4 * s + kk;
+            double2 g = make_double2(0.0, 0.0);
+            if (active && m < b && n < b) g = Gk[(size_t)m * b + n];
+            ar[s] = g.x;
+            ai[s] = g.y;
+        }
+    }
+    const int padn = BP - b;
+    for (int e = threadIdx.x; e < 2 * NT * padn; e += NTH) {
+        const int pw = e / padn, n = b + (e - pw * padn);
+        xs[pw * ldx + 2 * n] = 0.0;
+        xs[pw * ldx + 2 * n + 1] = 0.0;
+    }
+    const int tile = NT * b;
+    const double2* __restrict__ Xa = static_cast<const double2*>(t.X) + (size_t)kA * W * b;
+    const double2* __restrict__ Xb = static_cast<const double2*>(t.X) + (size_t)kB * W * b;
+    double2* __restrict__ Yk = static_cast<double2*>(t.Y) + (size_t)kw * W * b;
+    const int j = lane & 15, q = lane >> 4;
+    double2 pre[2 * PF];
+    auto fetch = [&](int w0) {
+        const int have = min(NT, W - w0) * b;
+#pragma unroll
+        for (int i = 0; i < 2 * PF; ++i) {
+            const int e = threadIdx.x + (i % PF) * NTH;
+            const int p = i / PF;
+            const double2* __restrict__ src = (p ? Xb : Xa) + (size_t)w0 * b;
+            pre[i] = (p < npan && e < have) ? src[e] : make_double2(0.0, 0.0);
+        }
+    };
+    fetch(0);
+    for (int w0 = 0; w0 < W; w0 += NT) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2 * PF; ++i) {
+            const int e = threadIdx.x + (i % PF) * NTH;
+            const int p = i / PF;
+            if (p < npan && e < tile) {
+                const int w = e / b, n = e - w * b;
+                *reinterpret_cast<double2*>(&xs[(p * NT + w) * ldx + 2 * n]) = pre[i];
+            }
+        }
+        __syncthreads();
+        if (w0 + NT < W) fetch(w0 + NT);
+        if (active) {
+            const double* __restrict__ xp = xs + pan * NT * ldx;
+            doublex4 t1[NT / 16], t2[NT / 16], t3[NT / 16];
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) {
+                t1[cg] = doublex4{0, 0, 0, 0};
+                t2[cg] = doublex4{0, 0, 0, 0};
+                t3[cg] = doublex4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int s = 0; s < BP / 4; ++s) {
+                const double as = ar[s] + ai[s];
+#pragma unroll
+                for (int cg = 0; cg < NT / 16; ++cg) {
+                    const double2 u = *reinterpret_cast<const double2*>(&xp[(cg * 16 + j) * ldx + 2 * (4 * s + q)]);
+                    t1[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[s], u.x, t1[cg], 0, 0, 0);
+                    t2[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[s], u.y, t2[cg], 0, 0, 0);
+                    t3[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, u.x + u.y, t3[cg], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) {
+                const int w = w0 + cg * 16 + j;
+                if (w < W) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = m_base + 4 * r + q;
+                        if (m < b) {
+                            const double re = t1[cg][r] - t2[cg][r];
+                            const double im = t3[cg][r] - t1[cg][r] - t2[cg][r];
+                            Yk[(size_t)w * b + m] = make_double2(re, im);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ BF16
 
 __device__ __forceinline__ unsigned short bf16_rne(float f) { return f32_to_bf16_bits(f); }

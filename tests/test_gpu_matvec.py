@@ -192,3 +192,23 @@ def test_autotuned_shapes_keep_parity(ctx):
     R = synth.random_vectors(Nx * Ny * b, W, seed=9)
     z = ctx.precond_apply(51, to_dev(R, DT["fp32"]), kind=1, prec="fp32")
     assert relerr(to_host(z), opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)) <= 1e-4
+
+
+@pytest.mark.parametrize("b", [24, 120, 200, 13, 40])
+def test_fp64_flat_three_product_matches_oracle(ctx, b):
+    """The FP64 three-product block product with the flat (frequency, slice) assignment."""
+    Nx, Ny, W = 3, 4, 37
+    blocks = synth.random_blocks(Nx, Ny, b, seed=b + 1)
+    ctx.set_blocks(52, blocks)
+    bp = (b + 7) // 8 * 8
+    abi.mlfft_tune_import(ctx.h, f"gemm 0 {bp} 4 16 2\n")
+    try:
+        X = synth.random_vectors(Nx * Ny * b, W, seed=5)
+        y = ctx.matvec(52, to_dev(X), prec="fp64")
+        assert relerr(to_host(y), tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)) <= TOL["fp64"]
+        # the preconditioner product uses the same kernel (fixed shape)
+        R = synth.random_vectors(Nx * Ny * b, W, seed=6)
+        z = ctx.precond_apply(52, to_dev(R), kind=1, prec="fp64")
+        assert relerr(to_host(z), opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)) <= 1e-10
+    finally:
+        abi.mlfft_tune_import(ctx.h, f"gemm 0 {bp} 8 {16 if bp > 128 else 32} 0\n")
