@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_real_kernel(GemmTask t0, con
             const int n = 2 * s + (kk >> 1);
             T v = 0;
             if (active && m < b && n < b) {
-                const C g = Gk[(size_t)m * b + n];
+                const C g = gload(Gk + (size_t)m * b + n);
                 v = pr == 0 ? (pc == 0 ? g.x : -g.y) : (pc == 0 ? g.y : g.x);
             }
             a[s] = v;
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_real_kernel(GemmTask t0, con
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
             const int e = threadIdx.x + i * 64 * WAVES;
-            pre[i] = e < have ? src[e] : czero<C>();
+            pre[i] = e < have ? gload(src + e) : czero<C>();
         }
     };
     fetch(0);
@@ -169,8 +169,8 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_real_kernel(GemmTask t0, con
             for (int cg = 0; cg < NT / 16; ++cg) {
                 const int w = w0 + cg * 16 + j;
                 if (w < W) {
-                    if (m < b) Yk[(size_t)w * b + m] = cmake<C>(acc[cg][0], acc[cg][1]);
-                    if (m + 1 < b) Yk[(size_t)w * b + m + 1] = cmake<C>(acc[cg][2], acc[cg][3]);
+                    if (m < b) gstore(Yk + (size_t)w * b + m, cmake<C>(acc[cg][0], acc[cg][1]));
+                    if (m + 1 < b) gstore(Yk + (size_t)w * b + m + 1, cmake<C>(acc[cg][2], acc[cg][3]));
                 }
             }
         }
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_f32_3m_kernel(GemmTask t0, c
         for (int s = 0; s < BP / 4; ++s) {
             const int n = 4 * s + kk;
             float2 g = make_float2(0.f, 0.f);
-            if (active && m < b && n < b) g = Gk[(size_t)m * b + n];
+            if (active && m < b && n < b) g = gload(Gk + (size_t)m * b + n);
             ar[s] = g.x;
             ai[s] = g.y;
             as[s] = g.x + g.y;
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_f32_3m_kernel(GemmTask t0, c
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
             const int e = threadIdx.x + i * 64 * WAVES;
-            pre[i] = e < have ? src[e] : make_float2(0.f, 0.f);
+            pre[i] = e < have ? gload(src + e) : make_float2(0.f, 0.f);
         }
     };
     fetch(0);
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_f32_3m_kernel(GemmTask t0, c
                         if (m < b) {
                             const float re = t1[cg][r] - t2[cg][r];
                             const float im = t3[cg][r] - t1[cg][r] - t2[cg][r];
-                            Yk[(size_t)w * b + m] = make_float2(re, im);
+                            gstore(Yk + (size_t)w * b + m, make_float2(re, im));
                         }
                     }
                 }
@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(512) bgemm_f32_3m_flat_kernel(GemmTask t0, con
         for (int s = 0; s < BP / 4; ++s) {
             const int n = 4 * s + kk;
             float2 g = make_float2(0.f, 0.f);
-            if (active && m < b && n < b) g = Gk[(size_t)m * b + n];
+            if (active && m < b && n < b) g = gload(Gk + (size_t)m * b + n);
             ar[s] = g.x;
             ai[s] = g.y;
         }
@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(512) bgemm_f32_3m_flat_kernel(GemmTask t0, con
             const int e = threadIdx.x + (i % PF) * NTH;
             const int p = i / PF;
             const float2* __restrict__ src = (p ? Xb : Xa) + (size_t)w0 * b;
-            pre[i] = (p < npan && e < have) ? src[e] : make_float2(0.f, 0.f);
+            pre[i] = (p < npan && e < have) ? gload(src + e) : make_float2(0.f, 0.f);
         }
     };
     fetch(0);
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(512) bgemm_f32_3m_flat_kernel(GemmTask t0, con
                         if (m < b) {
                             const float re = t1[cg][r] - t2[cg][r];
                             const float im = t3[cg][r] - t1[cg][r] - t2[cg][r];
-                            Yk[(size_t)w * b + m] = make_float2(re, im);
+                            gstore(Yk + (size_t)w * b + m, make_float2(re, im));
                         }
                     }
                 }
@@ -446,7 +446,7 @@ __global__ void __launch_bounds__(256) bgemm_f64_3m_flat_kernel(GemmTask t0, con
         for (int s = 0; s < BP / 4; ++s) {
             const int n = 4 * s + kk;
             double2 g = make_double2(0.0, 0.0);
-            if (active && m < b && n < b) g = Gk[(size_t)m * b + n];
+            if (active && m < b && n < b) g = gload(Gk + (size_t)m * b + n);
             ar[s] = g.x;
             ai[s] = g.y;
         }
@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(256) bgemm_f64_3m_flat_kernel(GemmTask t0, con
             const int e = threadIdx.x + (i % PF) * NTH;
             const int p = i / PF;
             const double2* __restrict__ src = (p ? Xb : Xa) + (size_t)w0 * b;
-            pre[i] = (p < npan && e < have) ? src[e] : make_double2(0.0, 0.0);
+            pre[i] = (p < npan && e < have) ? gload(src + e) : make_double2(0.0, 0.0);
         }
     };
     fetch(0);
@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(256) bgemm_f64_3m_flat_kernel(GemmTask t0, con
                         if (m < b) {
                             const double re = t1[cg][r] - t2[cg][r];
                             const double im = t3[cg][r] - t1[cg][r] - t2[cg][r];
-                            Yk[(size_t)w * b + m] = make_double2(re, im);
+                            gstore(Yk + (size_t)w * b + m, make_double2(re, im));
                         }
                     }
                 }
@@ -559,7 +559,7 @@ __global__ void __launch_bounds__(512) bgemm_bf16_kernel(GemmTask t0, const Gemm
             for (int e = 0; e < 4; ++e) {
                 const int n = 16 * s + 4 * q + e;
                 uint32_t g = 0;
-                if (active && m < b && n < b) g = Gk[(size_t)m * b + n];
+                if (active && m < b && n < b) g = gload(Gk + (size_t)m * b + n);
                 const unsigned short gr = (unsigned short)(g & 0xffffu), gi = (unsigned short)(g >> 16);
                 if (pr == 0) { v[2 * e] = gr; v[2 * e + 1] = (unsigned short)(gi ^ 0x8000u); }
                 else         { v[2 * e] = gi; v[2 * e + 1] = gr; }
@@ -582,7 +582,7 @@ __global__ void __launch_bounds__(512) bgemm_bf16_kernel(GemmTask t0, const Gemm
         const int tot = NT * b, have = ncols * b;
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
             const int w = e / b, n = e - w * b;
-            const float2 v = e < have ? src[e] : make_float2(0.f, 0.f);
+            const float2 v = e < have ? gload(src + e) : make_float2(0.f, 0.f);
             const uint32_t packed = (uint32_t)bf16_rne(v.x) | ((uint32_t)bf16_rne(v.y) << 16);
             *reinterpret_cast<uint32_t*>(&xs[w * ldx + 2 * n]) = packed;
         }
@@ -605,8 +605,8 @@ __global__ void __launch_bounds__(512) bgemm_bf16_kernel(GemmTask t0, const Gemm
             for (int cg = 0; cg < NT / 16; ++cg) {
                 const int w = w0 + cg * 16 + j;
                 if (w < W) {
-                    if (m < b) Yk[(size_t)w * b + m] = make_float2(acc[cg][0], acc[cg][1]);
-                    if (m + 1 < b) Yk[(size_t)w * b + m + 1] = make_float2(acc[cg][2], acc[cg][3]);
+                    if (m < b) gstore(Yk + (size_t)w * b + m, make_float2(acc[cg][0], acc[cg][1]));
+                    if (m + 1 < b) gstore(Yk + (size_t)w * b + m + 1, make_float2(acc[cg][2], acc[cg][3]));
                 }
             }
         }

@@ -53,3 +53,23 @@ __host__ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) {
 }
 
 #define MLFFT_DEV_INLINE __device__ __forceinline__
+
+// Loads and stores through the global address space.  Pointers taken from task
+// tables are generic, for which the compiler emits flat memory instructions;
+// a flat load counts against the LDS wait counter as well, so every wait for
+// an LDS read would also wait for the global loads in flight (a prefetch of the
+// next tile, say).  These helpers make the access a global_load / global_store.
+#define MLFFT_GLOBAL __attribute__((address_space(1)))
+typedef float mlfft_f2v __attribute__((ext_vector_type(2)));
+typedef double mlfft_d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 gload(const float2* p) {
+    const mlfft_f2v v = *(const MLFFT_GLOBAL mlfft_f2v*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 gload(const double2* p) {
+    const mlfft_d2v v = *(const MLFFT_GLOBAL mlfft_d2v*)p;
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore(float2* p, float2 v) { *(MLFFT_GLOBAL mlfft_f2v*)p = mlfft_f2v{v.x, v.y}; }
+__device__ __forceinline__ void gstore(double2* p, double2 v) { *(MLFFT_GLOBAL mlfft_d2v*)p = mlfft_d2v{v.x, v.y}; }
+__device__ __forceinline__ uint32_t gload(const uint32_t* p) { return *(const MLFFT_GLOBAL uint32_t*)p; }
