@@ -293,12 +293,12 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_f32_3m_kernel(GemmTask t0, c
 // 13 slices for 16 wave slots).  A workgroup then spans at most two
 // frequencies and stages the X tiles of both; Gr + Gi is formed from the
 // register-resident Gr, Gi fragments at each reduction step.
-template<int BP, int NT, int TAG>
+template<int BP, int NT, int TAG, int DB>
 __global__ void __launch_bounds__(512) bgemm_f32_3m_flat_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
     constexpr int WAVES = 8, NTH = 64 * WAVES;
     constexpr int PF = (NT * BP + NTH - 1) / NTH;      // prefetched complex values per thread and panel
     extern __shared__ unsigned char smem_raw[];
-    float* xs = reinterpret_cast<float*>(smem_raw);     // [panel][NT][ldx]
+    float* xs = reinterpret_cast<float*>(smem_raw);     // [buffer][panel][NT][ldx]
     const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
     const int b = t.b, W = t.W, K = t.K;
     const int ns = (b + 15) >> 4;
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(512) bgemm_f32_3m_flat_kernel(GemmTask t0, con
         }
     }
     const int padn = BP - b;
-    for (int e = threadIdx.x; e < 2 * NT * padn; e += NTH) {
+    for (int e = threadIdx.x; e < (DB ? 4 : 2) * NT * padn; e += NTH) {
         const int pw = e / padn, n = b + (e - pw * padn);
         xs[pw * ldx + 2 * n] = 0.f;
         xs[pw * ldx + 2 * n + 1] = 0.f;
@@ -354,22 +354,37 @@ __global__ void __launch_bounds__(512) bgemm_f32_3m_flat_kernel(GemmTask t0, con
             pre[i] = (p < npan && e < have) ? gload(src + e) : make_float2(0.f, 0.f);
         }
     };
-    fetch(0);
-    for (int w0 = 0; w0 < W; w0 += NT) {
-        __syncthreads();
+    auto stage = [&](float* buf) {
 #pragma unroll
         for (int i = 0; i < 2 * PF; ++i) {
             const int e = threadIdx.x + (i % PF) * NTH;
             const int p = i / PF;
             if (p < npan && e < tile) {
                 const int w = e / b, n = e - w * b;
-                *reinterpret_cast<float2*>(&xs[(p * NT + w) * ldx + 2 * n]) = pre[i];
+                *reinterpret_cast<float2*>(&buf[(p * NT + w) * ldx + 2 * n]) = pre[i];
             }
         }
+    };
+    const int bufsz = 2 * NT * ldx;
+    fetch(0);
+    if (DB) {
+        // double buffering: tile t+1 is stored into the other buffer while tile t is
+        // multiplied, one barrier per tile
+        __syncthreads();                      // padding zeroed
+        stage(xs);
+        if (NT < W) fetch(NT);
         __syncthreads();
-        if (w0 + NT < W) fetch(w0 + NT);
+    }
+    for (int w0 = 0, it = 0; w0 < W; w0 += NT, ++it) {
+        const float* cur = xs + (DB ? (it & 1) * bufsz : 0);
+        if (!DB) {
+            __syncthreads();
+            stage(xs);
+            __syncthreads();
+            if (w0 + NT < W) fetch(w0 + NT);
+        }
         if (active) {
-            const float* __restrict__ xp = xs + pan * NT * ldx;
+            const float* __restrict__ xp = cur + pan * NT * ldx;
             floatx4 t1[NT / 16], t2[NT / 16], t3[NT / 16];
 #pragma unroll
             for (int cg = 0; cg < NT / 16; ++cg) {
@@ -403,6 +418,13 @@ __global__ void __launch_bounds__(512) bgemm_f32_3m_flat_kernel(GemmTask t0, con
                     }
                 }
             }
+        }
+        if (DB) {
+            if (w0 + NT < W) {
+                stage(xs + ((it + 1) & 1) * bufsz);
+                if (w0 + 2 * NT < W) fetch(w0 + 2 * NT);
+            }
+            __syncthreads();
         }
     }
 }

@@ -57,6 +57,7 @@ struct Work {
     int* cN;
     double *vnorm, *rnorm, *target, *est, *hist;
     const double* kscale;         // norm of each Krylov column's unscaled right-hand side
+    const int* seg_of = nullptr;  // host: array (segment) of each column, per-RHS mode only
     int *state, *kcyc, *iters, *mask;
     double2 *H, *g, *sn, *y;
     double* cs;
@@ -207,6 +208,24 @@ static mlfft_status graph_step(Ctx* c, const std::string& key, F&& step) {
     return MLFFT_OK;
 }
 
+// The arrays of a batch that still have an iterating column: the batched
+// products of a Krylov step skip the others (their columns are retired, and
+// the Arnoldi step leaves their slots at zero).  In the global mode there is
+// one Krylov column and every array takes part until it retires.
+static void active_segs(const std::vector<Seg>& segs, const Work& w, const int* state, int Wk,
+                        std::vector<Seg>& act) {
+    act.clear();
+    if (!w.seg_of || Wk == 1) {
+        act = segs;
+        return;
+    }
+    std::vector<char> on(segs.size(), 0);
+    for (int i = 0; i < Wk; ++i)
+        if (state[i] == 0) on[w.seg_of[i]] = 1;
+    for (size_t k = 0; k < segs.size(); ++k)
+        if (on[k]) act.push_back(segs[k]);
+}
+
 template<typename C>
 static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const Cols& cols, const mlfft_solve_opts& o,
                                 int prec, mlfft_solve_info* info, std::vector<int>& hstate) {
@@ -233,6 +252,8 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
         int running = 0;
         for (int i = 0; i < Wt; ++i) running += pinned_state[i] == 0;
         if (running == 0) break;
+        std::vector<Seg> act;
+        active_segs(segs, w, pinned_state, Wt, act);
         for (int j = 0; j < m;) {
             // one Krylov step: z_q = P^{-1} v_q, u = Z z_q, orthogonalise, rotate
             auto step = [&](int q) -> mlfft_status {
@@ -241,10 +262,10 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
                 const void* zsrc = vq;
                 if (o.precond) {
                     void* zdst = flexible ? (char*)w.Zb + (size_t)q * vb : w.tmp2T;
-                    STCHK(batch_precond(c, segs, o.precond, vq, zdst, w.tmpT, prec, nullptr, nullptr));
+                    STCHK(batch_precond(c, act, o.precond, vq, zdst, w.tmpT, prec, nullptr, nullptr));
                     zsrc = zdst;
                 }
-                STCHK(batch_matvec(c, segs, zsrc, vnext, nullptr, 1.0, 0.0, prec));
+                STCHK(batch_matvec(c, act, zsrc, vnext, nullptr, 1.0, 0.0, prec));
                 // algorithmic traffic of one step: (orth + 1) passes over the q+2 vectors, one write
                 const int pr = c->prof_begin(PK_ARNOLDI, prec, (double)eb * w.S * ((o.orth + 1) * (q + 2) + 1), 0);
                 HIPCHK(k_arnoldi<C>(w.Vb, q, cols, w.H, m, w.state, o.orth, s), "arnoldi");
@@ -265,13 +286,13 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
                 return MLFFT_OK;
             };
             if (o.use_graph) {
-                STCHK(graph_step(c, graph_key(c, segs, w, o, prec, j, info), steps));
+                STCHK(graph_step(c, graph_key(c, act, w, o, prec, j, info), steps));
             } else {
                 STCHK(steps());
             }
             if (info) {
                 if (o.precond) info->precond_applies += nstep;
-                if (flexible) info->net_applies += nstep * (int)segs.size();
+                if (flexible) info->net_applies += nstep * (int)act.size();
                 info->matvecs_inner += nstep;
             }
             j += nstep;
@@ -279,6 +300,7 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
             running = 0;
             for (int i = 0; i < Wt; ++i) running += pinned_state[i] == 0;
             if (running == 0) break;
+            active_segs(segs, w, pinned_state, Wt, act);
         }
         HIPCHK(k_lsq(w.H, w.g, w.y, w.kcyc, m, Wt, s), "least squares");
         if (flexible) {
@@ -389,6 +411,7 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     (void)scratch_d;
     Cols cols{w.coff, w.cN, Wt, S, w.maxN};
     Cols kc = global ? Cols{gkoff, gkN, 1, S, S} : cols;
+    w.seg_of = global ? nullptr : seg_of.data();
     kc.choff = choff;
     kc.nch = nch;
     kc.part1 = part1;
@@ -420,11 +443,15 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     // operator inexact at the 1e-3 level, so its solve is stopped at 1e-2.
     const double inner_floor = o.inner_tol > 0.0 ? o.inner_tol : (prec == PBF16 ? 1e-2 : 3e-7);
     bool r_current = false;     // r64 holds V - Z x64 for the current x64
+    // arrays whose x changed in the last inner solve; in the per-RHS mode the
+    // update is masked to the solved columns, so the residual of an array with
+    // no solved column is still current
+    std::vector<Seg> rsegs = segs;
     for (int outer = 0; outer < o.max_outer; ++outer) {
         if (outer == 0 && !o.x0_given) {
             HIPCHK(hipMemcpyAsync(w.r64, w.v64, S * 16, hipMemcpyDeviceToDevice, s), "r = V");
-        } else {
-            STCHK(batch_matvec(c, segs, w.x64, w.r64, w.v64, -1.0, 1.0, P64));
+        } else if (!rsegs.empty()) {
+            STCHK(batch_matvec(c, rsegs, w.x64, w.r64, w.v64, -1.0, 1.0, P64));
             if (info) info->matvecs64 += 1;
         }
         HIPCHK(k_colnorm<double2>(w.r64, cols, w.rnorm, s), "norms");
@@ -445,6 +472,8 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
             if (!done) outer_used[i] = outer + 1;
         }
         if (active == 0) { r_current = true; break; }
+        if (global) rsegs = segs;
+        else active_segs(segs, w, hstate.data(), Wt, rsegs);
         const double* scale = w.rnorm;
         if (global) {
             // one inner solve of Z D = R / ||R||_F over all columns, to the Frobenius target

@@ -158,7 +158,7 @@ def test_full_size_30x30_b120_sampled_columns(ctx, prec):
 
 
 @pytest.mark.parametrize("b", [8, 24, 120, 200, 13])
-@pytest.mark.parametrize("shape", ["4 32 1", "8 64 1", "4 64 0", "8 32 0", "8 32 2"])
+@pytest.mark.parametrize("shape", ["4 32 1", "8 64 1", "4 64 0", "8 32 0", "8 32 2", "8 16 2"])
 def test_block_product_shapes_match_oracle(ctx, b, shape):
     """Every launch shape the autotuner can pick, including the three-product FP32 form."""
     Nx, Ny, W = 3, 4, 70
@@ -212,3 +212,17 @@ def test_fp64_flat_three_product_matches_oracle(ctx, b):
         assert relerr(to_host(z), opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)) <= 1e-10
     finally:
         abi.mlfft_tune_import(ctx.h, f"gemm 0 {bp} 8 {16 if bp > 128 else 32} 0\n")
+
+
+def test_empty_and_overlapping_arguments(ctx):
+    Nx, Ny, b = 3, 3, 4
+    ctx.set_blocks(53, synth.green_blocks(Nx, Ny, b, np.pi, seed=0))
+    assert abi.mlfft_matvec(ctx.h, 53, 0, 0, 0, abi.MLFFT_FP64) == abi.MLFFT_OK
+    assert abi.mlfft_precond_apply(ctx.h, 53, 1, 0, 0, 0, abi.MLFFT_FP32) == abi.MLFFT_OK
+    x = to_dev(synth.random_vectors(Nx * Ny * b, 2, seed=1))
+    with pytest.raises(abi.MlfftError) as e:
+        abi.mlfft_matvec(ctx.h, 53, 2, x.data_ptr(), x.data_ptr() + 16, abi.MLFFT_FP64)
+    assert e.value.status == abi.MLFFT_E_ARG
+    with pytest.raises(abi.MlfftError) as e:
+        abi.mlfft_matvec(ctx.h, 53, 2, x.data_ptr(), x.data_ptr(), 7)
+    assert e.value.status == abi.MLFFT_E_ARG
