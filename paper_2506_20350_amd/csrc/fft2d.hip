@@ -357,6 +357,16 @@ void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block,
     *lds = l;
 }
 
+int fft_group_key(int prec, const FftTask& t) {
+    FftTask one = t;
+    int grid, block;
+    size_t lds;
+    plan_fft_tasks(prec, &one, 1, &grid, &block, &lds);
+    int bucket = 0;
+    while (((size_t)1 << bucket) < lds) ++bucket;
+    return std::max(len_class(t.Nx), len_class(t.Ny)) * 64 + bucket;
+}
+
 typedef void (*FftKernel)(FftTask, const FftTask*, int);
 
 template<typename C, int INV>

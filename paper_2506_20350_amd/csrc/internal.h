@@ -51,6 +51,8 @@ hipError_t launch_fft_inv(int prec, const FftTask* tasks_host, const FftTask* ta
 // fills cm / nmc / block_begin for a list of tasks; returns the total grid size and the
 // block size / dynamic LDS bytes the grouped launch needs
 void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block, size_t* lds);
+// key of the launch a task joins: its length class and its LDS tile size rounded up to a power of two
+int fft_group_key(int prec, const FftTask& t);
 
 // tag 0: MLFFT spectra, 1: preconditioner (separate kernel symbols for profilers)
 // tuned FFT m-chunk (basis functions per workgroup); cm <= 0 restores the default rule

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <vector>
 
 using namespace mlfft;
@@ -110,6 +111,12 @@ void Array::release() {
         if (e_ != hipSuccess) return c->hip_fail(e_, what);  \
     } while (0)
 
+#define STCHK(call)                                          \
+    do {                                                     \
+        mlfft_status s_ = (call);                            \
+        if (s_ < 0) return s_;                               \
+    } while (0)
+
 int prec_elem_bytes(int prec) { return prec == P64 ? 16 : 8; }
 
 // ------------------------------------------------------------------ matvec core
@@ -124,7 +131,7 @@ mlfft_status Ctx::upload_tasks(const void* host, size_t bytes, void** dev) {
         if (e.first == key) { *dev = e.second.p; return MLFFT_OK; }
     // a graph capture replays only launches whose tables are already resident
     if (capturing) return fail(MLFFT_E_STATE, "task table not resident during graph capture");
-    if (task_cache.size() >= 64) {
+    if (task_cache.size() >= 256) {
         HIPCHK(hipStreamSynchronize(stream), "task cache flush");
         task_cache.clear();
     }
@@ -133,6 +140,54 @@ mlfft_status Ctx::upload_tasks(const void* host, size_t bytes, void** dev) {
     HIPCHK(b.ensure(bytes), "task table");
     HIPCHK(hipMemcpy(b.p, host, bytes, hipMemcpyHostToDevice), "task table upload");
     *dev = b.p;
+    return MLFFT_OK;
+}
+
+// Block products of a group of arrays.  The kernels are instantiated for a
+// padded reduction length BP and run every task of a launch at the largest
+// one, so tasks are launched in groups of equal padded b: a small-b array is
+// never padded to the b of a larger one.
+mlfft_status Ctx::gemm_grouped(int prec, std::vector<GemmTask>& gm, int tag, const char* what) {
+    Ctx* c = this;
+    std::map<int, std::vector<GemmTask>> groups;
+    for (const GemmTask& g : gm) groups[gemm_bp(prec, g.b)].push_back(g);
+    for (auto& kv : groups) {
+        std::vector<GemmTask>& sub = kv.second;
+        const int n = (int)sub.size();
+        int grid, bpm;
+        plan_gemm_tasks(prec, sub.data(), n, tag, &grid, &bpm);
+        void* d = nullptr;
+        if (n > 1) {
+            mlfft_status st = upload_tasks(sub.data(), sizeof(GemmTask) * n, &d);
+            if (st != MLFFT_OK) return st;
+        }
+        HIPCHK(launch_bgemm(prec, sub.data(), (const GemmTask*)d, n, tag, stream), what);
+    }
+    return MLFFT_OK;
+}
+
+// 2-D FFTs of a group of arrays, one launch per (length class, LDS tile size):
+// a grouped launch runs the kernel of its largest length class and reserves
+// its largest tile for every workgroup, which would cost small arrays their
+// occupancy.
+mlfft_status Ctx::fft_grouped(int prec, std::vector<FftTask>& tasks, bool inverse, const char* what) {
+    Ctx* c = this;
+    std::map<int, std::vector<FftTask>> groups;
+    for (const FftTask& t : tasks) groups[fft_group_key(prec, t)].push_back(t);
+    for (auto& kv : groups) {
+        std::vector<FftTask>& sub = kv.second;
+        const int n = (int)sub.size();
+        int grid, block;
+        size_t lds;
+        plan_fft_tasks(prec, sub.data(), n, &grid, &block, &lds);
+        void* d = nullptr;
+        if (n > 1) {
+            mlfft_status st = upload_tasks(sub.data(), sizeof(FftTask) * n, &d);
+            if (st != MLFFT_OK) return st;
+        }
+        HIPCHK(inverse ? launch_fft_inv(prec, sub.data(), (const FftTask*)d, n, stream)
+                       : launch_fft_fwd(prec, sub.data(), (const FftTask*)d, n, stream), what);
+    }
     return MLFFT_OK;
 }
 
@@ -173,25 +228,6 @@ mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec) {
         u.Nx = a->Nx; u.Ny = a->Ny; u.b = a->b; u.W = it.W; u.pad = 1;
         iv[i] = u;
     }
-    int grid, block, gridg, bpm;
-    size_t lds;
-    plan_fft_tasks(prec, fw.data(), nt, &grid, &block, &lds);
-    plan_fft_tasks(prec, iv.data(), nt, &grid, &block, &lds);
-    plan_gemm_tasks(prec, gm.data(), nt, 0, &gridg, &bpm);
-    void* dfw = nullptr;
-    void* div = nullptr;
-    void* dgm = nullptr;
-    if (nt > 1) {
-        const size_t sf = sizeof(FftTask) * nt, sg = sizeof(GemmTask) * nt;
-        std::vector<char> blob(2 * sf + sg);
-        memcpy(blob.data(), fw.data(), sf);
-        memcpy(blob.data() + sf, iv.data(), sf);
-        memcpy(blob.data() + 2 * sf, gm.data(), sg);
-        void* d;
-        mlfft_status st = upload_tasks(blob.data(), blob.size(), &d);
-        if (st != MLFFT_OK) return st;
-        dfw = d; div = (char*)d + sf; dgm = (char*)d + 2 * sf;
-    }
     // algorithmic bytes / flops of the three launches (s: bytes per complex of the data, sg: of the spectra)
     double bf = 0, bg = 0, bi = 0, fl = 0;
     const double s = eb, sg = prec == P64 ? 16 : prec == P32 ? 8 : 4;
@@ -204,13 +240,13 @@ mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec) {
         fl += 8.0 * a->K * (double)a->b * a->b * items[i].W;
     }
     int pr = prof_begin(PK_FFT_FWD, prec, bf, 0);
-    HIPCHK(launch_fft_fwd(prec, fw.data(), (const FftTask*)dfw, nt, stream), "forward MLFFT launch");
+    STCHK(fft_grouped(prec, fw, false, "forward MLFFT launch"));
     prof_end(pr);
     pr = prof_begin(PK_GEMM, prec, bg, fl);
-    HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, 0, stream), "block product launch");
+    STCHK(gemm_grouped(prec, gm, 0, "block product launch"));
     prof_end(pr);
     pr = prof_begin(PK_FFT_INV, prec, bi, 0);
-    HIPCHK(launch_fft_inv(prec, iv.data(), (const FftTask*)div, nt, stream), "inverse MLFFT launch");
+    STCHK(fft_grouped(prec, iv, true, "inverse MLFFT launch"));
     prof_end(pr);
     return MLFFT_OK;
 }
@@ -233,15 +269,7 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
             g.X = it.x; g.Y = it.y; g.K = it.W; g.b = a->b; g.W = a->Nx * a->Ny; g.gstride = 0;
             gm[i] = g;
         }
-        int gridg, bpm;
-        plan_gemm_tasks(prec, gm.data(), nt, 1, &gridg, &bpm);
-        void* dgm = nullptr;
-        if (nt > 1) {
-            mlfft_status st = upload_tasks(gm.data(), sizeof(GemmTask) * nt, &dgm);
-            if (st != MLFFT_OK) return st;
-        }
-        HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, 1, stream), "self-block apply launch");
-        return MLFFT_OK;
+        return gemm_grouped(prec, gm, 1, "self-block apply launch");
     }
     size_t need = 0;
     std::vector<size_t> off(nt);
@@ -273,25 +301,6 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
         u.Nx = a->Nx; u.Ny = a->Ny; u.b = a->b; u.W = it.W; u.pad = 0;
         iv[i] = u;
     }
-    int grid, block, gridg, bpm;
-    size_t lds;
-    plan_fft_tasks(prec, fw.data(), nt, &grid, &block, &lds);
-    plan_fft_tasks(prec, iv.data(), nt, &grid, &block, &lds);
-    plan_gemm_tasks(prec, gm.data(), nt, 1, &gridg, &bpm);
-    void* dfw = nullptr;
-    void* div = nullptr;
-    void* dgm = nullptr;
-    if (nt > 1) {
-        const size_t sf = sizeof(FftTask) * nt, sg = sizeof(GemmTask) * nt;
-        std::vector<char> blob(2 * sf + sg);
-        memcpy(blob.data(), fw.data(), sf);
-        memcpy(blob.data() + sf, iv.data(), sf);
-        memcpy(blob.data() + 2 * sf, gm.data(), sg);
-        void* d;
-        mlfft_status st = upload_tasks(blob.data(), blob.size(), &d);
-        if (st != MLFFT_OK) return st;
-        dfw = d; div = (char*)d + sf; dgm = (char*)d + 2 * sf;
-    }
     double bf = 0, bg = 0, fl = 0;
     const double s = eb, sg = prec == P64 ? 16 : prec == P32 ? 8 : 4;
     for (int i = 0; i < nt; ++i) {
@@ -302,13 +311,13 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
         fl += 8.0 * a->Nx * a->Ny * (double)a->b * a->b * items[i].W;
     }
     int pr = prof_begin(PK_PC_FFT_FWD, prec, bf, 0);
-    HIPCHK(launch_fft_fwd(prec, fw.data(), (const FftTask*)dfw, nt, stream), "preconditioner FFT launch");
+    STCHK(fft_grouped(prec, fw, false, "preconditioner FFT launch"));
     prof_end(pr);
     pr = prof_begin(PK_PC_GEMM, prec, bg, fl);
-    HIPCHK(launch_bgemm(prec, gm.data(), (const GemmTask*)dgm, nt, 1, stream), "preconditioner product launch");
+    STCHK(gemm_grouped(prec, gm, 1, "preconditioner product launch"));
     prof_end(pr);
     pr = prof_begin(PK_PC_FFT_INV, prec, bf, 0);
-    HIPCHK(launch_fft_inv(prec, iv.data(), (const FftTask*)div, nt, stream), "preconditioner IFFT launch");
+    STCHK(fft_grouped(prec, iv, true, "preconditioner IFFT launch"));
     prof_end(pr);
     return MLFFT_OK;
 }

@@ -111,6 +111,8 @@ struct mlfft_ctx_s {
     mlfft_status hip_fail(hipError_t e, const char* what);
     mlfft::Array* find(int id);
     mlfft_status upload_tasks(const void* host, size_t bytes, void** dev);
+    mlfft_status gemm_grouped(int prec, std::vector<mlfft::GemmTask>& gm, int tag, const char* what);
+    mlfft_status fft_grouped(int prec, std::vector<mlfft::FftTask>& tasks, bool inverse, const char* what);
     mlfft_status matvec_group(const std::vector<mlfft::MatvecItem>& items, int prec);
     mlfft_status precond_group(const std::vector<mlfft::MatvecItem>& items, int kind, int prec);
     void release_workspaces() {
