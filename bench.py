@@ -189,6 +189,20 @@ def bench_batch(a, torch):
     form = a.form if a.form in ("fp32", "fp64", "bf16") else "fp32"
     opts = dict(FORMS[form])
     opts.pop("label")
+    tune_s = None
+    if not a.no_tune:
+        # the block-product shape is tuned per padded b: one representative array (the largest) per b
+        t0 = time.perf_counter()
+        rep = {}
+        for i, sp in enumerate(specs):
+            if sp["b"] not in rep or sp["Nx"] * sp["Ny"] > specs[rep[sp["b"]]]["Nx"] * specs[rep[sp["b"]]]["Ny"]:
+                rep[sp["b"]] = i
+        pmap = {"fp64": 0, "fp32": 1, "bf16": 2}
+        for b_, i in sorted(rep.items()):
+            for p in sorted({0, pmap[FORMS[form]["inner_prec"]]}):
+                abi.mlfft_autotune(ctx.h, i, specs[i]["Nx"] * specs[i]["Ny"], p, 2)
+        tune_s = time.perf_counter() - t0
+        log(f"[bench] autotune {tune_s:.1f} s for b in {sorted(rep)}")
 
     def run(opts):
         Is, info = ctx.solve_batch(ids, Vs, tol=a.tol, **opts)
@@ -239,7 +253,8 @@ def bench_batch(a, torch):
                                     avg_ms=round(dom["ms"] / dom["launches"], 4)),
                kernels=[dict(name=s["name"], prec=s["prec"], launches=s["launches"],
                              avg_ms=round(s["ms"] / s["launches"], 4)) for s in sorted(stats, key=lambda s: -s["ms"])],
-               setup_s=round(setup, 3), iters_mean=float(infos[-1]["iters"].mean()),
+               setup_s=round(setup, 3), tune_s=None if tune_s is None else round(tune_s, 2),
+               iters_mean=float(infos[-1]["iters"].mean()),
                max_relres=float(infos[-1]["relres"].max()),
                compare=[dict(form="fp64", value=round(int(np.sum(i64["relres"] <= a.tol)) / d64, 2),
                              ms_per_step=round(d64 * 1e3, 3)),

@@ -58,6 +58,7 @@ struct Work {
     double *vnorm, *rnorm, *target, *est, *hist;
     const double* kscale;         // norm of each Krylov column's unscaled right-hand side
     const int* seg_of = nullptr;  // host: array (segment) of each column, per-RHS mode only
+    const int* colN = nullptr;    // host: entries of each column
     int *state, *kcyc, *iters, *mask;
     double2 *H, *g, *sn, *y;
     double* cs;
@@ -254,6 +255,14 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
         if (running == 0) break;
         std::vector<Seg> act;
         active_segs(segs, w, pinned_state, Wt, act);
+        // entries of the iterating columns (for the algorithmic traffic of the profile)
+        auto running_elems = [&]() {
+            double e = 0.0;
+            if (w.colN)
+                for (int i = 0; i < Wt; ++i) e += pinned_state[i] == 0 ? (double)w.colN[i] : 0.0;
+            return e;
+        };
+        double run_elems = running_elems();
         for (int j = 0; j < m;) {
             // one Krylov step: z_q = P^{-1} v_q, u = Z z_q, orthogonalise, rotate
             auto step = [&](int q) -> mlfft_status {
@@ -266,8 +275,11 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
                     zsrc = zdst;
                 }
                 STCHK(batch_matvec(c, act, zsrc, vnext, nullptr, 1.0, 0.0, prec));
-                // algorithmic traffic of one step: (orth + 1) passes over the q+2 vectors, one write
-                const int pr = c->prof_begin(PK_ARNOLDI, prec, (double)eb * w.S * ((o.orth + 1) * (q + 2) + 1), 0);
+                // algorithmic traffic of one step: (orth + 1) passes over the q+2 vectors and one
+                // write for every iterating column, one write (the zeroed slot) for the others
+                const double iter_elems = Wt == 1 ? (double)w.S : run_elems;
+                const double bytes = (double)eb * (iter_elems * ((o.orth + 1) * (q + 2) + 1) + ((double)w.S - iter_elems));
+                const int pr = c->prof_begin(PK_ARNOLDI, prec, bytes, 0);
                 HIPCHK(k_arnoldi<C>(w.Vb, q, cols, w.H, m, w.state, o.orth, s), "arnoldi");
                 c->prof_end(pr);
                 HIPCHK(k_givens(w.H, w.cs, w.sn, w.g, q, m, Wt, w.state, w.target, w.kcyc, w.iters, w.est,
@@ -301,6 +313,7 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
             for (int i = 0; i < Wt; ++i) running += pinned_state[i] == 0;
             if (running == 0) break;
             active_segs(segs, w, pinned_state, Wt, act);
+            run_elems = running_elems();
         }
         HIPCHK(k_lsq(w.H, w.g, w.y, w.kcyc, m, Wt, s), "least squares");
         if (flexible) {
@@ -412,6 +425,7 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     Cols cols{w.coff, w.cN, Wt, S, w.maxN};
     Cols kc = global ? Cols{gkoff, gkN, 1, S, S} : cols;
     w.seg_of = global ? nullptr : seg_of.data();
+    w.colN = global ? nullptr : hN.data();
     kc.choff = choff;
     kc.nch = nch;
     kc.part1 = part1;
