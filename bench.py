@@ -52,10 +52,11 @@ FORMS = {
     "fp64": dict(inner_prec="fp64", precond=1, label="plain FP64 GMRES(30), block-circulant preconditioner"),
     "learned": dict(inner_prec="fp32", precond=3, label="FP32 inner flexible GMRES(30) with learned correction (validation-gated, block-circulant fallback) + FP64 refinement"),
     "learned_forced": dict(inner_prec="fp32", precond=3, label="FP32 inner flexible GMRES(30) with the learned correction forced on + FP64 refinement"),
+    "fp32_global": dict(inner_prec="fp32", precond=1, mode=1, label="FP32 inner global (vectorised) GMRES(30), one Krylov space for all ports, + FP64 refinement, block-circulant preconditioner"),
 }
 
 DTYPE = {"fp32": "f32+f64", "bf16": "bf16xf32+f64", "fp64": "f64", "learned": "f32+bf16+f64",
-         "learned_forced": "f32+bf16+f64"}
+         "learned_forced": "f32+bf16+f64", "fp32_global": "f32+f64"}
 GATED = {}   # form -> replacement options when the learned correction is gated off
 
 
@@ -333,7 +334,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="residual reduction asked of each FP32 inner solve (library default if omitted)")
-    ap.add_argument("--compare", default="fp64,fp32,learned_forced",
+    ap.add_argument("--compare", default="fp64,fp32,learned_forced,fp32_global",
                     help="comma-separated forms timed on the same GPU for comparison (or 'none')")
     ap.add_argument("--train-steps", type=int, default=400, help="Adam steps of the learned correction")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch shapes)")

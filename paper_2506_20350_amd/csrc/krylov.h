@@ -15,11 +15,14 @@ struct Cols {
     size_t maxN;
     // Arnoldi chunking: column w owns chunks choff[w] .. choff[w+1]-1 (device,
     // W+1 entries, arnoldi_chunks(N[w]) each), nch chunks in all; part1 / part2
-    // hold nch rows of 2m+3 doubles of partial sums (device)
+    // hold the per-chunk partial sums coefficient-major, (2m+3) x nch doubles,
+    // and hsum1 / hsum2 their per-column totals, W x (2m+3) doubles (device)
     const int* choff = nullptr;
     int nch = 0;
     double* part1 = nullptr;
     double* part2 = nullptr;
+    double* hsum1 = nullptr;
+    double* hsum2 = nullptr;
 };
 
 // chunks of kArnChunk entries one column of N entries is cut into by k_arnoldi

@@ -82,8 +82,7 @@ __global__ void __launch_bounds__(256) colnorm_kernel(const C* __restrict__ x, c
 //                  Vᴴu' and ||u'||² partials with u' = u - V h1 (u' is not stored)
 //   update         h = h1 + h2, beta² = ||u'||² - ||h2||², v_{j+1} = (u - V h) / beta
 // Every workgroup of a column reduces that column's partials itself, in the same
-// order, so the result does not depend on scheduling.  Partial rows have
-// `stride` doubles: 2 (j+1) for the coefficients, then the squared norm.
+// order, so the result does not depend on scheduling.
 constexpr int kArnT = 256;
 constexpr int kArnE = 32;
 constexpr int kArnChunk = kArnT * kArnE;
@@ -97,13 +96,28 @@ __device__ __forceinline__ int chunk_column(const int* __restrict__ choff, int W
     return lo;
 }
 
-// out[i] = sum over the column's chunks of part[chunk][i], i < cnt (fixed order)
-__device__ __forceinline__ void reduce_parts(const double* __restrict__ part, int c0, int nch, int stride, int cnt,
-                                             double* out) {
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+// hsum[w][i] = sum over the column's chunks of part[i][chunk], i < cnt, in a
+// fixed order (strided per-thread sums, then a fixed tree): one workgroup per
+// iterating column.  Partial sums are stored coefficient-major, part[i][chunk],
+// so this read is coalesced.
+__global__ void __launch_bounds__(256) arnoldi_reduce_kernel(const double* __restrict__ part, int nchT,
+                                                             const int* __restrict__ choff,
+                                                             const int* __restrict__ state, int stride, int cnt,
+                                                             double* __restrict__ hsum) {
+    __shared__ double red[4];
+    const int w = blockIdx.x;
+    if (state[w] != 0) return;
+    const int c0 = choff[w], nch = choff[w + 1] - c0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = 0; i < cnt; ++i) {
+        const double* __restrict__ row = part + (size_t)i * nchT + c0;
         double s = 0.0;
-        for (int q = 0; q < nch; ++q) s += part[(size_t)(c0 + q) * stride + i];
-        out[i] = s;
+        for (int q = threadIdx.x; q < nch; q += blockDim.x) s += row[q];
+        s = wave_sum(s);
+        if (lane == 0) red[wave] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) hsum[(size_t)w * stride + i] = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
     }
 }
 
@@ -112,21 +126,21 @@ __global__ void __launch_bounds__(256) arnoldi_dots_kernel(const C* __restrict__
                                                            const size_t* __restrict__ coff, const int* __restrict__ cN,
                                                            const int* __restrict__ choff, int W,
                                                            const int* __restrict__ state,
-                                                           const double* __restrict__ part1,
-                                                           double* __restrict__ out, int stride) {
+                                                           const double* __restrict__ hsum1,
+                                                           double* __restrict__ out, int nchT, int stride) {
     __shared__ double red[4 * 72];
     __shared__ double sh[2 * MAXJ + 1];
     __shared__ double h1[2 * MAXJ + 1];
     const int c = blockIdx.x;
     const int w = chunk_column(choff, W, c);
     if (state[w] != 0) return;
-    const int c0 = choff[w], nch = choff[w + 1] - c0;
+    const int c0 = choff[w];
     const size_t N = cN[w];
     const size_t n0 = (size_t)(c - c0) * kArnChunk;
     const C* __restrict__ V = Vb + coff[w];
     const C* __restrict__ u = Vb + (size_t)(j + 1) * vstride + coff[w];
     if (PASS == 2) {
-        reduce_parts(part1, c0, nch, stride, 2 * (j + 1), h1);
+        for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) h1[i] = hsum1[(size_t)w * stride + i];
         __syncthreads();
     }
     double vals[2 * MAXJ + 1];
@@ -158,9 +172,8 @@ __global__ void __launch_bounds__(256) arnoldi_dots_kernel(const C* __restrict__
         }
     }
     block_sum<2 * MAXJ + 1>(vals, 2 * (j + 1), red, sh);
-    double* o = out + (size_t)c * stride;
-    for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) o[i] = sh[i];
-    if (threadIdx.x == 0) o[2 * (j + 1)] = sh[2 * MAXJ];
+    for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) out[(size_t)i * nchT + c] = sh[i];
+    if (threadIdx.x == 0) out[(size_t)(2 * (j + 1)) * nchT + c] = sh[2 * MAXJ];
 }
 
 template<typename C, int MAXJ>
@@ -170,13 +183,13 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
                                                              const int* __restrict__ choff, int W,
                                                              double2* __restrict__ H, int m,
                                                              const int* __restrict__ state, int orth,
-                                                             const double* __restrict__ part1,
-                                                             const double* __restrict__ part2, int stride) {
+                                                             const double* __restrict__ hsum1,
+                                                             const double* __restrict__ hsum2, int stride) {
     __shared__ double h1[2 * MAXJ + 1];
     __shared__ double h2[2 * MAXJ + 1];
     const int c = blockIdx.x;
     const int w = chunk_column(choff, W, c);
-    const int c0 = choff[w], nch = choff[w + 1] - c0;
+    const int c0 = choff[w];
     const size_t N = cN[w];
     const size_t n0 = (size_t)(c - c0) * kArnChunk;
     const C* __restrict__ V = Vb + coff[w];
@@ -191,8 +204,10 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
         return;
     }
     const int cnt = 2 * (j + 1) + 1;
-    reduce_parts(part1, c0, nch, stride, cnt, h1);
-    if (orth == 2) reduce_parts(part2, c0, nch, stride, cnt, h2);
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        h1[i] = hsum1[(size_t)w * stride + i];
+        if (orth == 2) h2[i] = hsum2[(size_t)w * stride + i];
+    }
     __syncthreads();
     const double unorm2 = h1[2 * (j + 1)];
     double beta2;
@@ -286,41 +301,81 @@ __global__ void givens_kernel(double2* __restrict__ H, double* __restrict__ cs, 
 }
 
 // Start a cycle: beta = ||r_w||; columns at or below target become inactive;
-// v_0 = r / beta, g = (beta, 0, ...).
+// v_0 = r / beta, g = (beta, 0, ...).  Three launches over the Arnoldi chunks
+// (so one long column, as in the global mode, is spread over the whole chip):
+// partial sums of |r|^2 per chunk, one workgroup per column for beta and the
+// column state, then the scaling.
 template<typename C>
-__global__ void __launch_bounds__(256) cycle_start_kernel(const C* __restrict__ r, C* __restrict__ v0,
-                                                          const size_t* __restrict__ coff, const int* __restrict__ cN,
-                                                          double2* __restrict__ g, int m, int* __restrict__ state,
-                                                          const double* __restrict__ target, int* __restrict__ kcyc,
-                                                          double* __restrict__ est) {
+__global__ void __launch_bounds__(256) cycle_norm_kernel(const C* __restrict__ r, const size_t* __restrict__ coff,
+                                                         const int* __restrict__ cN, const int* __restrict__ choff,
+                                                         int W, const int* __restrict__ state,
+                                                         double* __restrict__ part, int nchT) {
     __shared__ double red[4 * 72];
     __shared__ double res[1];
-    const int w = blockIdx.x;
+    const int c = blockIdx.x;
+    const int w = chunk_column(choff, W, c);
+    if (state[w] == 2) return;
     const size_t N = cN[w];
-    C* vw = v0 + coff[w];
-    if (state[w] == 2) {
-        if (threadIdx.x == 0) kcyc[w] = 0;
-        for (size_t n = threadIdx.x; n < N; n += blockDim.x) vw[n] = narrow<C>(make_double2(0.0, 0.0));
-        return;
-    }
-    const C* rw = r + coff[w];
+    const size_t n0 = (size_t)(c - choff[w]) * kArnChunk;
+    const C* __restrict__ rw = r + coff[w];
     double s = 0.0;
-    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+    for (int k = 0; k < kArnE; ++k) {
+        const size_t n = n0 + (size_t)k * kArnT + threadIdx.x;
+        if (n >= N) break;
         const double2 v = Acc<C>::w(rw[n]);
         s = fma(v.x, v.x, fma(v.y, v.y, s));
     }
     block_sum<1>(&s, 0, red, res);
-    const double beta = sqrt(res[0]);
-    const bool done = !(beta > target[w]);
+    if (threadIdx.x == 0) part[c] = res[0];
+}
+
+__global__ void __launch_bounds__(256) cycle_state_kernel(const double* __restrict__ part,
+                                                          const int* __restrict__ choff, double2* __restrict__ g,
+                                                          int m, int* __restrict__ state,
+                                                          const double* __restrict__ target, int* __restrict__ kcyc,
+                                                          double* __restrict__ est, double* __restrict__ beta_out) {
+    __shared__ double red[4];
+    const int w = blockIdx.x;
+    if (state[w] == 2) {
+        if (threadIdx.x == 0) kcyc[w] = 0;
+        return;
+    }
+    const int c0 = choff[w], nch = choff[w + 1] - c0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nch; q += blockDim.x) s += part[c0 + q];
+    s = wave_sum(s);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
     if (threadIdx.x == 0) {
+        const double beta = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+        const bool done = !(beta > target[w]);
         est[w] = beta;
         kcyc[w] = 0;
         state[w] = done ? 2 : 0;
+        beta_out[w] = beta;
         for (int i = 0; i <= m; ++i) g[(size_t)w * (m + 1) + i] = make_double2(i == 0 ? beta : 0.0, 0.0);
     }
-    const double inv = done ? 0.0 : 1.0 / beta;
-    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
-        const double2 v = Acc<C>::w(rw[n]);
+}
+
+template<typename C>
+__global__ void __launch_bounds__(256) cycle_scale_kernel(const C* __restrict__ r, C* __restrict__ v0,
+                                                          const size_t* __restrict__ coff, const int* __restrict__ cN,
+                                                          const int* __restrict__ choff, int W,
+                                                          const int* __restrict__ state,
+                                                          const double* __restrict__ beta) {
+    const int c = blockIdx.x;
+    const int w = chunk_column(choff, W, c);
+    const size_t N = cN[w];
+    const size_t n0 = (size_t)(c - choff[w]) * kArnChunk;
+    const C* __restrict__ rw = r + coff[w];
+    C* __restrict__ vw = v0 + coff[w];
+    const bool off = state[w] == 2;
+    const double inv = off ? 0.0 : 1.0 / beta[w];
+    for (int k = 0; k < kArnE; ++k) {
+        const size_t n = n0 + (size_t)k * kArnT + threadIdx.x;
+        if (n >= N) break;
+        const double2 v = off ? make_double2(0.0, 0.0) : Acc<C>::w(rw[n]);
         vw[n] = narrow<C>(make_double2(v.x * inv, v.y * inv));
     }
 }
@@ -430,20 +485,27 @@ template<typename C, int MAXJ>
 static hipError_t arnoldi_t(C* Vb, int j, const Cols& c, double2* H, int m, const int* state, int orth,
                             hipStream_t s) {
     const int stride = 2 * m + 3;
+    const int cnt = 2 * (j + 1) + 1;
     const dim3 grid((unsigned)c.nch);
     hipLaunchKernelGGL((arnoldi_dots_kernel<C, MAXJ, 1>), grid, dim3(kArnT), 0, s, (const C*)Vb, j, c.S, c.off, c.N,
-                       c.choff, c.W, state, (const double*)nullptr, c.part1, stride);
-    if (orth == 2)
+                       c.choff, c.W, state, (const double*)nullptr, c.part1, c.nch, stride);
+    hipLaunchKernelGGL(arnoldi_reduce_kernel, dim3(c.W), dim3(256), 0, s, (const double*)c.part1, c.nch, c.choff,
+                       state, stride, cnt, c.hsum1);
+    if (orth == 2) {
         hipLaunchKernelGGL((arnoldi_dots_kernel<C, MAXJ, 2>), grid, dim3(kArnT), 0, s, (const C*)Vb, j, c.S, c.off,
-                           c.N, c.choff, c.W, state, (const double*)c.part1, c.part2, stride);
+                           c.N, c.choff, c.W, state, (const double*)c.hsum1, c.part2, c.nch, stride);
+        hipLaunchKernelGGL(arnoldi_reduce_kernel, dim3(c.W), dim3(256), 0, s, (const double*)c.part2, c.nch, c.choff,
+                           state, stride, cnt, c.hsum2);
+    }
     hipLaunchKernelGGL((arnoldi_update_kernel<C, MAXJ>), grid, dim3(kArnT), 0, s, Vb, j, c.S, c.off, c.N, c.choff,
-                       c.W, H, m, state, orth, (const double*)c.part1, (const double*)c.part2, stride);
+                       c.W, H, m, state, orth, (const double*)c.hsum1, (const double*)c.hsum2, stride);
     return hipGetLastError();
 }
 
 template<typename C>
 hipError_t k_arnoldi(void* Vb, int j, const Cols& c, double2* H, int m, const int* state, int orth, hipStream_t s) {
-    if (c.nch <= 0 || !c.choff || !c.part1 || (orth == 2 && !c.part2)) return hipErrorInvalidValue;
+    if (c.nch <= 0 || !c.choff || !c.part1 || !c.hsum1 || (orth == 2 && (!c.part2 || !c.hsum2)))
+        return hipErrorInvalidValue;
     if (j + 1 > m || m > 31) return hipErrorInvalidValue;
     const int need = j + 1;
     C* V = (C*)Vb;
@@ -465,8 +527,14 @@ hipError_t k_givens(double2* H, double* cs, double2* sn, double2* g, int j, int 
 template<typename C>
 hipError_t k_cycle_start(const void* r, void* v0, const Cols& c, double2* g, int m, int* state, const double* target,
                          int* kcyc, double* est, hipStream_t s) {
-    hipLaunchKernelGGL(cycle_start_kernel<C>, dim3(c.W), dim3(256), 0, s, (const C*)r, (C*)v0, c.off, c.N, g, m, state,
-                       target, kcyc, est);
+    if (c.nch <= 0 || !c.choff || !c.part1 || !c.hsum1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)c.nch);
+    hipLaunchKernelGGL(cycle_norm_kernel<C>, grid, dim3(kArnT), 0, s, (const C*)r, c.off, c.N, c.choff, c.W, state,
+                       c.part1, c.nch);
+    hipLaunchKernelGGL(cycle_state_kernel, dim3(c.W), dim3(256), 0, s, (const double*)c.part1, c.choff, g, m, state,
+                       target, kcyc, est, c.hsum1);
+    hipLaunchKernelGGL(cycle_scale_kernel<C>, grid, dim3(kArnT), 0, s, (const C*)r, (C*)v0, c.off, c.N, c.choff, c.W,
+                       (const int*)state, (const double*)c.hsum1);
     return hipGetLastError();
 }
 

@@ -130,61 +130,87 @@ __global__ void target_kernel(const float2* __restrict__ e, size_t N, int npix, 
 // out[n][p][co] = sum_{tap, ci} wt[co][tap][ci] * act[n][p + off(tap)][ci]
 // act: bf16 [nimg][H*Wd][cin]; wt: bf16 [cout][9][cin] (cin, cout multiples of 32);
 // OUT_BF16_RELU: out = bf16(relu(.)) with cout channels, else FP32.
-// Workgroup: 4 waves x 16 pixels, 64 output channels (4 groups of 16).
+// Workgroup: 4 waves x 64 pixels (4 groups of 16 per wave), 64 output channels (4 groups of 16).
 template<int OUT_BF16_RELU>
 __global__ void __launch_bounds__(256) conv3x3_fwd_kernel(const unsigned short* __restrict__ act,
                                                           const unsigned short* __restrict__ wt, void* __restrict__ out,
                                                           int nimg, int H, int Wd, int cin, int cout) {
+    // Each wave computes 4 x 16 pixels x 64 channels: per reduction step of 32
+    // it loads 4 activation and 4 weight fragments for 16 MFMAs.
+    constexpr int PG = 4;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int npix = H * Wd;
     const long M = (long)nimg * npix;
-    const long p = (long)blockIdx.x * 64 + wave * 16 + (lane & 15);
     const int kg = lane >> 4;                 // which 8 of the 32 reduction entries
     const int c0 = blockIdx.y * 64;
     const int ngroups = min(4, (cout - c0) >> 4);
-    int n = 0, i = 0, j = 0;
-    const bool prow = p < M;
-    if (prow) {
-        n = (int)(p / npix);
-        const int q = (int)(p - (long)n * npix);
-        i = q / Wd;
-        j = q - i * Wd;
-    }
-    floatx4 acc[4];
+    const long pbase = ((long)blockIdx.x * 4 + wave) * (16 * PG);
+    int n[PG], i[PG], j[PG];
+    bool prow[PG];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) acc[g] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int pg = 0; pg < PG; ++pg) {
+        const long p = pbase + pg * 16 + (lane & 15);
+        prow[pg] = p < M;
+        n[pg] = 0; i[pg] = 0; j[pg] = 0;
+        if (prow[pg]) {
+            n[pg] = (int)(p / npix);
+            const int q = (int)(p - (long)n[pg] * npix);
+            i[pg] = q / Wd;
+            j[pg] = q - i[pg] * Wd;
+        }
+    }
+    floatx4 acc[PG][4];
+#pragma unroll
+    for (int pg = 0; pg < PG; ++pg)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[pg][g] = floatx4{0.f, 0.f, 0.f, 0.f};
     const ushortx8 zero8 = ushortx8{0, 0, 0, 0, 0, 0, 0, 0};
     for (int tap = 0; tap < 9; ++tap) {
-        const int ii = i + tap / 3 - 1, jj = j + tap % 3 - 1;
-        const bool ok = prow && ii >= 0 && ii < H && jj >= 0 && jj < Wd;
-        const unsigned short* arow = act + ((size_t)n * npix + (size_t)(ok ? ii * Wd + jj : 0)) * cin + 8 * kg;
+        const unsigned short* arow[PG];
+        bool ok[PG];
+#pragma unroll
+        for (int pg = 0; pg < PG; ++pg) {
+            const int ii = i[pg] + tap / 3 - 1, jj = j[pg] + tap % 3 - 1;
+            ok[pg] = prow[pg] && ii >= 0 && ii < H && jj >= 0 && jj < Wd;
+            arow[pg] = act + ((size_t)n[pg] * npix + (size_t)(ok[pg] ? ii * Wd + jj : 0)) * cin + 8 * kg;
+        }
         for (int ci = 0; ci < cin; ci += 32) {
-            const ushortx8 av = ok ? *reinterpret_cast<const ushortx8*>(arow + ci) : zero8;
+            ushortx8 av[PG], bv[4];
+#pragma unroll
+            for (int pg = 0; pg < PG; ++pg) av[pg] = ok[pg] ? *reinterpret_cast<const ushortx8*>(arow[pg] + ci) : zero8;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                if (g < ngroups) {
-                    const int co = c0 + g * 16 + (lane & 15);
-                    const ushortx8 bv = *reinterpret_cast<const ushortx8*>(wt + ((size_t)co * 9 + tap) * cin + ci + 8 * kg);
-                    acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                                     __builtin_bit_cast(bf16x8, bv), acc[g], 0, 0, 0);
-                }
+                const int co = c0 + g * 16 + (lane & 15);
+                bv[g] = g < ngroups ? *reinterpret_cast<const ushortx8*>(wt + ((size_t)co * 9 + tap) * cin + ci + 8 * kg)
+                                    : zero8;
             }
+#pragma unroll
+            for (int pg = 0; pg < PG; ++pg)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    if (g < ngroups)
+                        acc[pg][g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av[pg]),
+                                                                             __builtin_bit_cast(bf16x8, bv[g]), acc[pg][g],
+                                                                             0, 0, 0);
         }
     }
     // lane holds rows 4*(lane/16)+r (pixels) of column lane%16 (channel) in each group
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        if (g >= ngroups) continue;
-        const int co = c0 + g * 16 + (lane & 15);
+    for (int pg = 0; pg < PG; ++pg) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const long pr = (long)blockIdx.x * 64 + wave * 16 + 4 * kg + r;
-            if (pr >= M) continue;
-            const float v = acc[g][r];
-            if (OUT_BF16_RELU) {
-                static_cast<unsigned short*>(out)[(size_t)pr * cout + co] = f32_to_bf16_bits(v > 0.f ? v : 0.f);
-            } else {
-                static_cast<float*>(out)[(size_t)pr * cout + co] = v;
+        for (int g = 0; g < 4; ++g) {
+            if (g >= ngroups) continue;
+            const int co = c0 + g * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long pr = pbase + pg * 16 + 4 * kg + r;
+                if (pr >= M) continue;
+                const float v = acc[pg][g][r];
+                if (OUT_BF16_RELU) {
+                    static_cast<unsigned short*>(out)[(size_t)pr * cout + co] = f32_to_bf16_bits(v > 0.f ? v : 0.f);
+                } else {
+                    static_cast<float*>(out)[(size_t)pr * cout + co] = v;
+                }
             }
         }
     }
@@ -392,7 +418,7 @@ hipError_t n_target(const float2* e, size_t N, int W, int npix, int b, int cpad,
 hipError_t n_conv_fwd(const unsigned short* act, const unsigned short* wt, void* out, int nimg, int H, int Wd,
                       int cin, int cout, int bf16_relu, hipStream_t s) {
     const long M = (long)nimg * H * Wd;
-    dim3 grid((unsigned)((M + 63) / 64), (unsigned)((cout + 63) / 64));
+    dim3 grid((unsigned)((M + 255) / 256), (unsigned)((cout + 63) / 64));
     if (bf16_relu)
         hipLaunchKernelGGL(conv3x3_fwd_kernel<1>, grid, dim3(256), 0, s, act, wt, out, nimg, H, Wd, cin, cout);
     else

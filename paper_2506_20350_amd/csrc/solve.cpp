@@ -379,7 +379,8 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     for (int i = 0; i < Wk; ++i) hchoff[i + 1] = hchoff[i] + arnoldi_chunks((size_t)hkN[i]);
     const int nch = hchoff[Wk];
     const size_t partb = align_up((size_t)nch * (2 * m + 3) * sizeof(double));
-    size_t small = align_up((Wt + 1) * sizeof(int)) + 2 * partb + align_up(sizeof(size_t)) + align_up(sizeof(int)) +
+    const size_t hsb = align_up((size_t)Wk * (2 * m + 3) * sizeof(double));
+    size_t small = align_up((Wt + 1) * sizeof(int)) + 2 * partb + 2 * hsb + align_up(sizeof(size_t)) + align_up(sizeof(int)) +
                    align_up(Wt * sizeof(double)) + align_up(Wt * sizeof(size_t)) + 5 * align_up(Wt * sizeof(int)) +
                    6 * align_up(Wt * sizeof(double)) + align_up((size_t)Wt * (m + 1) * m * 16) +
                    align_up((size_t)Wt * (m + 1) * 16) + 2 * align_up((size_t)Wt * m * 16) +
@@ -400,6 +401,8 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     int* choff = (int*)q; q += align_up((Wt + 1) * sizeof(int));
     double* part1 = (double*)q; q += partb;
     double* part2 = (double*)q; q += partb;
+    double* hsum1 = (double*)q; q += hsb;
+    double* hsum2 = (double*)q; q += hsb;
     size_t* gkoff = (size_t*)q; q += align_up(sizeof(size_t));
     int* gkN = (int*)q; q += align_up(sizeof(int));
     double* gscale = (double*)q; q += align_up(Wt * sizeof(double));
@@ -430,6 +433,8 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     kc.nch = nch;
     kc.part1 = part1;
     kc.part2 = part2;
+    kc.hsum1 = hsum1;
+    kc.hsum2 = hsum2;
     HIPCHK(hipMemcpyAsync(choff, hchoff.data(), (Wk + 1) * sizeof(int), hipMemcpyHostToDevice, s), "columns");
     if (global) {
         HIPCHK(hipMemcpyAsync(gkoff, hkoff.data(), sizeof(size_t), hipMemcpyHostToDevice, s), "columns");
