@@ -19,6 +19,7 @@ struct Cols {
     // and hsum1 / hsum2 their per-column totals, W x (2m+3) doubles (device)
     const int* choff = nullptr;
     int nch = 0;
+    int maxch = 0;              // largest number of chunks of one column
     double* part1 = nullptr;
     double* part2 = nullptr;
     double* hsum1 = nullptr;

@@ -96,6 +96,18 @@ __device__ __forceinline__ int chunk_column(const int* __restrict__ choff, int W
     return lo;
 }
 
+// out[i] = sum over the column's chunks of part[i][chunk], i < cnt, in a fixed
+// order, by the threads of one workgroup (used when columns have few chunks).
+__device__ __forceinline__ void reduce_parts(const double* __restrict__ part, int nchT, int c0, int nch, int cnt,
+                                             double* out) {
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const double* __restrict__ row = part + (size_t)i * nchT + c0;
+        double s = 0.0;
+        for (int q = 0; q < nch; ++q) s += row[q];
+        out[i] = s;
+    }
+}
+
 // hsum[w][i] = sum over the column's chunks of part[i][chunk], i < cnt, in a
 // fixed order (strided per-thread sums, then a fixed tree): one workgroup per
 // iterating column.  Partial sums are stored coefficient-major, part[i][chunk],
@@ -127,20 +139,23 @@ __global__ void __launch_bounds__(256) arnoldi_dots_kernel(const C* __restrict__
                                                            const int* __restrict__ choff, int W,
                                                            const int* __restrict__ state,
                                                            const double* __restrict__ hsum1,
-                                                           double* __restrict__ out, int nchT, int stride) {
+                                                           const double* __restrict__ part1,
+                                                           double* __restrict__ out, int nchT, int stride, int inl) {
     __shared__ double red[4 * 72];
     __shared__ double sh[2 * MAXJ + 1];
     __shared__ double h1[2 * MAXJ + 1];
     const int c = blockIdx.x;
     const int w = chunk_column(choff, W, c);
     if (state[w] != 0) return;
-    const int c0 = choff[w];
+    const int c0 = choff[w], nch = choff[w + 1] - c0;
     const size_t N = cN[w];
     const size_t n0 = (size_t)(c - c0) * kArnChunk;
     const C* __restrict__ V = Vb + coff[w];
     const C* __restrict__ u = Vb + (size_t)(j + 1) * vstride + coff[w];
     if (PASS == 2) {
-        for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) h1[i] = hsum1[(size_t)w * stride + i];
+        if (inl) reduce_parts(part1, nchT, c0, nch, 2 * (j + 1), h1);
+        else
+            for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) h1[i] = hsum1[(size_t)w * stride + i];
         __syncthreads();
     }
     double vals[2 * MAXJ + 1];
@@ -184,12 +199,15 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
                                                              double2* __restrict__ H, int m,
                                                              const int* __restrict__ state, int orth,
                                                              const double* __restrict__ hsum1,
-                                                             const double* __restrict__ hsum2, int stride) {
+                                                             const double* __restrict__ hsum2,
+                                                             const double* __restrict__ part1,
+                                                             const double* __restrict__ part2, int nchT, int stride,
+                                                             int inl) {
     __shared__ double h1[2 * MAXJ + 1];
     __shared__ double h2[2 * MAXJ + 1];
     const int c = blockIdx.x;
     const int w = chunk_column(choff, W, c);
-    const int c0 = choff[w];
+    const int c0 = choff[w], nch = choff[w + 1] - c0;
     const size_t N = cN[w];
     const size_t n0 = (size_t)(c - c0) * kArnChunk;
     const C* __restrict__ V = Vb + coff[w];
@@ -204,9 +222,14 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
         return;
     }
     const int cnt = 2 * (j + 1) + 1;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        h1[i] = hsum1[(size_t)w * stride + i];
-        if (orth == 2) h2[i] = hsum2[(size_t)w * stride + i];
+    if (inl) {
+        reduce_parts(part1, nchT, c0, nch, cnt, h1);
+        if (orth == 2) reduce_parts(part2, nchT, c0, nch, cnt, h2);
+    } else {
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+            h1[i] = hsum1[(size_t)w * stride + i];
+            if (orth == 2) h2[i] = hsum2[(size_t)w * stride + i];
+        }
     }
     __syncthreads();
     const double unorm2 = h1[2 * (j + 1)];
@@ -327,6 +350,47 @@ __global__ void __launch_bounds__(256) cycle_norm_kernel(const C* __restrict__ r
     }
     block_sum<1>(&s, 0, red, res);
     if (threadIdx.x == 0) part[c] = res[0];
+}
+
+// The three steps in one launch when every column is a single chunk (one
+// workgroup per column).
+template<typename C>
+__global__ void __launch_bounds__(256) cycle_start_small_kernel(const C* __restrict__ r, C* __restrict__ v0,
+                                                                const size_t* __restrict__ coff,
+                                                                const int* __restrict__ cN, double2* __restrict__ g,
+                                                                int m, int* __restrict__ state,
+                                                                const double* __restrict__ target,
+                                                                int* __restrict__ kcyc, double* __restrict__ est) {
+    __shared__ double red[4 * 72];
+    __shared__ double res[1];
+    const int w = blockIdx.x;
+    const size_t N = cN[w];
+    C* __restrict__ vw = v0 + coff[w];
+    if (state[w] == 2) {
+        if (threadIdx.x == 0) kcyc[w] = 0;
+        for (size_t n = threadIdx.x; n < N; n += blockDim.x) vw[n] = narrow<C>(make_double2(0.0, 0.0));
+        return;
+    }
+    const C* __restrict__ rw = r + coff[w];
+    double s = 0.0;
+    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+        const double2 v = Acc<C>::w(rw[n]);
+        s = fma(v.x, v.x, fma(v.y, v.y, s));
+    }
+    block_sum<1>(&s, 0, red, res);
+    const double beta = sqrt(res[0]);
+    const bool done = !(beta > target[w]);
+    if (threadIdx.x == 0) {
+        est[w] = beta;
+        kcyc[w] = 0;
+        state[w] = done ? 2 : 0;
+        for (int i = 0; i <= m; ++i) g[(size_t)w * (m + 1) + i] = make_double2(i == 0 ? beta : 0.0, 0.0);
+    }
+    const double inv = done ? 0.0 : 1.0 / beta;
+    for (size_t n = threadIdx.x; n < N; n += blockDim.x) {
+        const double2 v = Acc<C>::w(rw[n]);
+        vw[n] = narrow<C>(make_double2(v.x * inv, v.y * inv));
+    }
 }
 
 __global__ void __launch_bounds__(256) cycle_state_kernel(const double* __restrict__ part,
@@ -487,18 +551,26 @@ static hipError_t arnoldi_t(C* Vb, int j, const Cols& c, double2* H, int m, cons
     const int stride = 2 * m + 3;
     const int cnt = 2 * (j + 1) + 1;
     const dim3 grid((unsigned)c.nch);
+    // columns of a few chunks: every workgroup reduces its column's partials itself
+    // (no reduction launches); long columns: one reduction workgroup per column
+    const int inl = c.maxch <= 16 ? 1 : 0;
     hipLaunchKernelGGL((arnoldi_dots_kernel<C, MAXJ, 1>), grid, dim3(kArnT), 0, s, (const C*)Vb, j, c.S, c.off, c.N,
-                       c.choff, c.W, state, (const double*)nullptr, c.part1, c.nch, stride);
-    hipLaunchKernelGGL(arnoldi_reduce_kernel, dim3(c.W), dim3(256), 0, s, (const double*)c.part1, c.nch, c.choff,
-                       state, stride, cnt, c.hsum1);
+                       c.choff, c.W, state, (const double*)nullptr, (const double*)nullptr, c.part1, c.nch, stride,
+                       inl);
+    if (!inl)
+        hipLaunchKernelGGL(arnoldi_reduce_kernel, dim3(c.W), dim3(256), 0, s, (const double*)c.part1, c.nch, c.choff,
+                           state, stride, cnt, c.hsum1);
     if (orth == 2) {
         hipLaunchKernelGGL((arnoldi_dots_kernel<C, MAXJ, 2>), grid, dim3(kArnT), 0, s, (const C*)Vb, j, c.S, c.off,
-                           c.N, c.choff, c.W, state, (const double*)c.hsum1, c.part2, c.nch, stride);
-        hipLaunchKernelGGL(arnoldi_reduce_kernel, dim3(c.W), dim3(256), 0, s, (const double*)c.part2, c.nch, c.choff,
-                           state, stride, cnt, c.hsum2);
+                           c.N, c.choff, c.W, state, (const double*)c.hsum1, (const double*)c.part1, c.part2, c.nch,
+                           stride, inl);
+        if (!inl)
+            hipLaunchKernelGGL(arnoldi_reduce_kernel, dim3(c.W), dim3(256), 0, s, (const double*)c.part2, c.nch,
+                               c.choff, state, stride, cnt, c.hsum2);
     }
     hipLaunchKernelGGL((arnoldi_update_kernel<C, MAXJ>), grid, dim3(kArnT), 0, s, Vb, j, c.S, c.off, c.N, c.choff,
-                       c.W, H, m, state, orth, (const double*)c.hsum1, (const double*)c.hsum2, stride);
+                       c.W, H, m, state, orth, (const double*)c.hsum1, (const double*)c.hsum2,
+                       (const double*)c.part1, (const double*)c.part2, c.nch, stride, inl);
     return hipGetLastError();
 }
 
@@ -528,6 +600,11 @@ template<typename C>
 hipError_t k_cycle_start(const void* r, void* v0, const Cols& c, double2* g, int m, int* state, const double* target,
                          int* kcyc, double* est, hipStream_t s) {
     if (c.nch <= 0 || !c.choff || !c.part1 || !c.hsum1) return hipErrorInvalidValue;
+    if (c.maxch == 1) {
+        hipLaunchKernelGGL(cycle_start_small_kernel<C>, dim3(c.W), dim3(256), 0, s, (const C*)r, (C*)v0, c.off, c.N,
+                           g, m, state, target, kcyc, est);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)c.nch);
     hipLaunchKernelGGL(cycle_norm_kernel<C>, grid, dim3(kArnT), 0, s, (const C*)r, c.off, c.N, c.choff, c.W, state,
                        c.part1, c.nch);

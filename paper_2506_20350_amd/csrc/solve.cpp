@@ -431,6 +431,8 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     w.colN = global ? nullptr : hN.data();
     kc.choff = choff;
     kc.nch = nch;
+    kc.maxch = 0;
+    for (int i = 0; i < Wk; ++i) kc.maxch = std::max(kc.maxch, hchoff[i + 1] - hchoff[i]);
     kc.part1 = part1;
     kc.part2 = part2;
     kc.hsum1 = hsum1;

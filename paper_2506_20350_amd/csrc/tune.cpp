@@ -28,6 +28,10 @@ struct Timer {
 
 std::string g_report;
 
+// A later candidate replaces the current best only if it is faster by more than
+// this margin, so that timing noise does not flip the choice between runs.
+const double kTuneMargin = 0.98;
+
 }  // namespace
 
 // time `reps` runs of fn (after one warm-up run); returns mean ms or a negative value on error
@@ -89,7 +93,7 @@ mlfft_status mlfft_autotune(mlfft_ctx ctx, int array_id, int W, int prec, int re
                 snprintf(line, sizeof line, "block_gemm prec=%d b=%d K=%d W=%d waves=%d nt=%d m3=%d: %.4f ms\n", prec,
                          a->b, a->K, W, waves, nt, m3, ms);
                 rep += line;
-                if (ms > 0 && ms < best) { best = ms; bw = waves; bn = nt; bm = m3; }
+                if (ms > 0 && ms < kTuneMargin * best) { best = ms; bw = waves; bn = nt; bm = m3; }
             }
         }
         if (bw) gemm_set_shape(prec, bp, bw, bn, bm);
@@ -118,7 +122,7 @@ mlfft_status mlfft_autotune(mlfft_ctx ctx, int array_id, int W, int prec, int re
             snprintf(line, sizeof line, "fft pair prec=%d pad=%d Nx=%d Ny=%d b=%d W=%d cm=%d: %.4f ms\n", fprec, pad,
                      a->Nx, a->Ny, a->b, W, cm, ms);
             rep += line;
-            if (ms > 0 && ms < bestms) { bestms = ms; bestcm = cm; }
+            if (ms > 0 && ms < kTuneMargin * bestms) { bestms = ms; bestcm = cm; }
         }
         fft_set_cm(fprec, pad, a->Nx, a->Ny, a->b, bestcm);
     }
