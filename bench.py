@@ -110,6 +110,27 @@ def roofline_of(stats):
                      frac=round(ach / PEAK_HBM_GBS, 4), traffic=None)
 
 
+def matvec_fraction(stats, prec):
+    """The MLFFT matvec (forward FFT, block product, inverse FFT) of one precision against its roofline.
+
+    Each phase's roofline time is its algorithmic bytes at the HBM peak or its
+    flops at the MFMA peak of its precision, whichever is longer; the fraction
+    is their sum over the measured time of the three phases (per launch).
+    """
+    ph = {s["name"]: s for s in stats if s["prec"] == prec and s["name"] in ("mlfft_fwd_fft", "block_gemm", "mlfft_inv_fft")}
+    if len(ph) != 3:
+        return None
+    meas = sum(s["ms"] / s["launches"] for s in ph.values())
+    roof = 0.0
+    for s in ph.values():
+        t_mem = s["bytes"] / s["launches"] / (PEAK_HBM_GBS * 1e9) * 1e3
+        t_fl = s["flops"] / s["launches"] / (PEAK_MFMA_TFLOPS[prec] * 1e12) * 1e3
+        roof += max(t_mem, t_fl)
+    return dict(prec={0: "fp64", 1: "fp32", 2: "bf16"}[prec], ms=round(meas, 3), roofline_ms=round(roof, 3),
+                frac=round(roof / meas, 4),
+                phases={n: round(s["ms"] / s["launches"], 3) for n, s in ph.items()})
+
+
 def traffic_record(group, prec, workload, tune_text):
     """HBM bytes per launch of a kernel group from a committed rocprofv3 counter record, or None.
 
@@ -425,6 +446,7 @@ def main():
                                     algorithmic_bytes=dom["bytes"] / dom["launches"],
                                     algorithmic_flops=dom["flops"] / dom["launches"]),
                kernels=kernels, setup_s=round(setup_s, 3), tune_s=None if tune_s is None else round(tune_s, 2),
+               matvec=[m for m in (matvec_fraction(stats, 1), matvec_fraction(stats, 0)) if m],
                iters_mean=float(last["iters"].mean()), outer_max=int(last["outer"].max()),
                max_relres=float(last["relres"].max()), converged_per_step=conv)
     if train_info is not None:
