@@ -9,9 +9,10 @@ Output: a header with, for each length n and direction s (-1 forward,
         static void tw2(C* v);   // v[j] <- v[j] * exp(s 2 pi i j / (2n))
     };
 
-Composite lengths use mixed-radix decimation in time (radix 4 first, then
-the smallest prime factor); prime lengths use the direct DFT written with
-the conjugate-pair symmetry x_j +- x_{p-j}.  Twiddles are literal double
+Lengths with coprime factors use the prime-factor (Good-Thomas) algorithm,
+which needs no twiddle factors (30 = 2 x 15 = 2 x 3 x 5); prime powers use
+mixed-radix decimation in time (radix 4 first, then the prime); prime lengths
+use the direct DFT written with the conjugate-pair symmetry x_j +- x_{p-j}.  Twiddles are literal double
 constants (17 significant digits) cast to the element type, so single and
 double precision codelets share one source.  The arrays are indexed only with
 constants, which keeps them in registers after inlining.
@@ -126,10 +127,33 @@ def smallest_factor(n):
     return n
 
 
+def coprime_split(n):
+    """n = a * b with gcd(a, b) = 1 and a, b > 1 (a the power of the smallest prime), or None."""
+    p = next(q for q in range(2, n + 1) if n % q == 0)
+    a, m = 1, n
+    while m % p == 0:
+        a, m = a * p, m // p
+    return (a, m) if m > 1 else None
+
+
 def fft(e, x, s):
     n = len(x)
     if n <= 2 or n == 4:
         return small_dft(e, x, s)
+    sp = coprime_split(n)
+    if sp:
+        # Good-Thomas prime-factor algorithm: with the input map n = (b n1 + a n2) mod N and
+        # the output map k = (k1 b (b^-1 mod a) + k2 a (a^-1 mod b)) mod N, the N-point DFT is an
+        # a x b two-dimensional DFT without twiddle factors.
+        a, b = sp
+        cols = [fft(e, [x[(b * n1 + a * n2) % n] for n1 in range(a)], s) for n2 in range(b)]
+        ainv, binv = pow(a, -1, b), pow(b, -1, a)
+        out = [None] * n
+        for k1 in range(a):
+            y = fft(e, [cols[n2][k1] for n2 in range(b)], s)
+            for k2 in range(b):
+                out[(k1 * b * binv + k2 * a * ainv) % n] = y[k2]
+        return out
     r = smallest_factor(n)
     if r == n:
         return small_dft(e, x, s)
