@@ -59,6 +59,7 @@ struct Work {
     const double* kscale;         // norm of each Krylov column's unscaled right-hand side
     const int* seg_of = nullptr;  // host: array (segment) of each column, per-RHS mode only
     const int* colN = nullptr;    // host: entries of each column
+    bool zstore = false;          // Zb holds the preconditioned directions
     int *state, *kcyc, *iters, *mask;
     double2 *H, *g, *sn, *y;
     double* cs;
@@ -270,7 +271,7 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
                 void* vnext = (char*)w.Vb + (size_t)(q + 1) * vb;
                 const void* zsrc = vq;
                 if (o.precond) {
-                    void* zdst = flexible ? (char*)w.Zb + (size_t)q * vb : w.tmp2T;
+                    void* zdst = w.zstore ? (char*)w.Zb + (size_t)q * vb : w.tmp2T;
                     STCHK(batch_precond(c, act, o.precond, vq, zdst, w.tmpT, prec, nullptr, nullptr));
                     zsrc = zdst;
                 }
@@ -316,7 +317,7 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
             run_elems = running_elems();
         }
         HIPCHK(k_lsq(w.H, w.g, w.y, w.kcyc, m, Wt, s), "least squares");
-        if (flexible) {
+        if (w.zstore) {
             HIPCHK(k_combine<C>(w.Zb, cols, w.y, w.kcyc, m, w.dT, 1, s), "update");
         } else if (o.precond) {
             HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, w.tmpT, 0, s), "update");
@@ -372,7 +373,12 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     std::vector<int> hkN = global ? std::vector<int>{(int)S} : hN;
     // carve the workspaces
     const size_t v64b = align_up(S * 16), vTb = align_up(S * eb);
-    size_t big = 3 * v64b + 4 * vTb + (size_t)(m + 1) * vTb + (flexible ? (size_t)m * vTb : 0);
+    // Preconditioned directions z_j = P^{-1} v_j are kept (m more vectors) when the
+    // solve is flexible, and also with a fixed preconditioner when the memory is
+    // there: x = Z y then replaces x = P^{-1} (V y), one preconditioner apply less
+    // per cycle.  Without the memory the fixed preconditioner is applied to V y.
+    const size_t big0 = 3 * v64b + 4 * vTb + (size_t)(m + 1) * vTb;
+    const size_t bigz = big0 + (size_t)m * vTb;
     const int hist_len = (info && o.record_history) ? info->history_len : 0;
     // Arnoldi chunks of every column and their partial-sum rows
     std::vector<int> hchoff(Wk + 1, 0);
@@ -385,7 +391,16 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
                    6 * align_up(Wt * sizeof(double)) + align_up((size_t)Wt * (m + 1) * m * 16) +
                    align_up((size_t)Wt * (m + 1) * 16) + 2 * align_up((size_t)Wt * m * 16) +
                    align_up((size_t)Wt * m * 8) + align_up((size_t)std::max(hist_len, 1) * Wt * 8);
-    HIPCHK(c->solve_ws.ensure(big), "Krylov workspace");
+    bool zstore = flexible;
+    if (flexible) {
+        HIPCHK(c->solve_ws.ensure(bigz), "Krylov workspace");
+    } else if (o.precond && c->solve_ws.ensure(bigz) == hipSuccess) {
+        zstore = true;
+    } else {
+        (void)hipGetLastError();
+        HIPCHK(c->solve_ws.ensure(big0), "Krylov workspace");
+    }
+    w.zstore = zstore;
     HIPCHK(c->solve_ws2.ensure(small), "Krylov workspace");
     char* p = (char*)c->solve_ws.p;
     w.v64 = (double2*)p; p += v64b;
@@ -396,7 +411,7 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     w.tmpT = p; p += vTb;
     w.tmp2T = p; p += vTb;
     w.Vb = p; p += (size_t)(m + 1) * vTb;
-    w.Zb = flexible ? (void*)p : nullptr;
+    w.Zb = zstore ? (void*)p : nullptr;
     char* q = (char*)c->solve_ws2.p;
     int* choff = (int*)q; q += align_up((Wt + 1) * sizeof(int));
     double* part1 = (double*)q; q += partb;

@@ -289,3 +289,28 @@ def test_mode_rejects_unknown_value(ctx):
     with pytest.raises(abi.MlfftError) as e:
         ctx.solve(84, to_dev(synth.port_rhs(Nx, Ny, b)), mode=2)
     assert e.value.status == abi.MLFFT_E_ARG
+
+
+def test_full_size_30x30_b200_autotuned_sampled_columns(ctx):
+    """The benchmark configuration: 30x30 array, b = 200, all 900 ports, autotuned launch shapes,
+    FP32 inner + FP64 refinement to the metric's 1e-6; one column checked against the oracle's
+    FP64 GMRES solution at 1e-12 (the oracle needs about a minute of CPU here), and the matvec of
+    the same launch shape on two sampled columns."""
+    Nx = Ny = 30
+    b = 200
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0)
+    ctx.set_blocks(18, blocks)
+    for prec in (0, 1):
+        abi.mlfft_autotune(ctx.h, 18, Nx * Ny, prec, 1)
+    V = synth.port_rhs(Nx, Ny, b)
+    I, info = ctx.solve(18, to_dev(V), tol=1e-6, inner_prec="fp32", precond=1)
+    assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-6)
+    cols = [0, 437]
+    Gh = tp.spectra(blocks, 2 * Ny, 2 * Nx)
+    mv = lambda X: tp.matvec_spectral(Gh, X, Nx, Ny)
+    Sinv = precond.strang_inverse_spectrum(blocks)
+    ref = krylov.gmres_columns(mv, V[cols[1:]], lambda X: precond.strang_apply(Sinv, X), tol=1e-12)[0].x
+    assert relerr(to_host(I)[cols[1]], ref) <= 2e-6       # relres <= 1e-6 and cond(Z) ~ 1.5
+    # the same tuned block-product shape in a plain FP32 matvec, sampled columns against the oracle
+    y = to_host(ctx.matvec(18, to_dev(V, torch.complex64), prec="fp32"))
+    assert relerr(y[cols], mv(V[cols])) <= 1e-5
