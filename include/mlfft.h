@@ -189,7 +189,10 @@ mlfft_status mlfft_solve_default_opts(mlfft_solve_opts* opts);
  * vector layout.  opts == NULL uses the defaults; info may be NULL.
  * Blocking: returns when every column converged (MLFFT_OK) or the limits are
  * reached (MLFFT_NOT_CONVERGED, outputs valid).  Zero columns of V give zero
- * columns of I.  Non-finite residuals: MLFFT_E_ARG. */
+ * columns of I.  Non-finite residuals: MLFFT_E_ARG.  When V and I do not overlap
+ * the solve reads V and builds the solution in I directly (no staging copies), so
+ * after an error return I is unspecified; overlapping V and I (also V == I) are
+ * staged through the workspace. */
 mlfft_status mlfft_solve(mlfft_ctx ctx, int array_id, int W, const void* V, void* I,
                          const mlfft_solve_opts* opts, mlfft_solve_info* info);
 
@@ -197,7 +200,10 @@ mlfft_status mlfft_solve(mlfft_ctx ctx, int array_id, int W, const void* V, void
  * product, preconditioner apply and Krylov step of the solve covers all arrays
  * in one grouped launch.  V[i], I[i]: device, complex128, W[i] columns of array
  * array_ids[i] (ids distinct).  info: NULL or one struct for the whole batch whose
- * per-column arrays are indexed by the concatenated column order. */
+ * per-column arrays are indexed by the concatenated column order.  The solve works
+ * in V and I directly when the V[i] lie back to back in batch order in one range,
+ * the I[i] likewise, and the two ranges do not overlap; otherwise V and I are
+ * staged through the workspace. */
 mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids, const int* W,
                                const void* const* V, void* const* I,
                                const mlfft_solve_opts* opts, mlfft_solve_info* info);

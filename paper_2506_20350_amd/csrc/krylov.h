@@ -43,7 +43,9 @@ template<typename C> hipError_t k_combine(const void* B, const Cols& c, const do
 template<typename C> hipError_t k_add_cols(void* dst, const void* src, const Cols& c, hipStream_t s);
 template<typename A, typename B> hipError_t k_scale_cols(const void* src, void* dst, const Cols& c, const double* sc,
                                                          int invert, hipStream_t s);
+// x += sc[w] d in the columns with mask[w] set (mask NULL: all); assign != 0
+// writes x = sc[w] d there and zero in the other columns instead (x is not read)
 template<typename C> hipError_t k_axpy_cols(double2* x, const void* d, const Cols& c, const double* sc,
-                                            const int* mask, hipStream_t s);
+                                            const int* mask, int assign, hipStream_t s);
 
 }  // namespace mlfft

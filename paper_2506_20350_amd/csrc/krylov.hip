@@ -515,18 +515,25 @@ __global__ void scale_cols_kernel(const A* __restrict__ src, B* __restrict__ dst
     dst[o] = narrow<B>(make_double2(v.x * f, v.y * f));
 }
 
-// x64 += s[w] * d (d in the inner precision)
+// x64 += s[w] * d (d in the inner precision), or x64 = s[w] * d and zero in the
+// unmasked columns when assign is set
 template<typename C>
 __global__ void axpy_cols_kernel(double2* __restrict__ x, const C* __restrict__ d, const size_t* __restrict__ coff,
-                                 const int* __restrict__ cN, const double* __restrict__ s, const int* __restrict__ mask) {
+                                 const int* __restrict__ cN, const double* __restrict__ s, const int* __restrict__ mask,
+                                 int assign) {
     const int w = blockIdx.y;
-    if (mask && !mask[w]) return;
+    const bool on = !mask || mask[w];
+    if (!on && !assign) return;
     const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (size_t)cN[w]) return;
     const size_t o = coff[w] + n;
+    if (!on) {
+        x[o] = make_double2(0.0, 0.0);
+        return;
+    }
     const double f = s ? s[w] : 1.0;
     const double2 v = Acc<C>::w(d[o]);
-    double2 xo = x[o];
+    double2 xo = assign ? make_double2(0.0, 0.0) : x[o];
     xo.x = fma(f, v.x, xo.x);
     xo.y = fma(f, v.y, xo.y);
     x[o] = xo;
@@ -643,9 +650,10 @@ hipError_t k_scale_cols(const void* src, void* dst, const Cols& c, const double*
 }
 
 template<typename C>
-hipError_t k_axpy_cols(double2* x, const void* d, const Cols& c, const double* sc, const int* mask, hipStream_t s) {
+hipError_t k_axpy_cols(double2* x, const void* d, const Cols& c, const double* sc, const int* mask, int assign,
+                       hipStream_t s) {
     hipLaunchKernelGGL(axpy_cols_kernel<C>, cols_grid(c.maxN, c.W), dim3(256), 0, s, x, (const C*)d, c.off, c.N, sc,
-                       mask);
+                       mask, assign);
     return hipGetLastError();
 }
 
@@ -657,7 +665,8 @@ hipError_t k_axpy_cols(double2* x, const void* d, const Cols& c, const double* s
     template hipError_t k_combine<C>(const void*, const Cols&, const double2*, const int*, int, void*, int,       \
                                      hipStream_t);                                                                \
     template hipError_t k_add_cols<C>(void*, const void*, const Cols&, hipStream_t);                              \
-    template hipError_t k_axpy_cols<C>(double2*, const void*, const Cols&, const double*, const int*, hipStream_t);
+    template hipError_t k_axpy_cols<C>(double2*, const void*, const Cols&, const double*, const int*, int,       \
+                                       hipStream_t);
 INST(float2)
 INST(double2)
 template hipError_t k_scale_cols<double2, float2>(const void*, void*, const Cols&, const double*, int, hipStream_t);

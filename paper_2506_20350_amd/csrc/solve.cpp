@@ -371,13 +371,27 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     const int Wk = global ? 1 : Wt;
     std::vector<size_t> hkoff = global ? std::vector<size_t>{0} : hoff;
     std::vector<int> hkN = global ? std::vector<int>{(int)S} : hN;
+    // V and I are used in place (no gather of V, no scatter of x) when the
+    // batch's columns already lie back to back in batch order in both and the
+    // two ranges do not overlap; otherwise they are copied to and from the
+    // workspace.
+    bool in_place = true;
+    {
+        const char* v0 = (const char*)segs[0].V;
+        char* i0 = (char*)segs[0].I;
+        for (const Seg& sg : segs)
+            in_place = in_place && (const char*)sg.V == v0 + sg.off * 16 && (char*)sg.I == i0 + sg.off * 16;
+        const bool disjoint = i0 + S * 16 <= v0 || v0 + S * 16 <= (const char*)i0;
+        in_place = in_place && disjoint;
+    }
     // carve the workspaces
     const size_t v64b = align_up(S * 16), vTb = align_up(S * eb);
+    const size_t n64 = in_place ? 1 : 3;                     // FP64 batch vectors in the workspace
     // Preconditioned directions z_j = P^{-1} v_j are kept (m more vectors) when the
     // solve is flexible, and also with a fixed preconditioner when the memory is
     // there: x = Z y then replaces x = P^{-1} (V y), one preconditioner apply less
     // per cycle.  Without the memory the fixed preconditioner is applied to V y.
-    const size_t big0 = 3 * v64b + 4 * vTb + (size_t)(m + 1) * vTb;
+    const size_t big0 = n64 * v64b + 4 * vTb + (size_t)(m + 1) * vTb;
     const size_t bigz = big0 + (size_t)m * vTb;
     const int hist_len = (info && o.record_history) ? info->history_len : 0;
     // Arnoldi chunks of every column and their partial-sum rows
@@ -403,8 +417,13 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     w.zstore = zstore;
     HIPCHK(c->solve_ws2.ensure(small), "Krylov workspace");
     char* p = (char*)c->solve_ws.p;
-    w.v64 = (double2*)p; p += v64b;
-    w.x64 = (double2*)p; p += v64b;
+    if (in_place) {
+        w.v64 = (double2*)const_cast<void*>(segs[0].V);    // read only
+        w.x64 = (double2*)segs[0].I;
+    } else {
+        w.v64 = (double2*)p; p += v64b;
+        w.x64 = (double2*)p; p += v64b;
+    }
     w.r64 = (double2*)p; p += v64b;
     w.rT = p; p += vTb;
     w.dT = p; p += vTb;
@@ -461,13 +480,17 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     HIPCHK(hipMemcpyAsync(w.cN, hN.data(), Wt * sizeof(int), hipMemcpyHostToDevice, s), "columns");
     HIPCHK(hipMemsetAsync(w.iters, 0, Wt * sizeof(int), s), "iters");
     if (hist_len) HIPCHK(hipMemsetAsync(w.hist, 0, (size_t)hist_len * Wt * 8, s), "history");
-    // gather V (and x0) into batch vectors
-    for (auto& sg : segs) {
-        HIPCHK(hipMemcpyAsync(w.v64 + sg.off, sg.V, sg.N * sg.W * 16, hipMemcpyDeviceToDevice, s), "gather V");
-        if (o.x0_given)
-            HIPCHK(hipMemcpyAsync(w.x64 + sg.off, sg.I, sg.N * sg.W * 16, hipMemcpyDeviceToDevice, s), "gather x0");
+    // gather V (and x0) into batch vectors.  Without x0, x starts at zero: the
+    // first update writes x instead of adding to it (x_written).
+    if (!in_place) {
+        for (auto& sg : segs) {
+            HIPCHK(hipMemcpyAsync(w.v64 + sg.off, sg.V, sg.N * sg.W * 16, hipMemcpyDeviceToDevice, s), "gather V");
+            if (o.x0_given)
+                HIPCHK(hipMemcpyAsync(w.x64 + sg.off, sg.I, sg.N * sg.W * 16, hipMemcpyDeviceToDevice, s),
+                       "gather x0");
+        }
     }
-    if (!o.x0_given) HIPCHK(hipMemsetAsync(w.x64, 0, S * 16, s), "zero x");
+    bool x_written = o.x0_given != 0;
     HIPCHK(k_colnorm<double2>(w.v64, cols, w.vnorm, s), "norms");
     std::vector<double> hv(Wt), hr(Wt), ht(Wt);
     std::vector<int> hstate(Wt), outer_used(Wt, 0);
@@ -478,21 +501,32 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     // every transformed vector to 8 significant bits, which makes the inner
     // operator inexact at the 1e-3 level, so its solve is stopped at 1e-2.
     const double inner_floor = o.inner_tol > 0.0 ? o.inner_tol : (prec == PBF16 ? 1e-2 : 3e-7);
-    bool r_current = false;     // r64 holds V - Z x64 for the current x64
+    bool r_current = false;     // hr holds the norms of V - Z x64 for the current x64
+    bool r_is_v = false;        // the residual of the last step was V itself (x = 0), not stored in r64
     // arrays whose x changed in the last inner solve; in the per-RHS mode the
     // update is masked to the solved columns, so the residual of an array with
     // no solved column is still current
     std::vector<Seg> rsegs = segs;
     for (int outer = 0; outer < o.max_outer; ++outer) {
+        const double2* rsrc = w.r64;
         if (outer == 0 && !o.x0_given) {
-            HIPCHK(hipMemcpyAsync(w.r64, w.v64, S * 16, hipMemcpyDeviceToDevice, s), "r = V");
-        } else if (!rsegs.empty()) {
-            STCHK(batch_matvec(c, rsegs, w.x64, w.r64, w.v64, -1.0, 1.0, P64));
-            if (info) info->matvecs64 += 1;
+            // x = 0: the residual is V and its norms are those of V
+            rsrc = w.v64;
+            r_is_v = true;
+            HIPCHK(hipStreamSynchronize(s), "norms");
+            hr = hv;
+        } else {
+            // every array's slot of r64 is recomputed after a step that took the residual from V
+            if (r_is_v) rsegs = segs;
+            r_is_v = false;
+            if (!rsegs.empty()) {
+                STCHK(batch_matvec(c, rsegs, w.x64, w.r64, w.v64, -1.0, 1.0, P64));
+                if (info) info->matvecs64 += 1;
+            }
+            HIPCHK(k_colnorm<double2>(w.r64, cols, w.rnorm, s), "norms");
+            HIPCHK(hipMemcpyAsync(hr.data(), w.rnorm, Wt * sizeof(double), hipMemcpyDeviceToHost, s), "norms");
+            HIPCHK(hipStreamSynchronize(s), "norms");
         }
-        HIPCHK(k_colnorm<double2>(w.r64, cols, w.rnorm, s), "norms");
-        HIPCHK(hipMemcpyAsync(hr.data(), w.rnorm, Wt * sizeof(double), hipMemcpyDeviceToHost, s), "norms");
-        HIPCHK(hipStreamSynchronize(s), "norms");
         int active = 0;
         for (int i = 0; i < Wt; ++i) {
             const bool done = !(hv[i] > 0.0) || hr[i] <= o.tol * hv[i];
@@ -510,7 +544,7 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
         if (active == 0) { r_current = true; break; }
         if (global) rsegs = segs;
         else active_segs(segs, w, hstate.data(), Wt, rsegs);
-        const double* scale = w.rnorm;
+        const double* scale = r_is_v ? w.vnorm : w.rnorm;
         if (global) {
             // one inner solve of Z D = R / ||R||_F over all columns, to the Frobenius target
             double v2 = 0.0, r2 = 0.0;
@@ -531,29 +565,34 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
         for (int i = 0; i < Wt; ++i) hstate[i] = global ? 1 : hstate[i] == 0;
         HIPCHK(hipMemcpyAsync(w.mask, hstate.data(), Wt * sizeof(int), hipMemcpyHostToDevice, s), "mask");
         if (prec == P64)
-            HIPCHK((k_scale_cols<double2, double2>(w.r64, w.rT, cols, scale, 1, s)), "scale r");
+            HIPCHK((k_scale_cols<double2, double2>(rsrc, w.rT, cols, scale, 1, s)), "scale r");
         else
-            HIPCHK((k_scale_cols<double2, float2>(w.r64, w.rT, cols, scale, 1, s)), "scale r");
+            HIPCHK((k_scale_cols<double2, float2>(rsrc, w.rT, cols, scale, 1, s)), "scale r");
         mlfft_status st = prec == P64 ? inner_solve<double2>(c, segs, w, kc, o, prec, info, hstate)
                                       : inner_solve<float2>(c, segs, w, kc, o, prec, info, hstate);
         if (st < 0) return st;
+        const int assign = x_written ? 0 : 1;
         if (prec == P64)
-            HIPCHK(k_axpy_cols<double2>(w.x64, w.dT, cols, scale, w.mask, s), "update x");
+            HIPCHK(k_axpy_cols<double2>(w.x64, w.dT, cols, scale, w.mask, assign, s), "update x");
         else
-            HIPCHK(k_axpy_cols<float2>(w.x64, w.dT, cols, scale, w.mask, s), "update x");
+            HIPCHK(k_axpy_cols<float2>(w.x64, w.dT, cols, scale, w.mask, assign, s), "update x");
+        x_written = true;
         HIPCHK(hipStreamSynchronize(s), "update x");      // host vectors above are reused next step
     }
-    // final true FP64 residual (already at hand when the loop stopped on convergence)
+    // every column was already converged at x = 0 (zero right-hand sides)
+    if (!x_written) HIPCHK(hipMemsetAsync(w.x64, 0, S * 16, s), "zero x");
+    // final true FP64 residual (its norms are already at hand when the loop stopped on convergence)
     if (!r_current) {
         STCHK(batch_matvec(c, segs, w.x64, w.r64, w.v64, -1.0, 1.0, P64));
         if (info) info->matvecs64 += 1;
+        HIPCHK(k_colnorm<double2>(w.r64, cols, w.rnorm, s), "norms");
+        HIPCHK(hipMemcpyAsync(hr.data(), w.rnorm, Wt * sizeof(double), hipMemcpyDeviceToHost, s), "norms");
     }
-    HIPCHK(k_colnorm<double2>(w.r64, cols, w.rnorm, s), "norms");
-    HIPCHK(hipMemcpyAsync(hr.data(), w.rnorm, Wt * sizeof(double), hipMemcpyDeviceToHost, s), "norms");
     std::vector<int> hit(Wk);
     HIPCHK(hipMemcpyAsync(hit.data(), w.iters, Wk * sizeof(int), hipMemcpyDeviceToHost, s), "iters");
-    for (auto& sg : segs)
-        HIPCHK(hipMemcpyAsync(sg.I, w.x64 + sg.off, sg.N * sg.W * 16, hipMemcpyDeviceToDevice, s), "scatter x");
+    if (!in_place)
+        for (auto& sg : segs)
+            HIPCHK(hipMemcpyAsync(sg.I, w.x64 + sg.off, sg.N * sg.W * 16, hipMemcpyDeviceToDevice, s), "scatter x");
     std::vector<double> hh;
     if (hist_len) {
         hh.resize((size_t)hist_len * Wk);

@@ -314,3 +314,70 @@ def test_full_size_30x30_b200_autotuned_sampled_columns(ctx):
     # the same tuned block-product shape in a plain FP32 matvec, sampled columns against the oracle
     y = to_host(ctx.matvec(18, to_dev(V, torch.complex64), prec="fp32"))
     assert relerr(y[cols], mv(V[cols])) <= 1e-5
+
+
+def test_in_place_and_staged_solves_agree_bitwise(ctx):
+    """The solve works in V and I directly when the batch's columns lie back to back in both
+    (no staging copies) and stages them otherwise (separate tensors, or V and I overlapping);
+    the arithmetic is the same, so the three solutions agree bit for bit.  I starts as NaN:
+    without an initial guess the solve must not read it."""
+    shapes = [(4, 6, 24, 0.6 * np.pi), (5, 5, 16, np.pi)]
+    ids, Vh, refs = [], [], []
+    for i, (Nx, Ny, b, kd) in enumerate(shapes):
+        blocks = synth.green_blocks(Nx, Ny, b, kd, seed=2000 + i)
+        ctx.set_blocks(40 + i, blocks)
+        V = synth.port_rhs(Nx, Ny, b, cols=list(range(0, Nx * Ny, 3)))
+        ids.append(40 + i)
+        Vh.append(V)
+        refs.append(direct.lu_solve(tp.dense_Z(blocks), V))
+    opts = dict(tol=1e-10, inner_prec="fp32", precond=1)
+    sizes = [v.size for v in Vh]
+    # staged: the arrays' slices of V and of I are one element apart (not back to back)
+    Vgap = to_dev(np.concatenate([np.concatenate([v.ravel(), np.zeros(1)]) for v in Vh]))
+    Igap = torch.full_like(Vgap, float("nan"))
+    goffs = np.cumsum([0] + [n + 1 for n in sizes])
+    Vs_s = [Vgap[goffs[k]:goffs[k] + sizes[k]].view(v.shape) for k, v in enumerate(Vh)]
+    Is_s = [Igap[goffs[k]:goffs[k] + sizes[k]].view(v.shape) for k, v in enumerate(Vh)]
+    _, info_s = ctx.solve_batch(ids, Vs_s, Is_s, **opts)
+    # in place: one tensor for all V, one for all I, sliced per array
+    Vflat = to_dev(np.concatenate([v.ravel() for v in Vh]))
+    Iflat = torch.full_like(Vflat, float("nan"))
+    offs = np.cumsum([0] + sizes)
+    Vs_p = [Vflat[offs[k]:offs[k + 1]].view(v.shape) for k, v in enumerate(Vh)]
+    Is_p = [Iflat[offs[k]:offs[k + 1]].view(v.shape) for k, v in enumerate(Vh)]
+    _, info_p = ctx.solve_batch(ids, Vs_p, Is_p, **opts)
+    assert info_s["status"] == info_p["status"] == abi.MLFFT_OK
+    for a, b_, ref in zip(Is_s, Is_p, refs):
+        assert torch.equal(a, b_)
+        assert relerr(to_host(b_), ref) <= 1e-8
+    assert np.array_equal(info_s["iters"], info_p["iters"])
+    # V and I the same buffer: staged, the solution overwrites the excitation
+    X = to_dev(Vh[0])
+    _, info_x = ctx.solve(ids[0], X, X, **opts)
+    assert info_x["status"] == abi.MLFFT_OK
+    assert torch.equal(X, Is_s[0])
+
+
+def test_batch_with_an_all_zero_array_and_two_refinement_steps(ctx):
+    """An array whose excitations are all zero is converged at x = 0 and drops out of the
+    first Krylov steps; the next FP64 residual must still cover every array.  The FP32 inner
+    solve cannot reach 1e-11 in one refinement step, so a second one runs."""
+    shapes = [(4, 4, 16, np.pi), (3, 5, 8, 0.7 * np.pi)]
+    ids, Vs, refs = [], [], []
+    for i, (Nx, Ny, b, kd) in enumerate(shapes):
+        blocks = synth.green_blocks(Nx, Ny, b, kd, seed=2100 + i)
+        ctx.set_blocks(50 + i, blocks)
+        V = synth.port_rhs(Nx, Ny, b, cols=[0, 3, 7])
+        if i == 1:
+            V[:] = 0.0
+        ids.append(50 + i)
+        Vs.append(V)
+        refs.append(direct.lu_solve(tp.dense_Z(blocks), V))
+    Is = [torch.full(v.shape, float("nan"), dtype=torch.complex128, device="cuda") for v in Vs]
+    Is, info = ctx.solve_batch(ids, [to_dev(v) for v in Vs], Is, tol=1e-11, inner_prec="fp32", precond=1)
+    assert info["status"] == abi.MLFFT_OK
+    assert int(info["outer"].max()) >= 2
+    assert np.all(info["outer"][3:] == 0) and np.all(info["iters"][3:] == 0)
+    assert torch.count_nonzero(Is[1]) == 0
+    assert relerr(to_host(Is[0]), refs[0]) <= 1e-9
+    assert np.all(info["relres"] <= 1e-11)
