@@ -140,7 +140,9 @@ typedef struct {
     int max_outer;       /* FP64 refinement steps (default 10) */
     int precond;         /* 0 none, 1 block circulant (default), 2 self block (Kindt), 3 learned correction of the
                             block-circulant output (flexible GMRES; needs a network, see mlfft_net_create) */
-    int orth;            /* 1 classical Gram-Schmidt, 2 classical Gram-Schmidt applied twice (default); FP64 sums */
+    int orth;            /* 1 classical Gram-Schmidt, 2 classical Gram-Schmidt applied twice (default): the
+                            second projection is formed from the FP64 Gram matrix of the stored basis, so
+                            both read the basis twice per step; FP64 sums */
     int x0_given;        /* 1: I holds the initial guess on entry; 0: start from zero (default) */
     int record_history;  /* 1: fill info->history */
     int use_graph;       /* 1: run the Krylov steps (preconditioner, product, orthogonalisation,

@@ -14,16 +14,17 @@ struct Cols {
     size_t S;
     size_t maxN;
     // Arnoldi chunking: column w owns chunks choff[w] .. choff[w+1]-1 (device,
-    // W+1 entries, arnoldi_chunks(N[w]) each), nch chunks in all; part1 / part2
-    // hold the per-chunk partial sums coefficient-major, (2m+3) x nch doubles,
-    // and hsum1 / hsum2 their per-column totals, W x (2m+3) doubles (device)
+    // W+1 entries, arnoldi_chunks(N[w]) each), nch chunks in all; part1 holds
+    // the per-chunk partial sums coefficient-major, (4m+3) x nch doubles, and
+    // hsum1 their per-column totals, W x (4m+3) doubles; gram the Gram matrix of
+    // each column's basis, W x (m+1) x (m+1) complex doubles, needed with
+    // orth == 2 (all device)
     const int* choff = nullptr;
     int nch = 0;
     int maxch = 0;              // largest number of chunks of one column
     double* part1 = nullptr;
-    double* part2 = nullptr;
     double* hsum1 = nullptr;
-    double* hsum2 = nullptr;
+    double2* gram = nullptr;
 };
 
 // chunks of kArnChunk entries one column of N entries is cut into by k_arnoldi

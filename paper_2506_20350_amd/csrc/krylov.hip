@@ -29,28 +29,35 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Block-wide sums (256 threads = 4 waves) of the CNT per-thread values vals[i]
-// for i < lim and i = CNT-1; results land in out[] (LDS) for all threads.  The
-// loop bound is a compile-time constant so vals[] stays in registers.
-template<int CNT>
-__device__ __forceinline__ void block_sum(const double* vals, int lim, double* red, double* out) {
+// Block-wide sums (256 threads = 4 waves) of the per-thread values vals[i] for
+// the i < CNT with keep(i) (a condition uniform over the block); results land in
+// out[] (LDS) for all threads.  red holds 4 * CNT doubles.  The loop bound is a
+// compile-time constant so vals[] stays in registers.
+template<int CNT, typename K>
+__device__ __forceinline__ void block_sum_if(const double* vals, K keep, double* red, double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
     for (int i = 0; i < CNT; ++i) {
-        if (i < lim || i == CNT - 1) {
+        if (keep(i)) {
             const double s = wave_sum(vals[i]);
-            if (lane == 0) red[wave * 72 + i] = s;
+            if (lane == 0) red[wave * CNT + i] = s;
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < CNT; i += blockDim.x) {
-        if (i < lim || i == CNT - 1) {
+        if (keep(i)) {
             double s = 0.0;
-            for (int q = 0; q < nw; ++q) s += red[q * 72 + i];
+            for (int q = 0; q < nw; ++q) s += red[q * CNT + i];
             out[i] = s;
         }
     }
     __syncthreads();
+}
+
+// the same for vals[i], i < lim, and the last value vals[CNT-1]
+template<int CNT>
+__device__ __forceinline__ void block_sum(const double* vals, int lim, double* red, double* out) {
+    block_sum_if<CNT>(vals, [=](int i) { return i < lim || i == CNT - 1; }, red, out);
 }
 
 // Per-column norms ||x_w||_2 in FP64.
@@ -71,18 +78,25 @@ __global__ void __launch_bounds__(256) colnorm_kernel(const C* __restrict__ x, c
 }
 
 // One Arnoldi step for every iterating column: orthogonalise u = Vb[j+1] against
-// Vb[0..j] (classical Gram-Schmidt, applied twice when orth == 2), store the
-// coefficients in H[:, j] and u / ||u|| in Vb[j+1].
+// the stored basis V = Vb[0..j] (classical Gram-Schmidt, applied twice when
+// orth == 2), store the coefficients in H[:, j] and the normalised remainder in
+// Vb[j+1].
 //
 // A column is cut into chunks of kArnChunk entries, one workgroup each, so that
-// a launch has many more workgroups than the chip has CUs whatever W is.  Three
+// a launch has many more workgroups than the chip has CUs whatever W is.  Two
 // passes over the j+2 vectors:
-//   dots (pass 1)  per chunk: Vᴴu and ||u||² partial sums
-//   dots (pass 2)  per chunk: h1 = sum of the pass-1 partials of the column, then
-//                  Vᴴu' and ||u'||² partials with u' = u - V h1 (u' is not stored)
-//   update         h = h1 + h2, beta² = ||u'||² - ||h2||², v_{j+1} = (u - V h) / beta
-// Every workgroup of a column reduces that column's partials itself, in the same
-// order, so the result does not depend on scheduling.
+//   dots    per chunk: partial sums of h1 = Vᴴu and ||u||², and with orth == 2
+//           also of g = Vᴴv_j, column j of the Gram matrix G = VᴴV of the
+//           stored (rounded) basis
+//   update  h1, ||u||² and g summed over the column's chunks; with orth == 2 the
+//           second projection is formed from G rather than from a second pass:
+//           Vᴴ(u - V h1) = h1 - G h1 holds exactly, so h2 = h1 - G h1, h = h1 + h2
+//           and beta² = ||u - V h||² = ||u||² - 2 Re(hᴴh1) + hᴴGh; with orth == 1
+//           h = h1 and beta² = ||u||² - ||h1||².  Then v_{j+1} = (u - V h) / beta.
+// Columns 0..j-1 of G were formed by the earlier steps of the cycle and are kept
+// per Krylov column in FP64.  Every workgroup of a column reduces that column's
+// partials itself, in the same order, so the result does not depend on
+// scheduling.
 constexpr int kArnT = 256;
 constexpr int kArnE = 32;
 constexpr int kArnChunk = kArnT * kArnE;
@@ -133,62 +147,67 @@ __global__ void __launch_bounds__(256) arnoldi_reduce_kernel(const double* __res
     }
 }
 
-template<typename C, int MAXJ, int PASS>
+template<typename C, int MAXJ, int GRAM>
 __global__ void __launch_bounds__(256) arnoldi_dots_kernel(const C* __restrict__ Vb, int j, size_t vstride,
                                                            const size_t* __restrict__ coff, const int* __restrict__ cN,
                                                            const int* __restrict__ choff, int W,
-                                                           const int* __restrict__ state,
-                                                           const double* __restrict__ hsum1,
-                                                           const double* __restrict__ part1,
-                                                           double* __restrict__ out, int nchT, int stride, int inl) {
-    __shared__ double red[4 * 72];
-    __shared__ double sh[2 * MAXJ + 1];
-    __shared__ double h1[2 * MAXJ + 1];
+                                                           const int* __restrict__ state, double* __restrict__ out,
+                                                           int nchT) {
+    // vals: [0, 2 MAXJ) Vᴴu, [2 MAXJ, 4 MAXJ) Vᴴv_j (GRAM), last ||u||²
+    constexpr int NV = GRAM ? 4 * MAXJ + 1 : 2 * MAXJ + 1;
+    __shared__ double red[4 * NV];
+    __shared__ double sh[NV];
     const int c = blockIdx.x;
     const int w = chunk_column(choff, W, c);
     if (state[w] != 0) return;
-    const int c0 = choff[w], nch = choff[w + 1] - c0;
+    const int c0 = choff[w];
     const size_t N = cN[w];
     const size_t n0 = (size_t)(c - c0) * kArnChunk;
     const C* __restrict__ V = Vb + coff[w];
     const C* __restrict__ u = Vb + (size_t)(j + 1) * vstride + coff[w];
-    if (PASS == 2) {
-        if (inl) reduce_parts(part1, nchT, c0, nch, 2 * (j + 1), h1);
-        else
-            for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) h1[i] = hsum1[(size_t)w * stride + i];
-        __syncthreads();
-    }
-    double vals[2 * MAXJ + 1];
+    double vals[NV];
 #pragma unroll
-    for (int i = 0; i < 2 * MAXJ + 1; ++i) vals[i] = 0.0;
+    for (int i = 0; i < NV; ++i) vals[i] = 0.0;
     for (int k = 0; k < kArnE; ++k) {
         const size_t n = n0 + (size_t)k * kArnT + threadIdx.x;
         if (n >= N) break;
-        double2 x = Acc<C>::w(u[n]);
-        double2 vv[MAXJ];
+        const double2 x = Acc<C>::w(u[n]);
+        C vv[MAXJ];
+        C vl = narrow<C>(make_double2(0.0, 0.0));
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i) {
             if (i <= j) {
-                vv[i] = Acc<C>::w(V[(size_t)i * vstride + n]);
-                if (PASS == 2) {
-                    const double hr = h1[2 * i], hi = h1[2 * i + 1];
-                    x.x -= hr * vv[i].x - hi * vv[i].y;
-                    x.y -= hr * vv[i].y + hi * vv[i].x;
+                vv[i] = V[(size_t)i * vstride + n];
+                if (GRAM && i == j) vl = vv[i];
+            }
+        }
+        vals[NV - 1] = fma(x.x, x.x, fma(x.y, x.y, vals[NV - 1]));
+        const double2 y = Acc<C>::w(vl);
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i) {
+            if (i <= j) {
+                const double2 v = Acc<C>::w(vv[i]);
+                vals[2 * i] = fma(v.x, x.x, fma(v.y, x.y, vals[2 * i]));
+                vals[2 * i + 1] = fma(v.x, x.y, fma(-v.y, x.x, vals[2 * i + 1]));
+                if (GRAM) {
+                    vals[2 * MAXJ + 2 * i] = fma(v.x, y.x, fma(v.y, y.y, vals[2 * MAXJ + 2 * i]));
+                    vals[2 * MAXJ + 2 * i + 1] = fma(v.x, y.y, fma(-v.y, y.x, vals[2 * MAXJ + 2 * i + 1]));
                 }
             }
         }
-        vals[2 * MAXJ] = fma(x.x, x.x, fma(x.y, x.y, vals[2 * MAXJ]));
-#pragma unroll
-        for (int i = 0; i < MAXJ; ++i) {
-            if (i <= j) {
-                vals[2 * i] = fma(vv[i].x, x.x, fma(vv[i].y, x.y, vals[2 * i]));
-                vals[2 * i + 1] = fma(vv[i].x, x.y, fma(-vv[i].y, x.x, vals[2 * i + 1]));
-            }
-        }
     }
-    block_sum<2 * MAXJ + 1>(vals, 2 * (j + 1), red, sh);
-    for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) out[(size_t)i * nchT + c] = sh[i];
-    if (threadIdx.x == 0) out[(size_t)(2 * (j + 1)) * nchT + c] = sh[2 * MAXJ];
+    const int J2 = 2 * (j + 1);
+    block_sum_if<NV>(vals, [=](int i) { return (i < NV - 1 && (i % (2 * MAXJ)) < J2) || i == NV - 1; }, red, sh);
+    // partial-sum rows: [0, 2J) Vᴴu, 2J ||u||², [2J + 1, 4J + 1) Vᴴv_j (J = j + 1)
+    for (int i = threadIdx.x; i < J2; i += blockDim.x) {
+        out[(size_t)i * nchT + c] = sh[i];
+        if (GRAM) out[(size_t)(J2 + 1 + i) * nchT + c] = sh[2 * MAXJ + i];
+    }
+    if (threadIdx.x == 0) out[(size_t)J2 * nchT + c] = sh[NV - 1];
+}
+
+__device__ __forceinline__ double2 cmul_d(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
 template<typename C, int MAXJ>
@@ -198,13 +217,12 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
                                                              const int* __restrict__ choff, int W,
                                                              double2* __restrict__ H, int m,
                                                              const int* __restrict__ state, int orth,
-                                                             const double* __restrict__ hsum1,
-                                                             const double* __restrict__ hsum2,
-                                                             const double* __restrict__ part1,
-                                                             const double* __restrict__ part2, int nchT, int stride,
-                                                             int inl) {
-    __shared__ double h1[2 * MAXJ + 1];
-    __shared__ double h2[2 * MAXJ + 1];
+                                                             const double* __restrict__ hsum,
+                                                             const double* __restrict__ part, int nchT, int stride,
+                                                             int inl, double2* __restrict__ gram) {
+    __shared__ double sm[4 * MAXJ + 1];
+    __shared__ double2 hh[MAXJ];
+    __shared__ double2 tt[MAXJ];
     const int c = blockIdx.x;
     const int w = chunk_column(choff, W, c);
     const int c0 = choff[w], nch = choff[w + 1] - c0;
@@ -221,35 +239,71 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
         }
         return;
     }
-    const int cnt = 2 * (j + 1) + 1;
-    if (inl) {
-        reduce_parts(part1, nchT, c0, nch, cnt, h1);
-        if (orth == 2) reduce_parts(part2, nchT, c0, nch, cnt, h2);
-    } else {
-        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-            h1[i] = hsum1[(size_t)w * stride + i];
-            if (orth == 2) h2[i] = hsum2[(size_t)w * stride + i];
-        }
-    }
+    const int J = j + 1, J2 = 2 * J;
+    const int cnt = orth == 2 ? 2 * J2 + 1 : J2 + 1;
+    if (inl) reduce_parts(part, nchT, c0, nch, cnt, sm);
+    else
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) sm[i] = hsum[(size_t)w * stride + i];
     __syncthreads();
-    const double unorm2 = h1[2 * (j + 1)];
+    const int t = threadIdx.x;
+    const double unorm2 = sm[J2];
+    const double* h1 = sm;
     double beta2;
     if (orth == 2) {
-        // ||u''||^2 = ||u'||^2 - ||h2||^2 (h2 is at rounding level; the subtraction is benign)
-        double hn = 0.0;
-        for (int i = 0; i <= j; ++i) hn += h2[2 * i] * h2[2 * i] + h2[2 * i + 1] * h2[2 * i + 1];
-        beta2 = h2[2 * (j + 1)] - hn;
+        // Gram matrix of the stored basis: column k at Gw[k (m+1) + i] for i <= k;
+        // column j (this step's) is read from the fresh sums, the others from
+        // the earlier steps
+        double2* Gw = gram + (size_t)w * (m + 1) * (m + 1);
+        const double* gj = sm + J2 + 1;
+        if (c == c0 && t <= j) Gw[(size_t)j * (m + 1) + t] = make_double2(gj[2 * t], gj[2 * t + 1]);
+        auto G = [&](int i, int k) -> double2 {
+            if (i <= k) return k == j ? make_double2(gj[2 * i], gj[2 * i + 1]) : Gw[(size_t)k * (m + 1) + i];
+            const double2 g = i == j ? make_double2(gj[2 * k], gj[2 * k + 1]) : Gw[(size_t)i * (m + 1) + k];
+            return make_double2(g.x, -g.y);
+        };
+        // h = h1 + (h1 - G h1)
+        if (t <= j) {
+            double2 a = make_double2(0.0, 0.0);
+            for (int k = 0; k <= j; ++k) {
+                const double2 p = cmul_d(G(t, k), make_double2(h1[2 * k], h1[2 * k + 1]));
+                a.x += p.x;
+                a.y += p.y;
+            }
+            hh[t] = make_double2(2.0 * h1[2 * t] - a.x, 2.0 * h1[2 * t + 1] - a.y);
+        }
         __syncthreads();
-        for (int i = threadIdx.x; i < 2 * (j + 1); i += blockDim.x) h1[i] += h2[i];
+        // G h
+        if (t <= j) {
+            double2 a = make_double2(0.0, 0.0);
+            for (int k = 0; k <= j; ++k) {
+                const double2 p = cmul_d(G(t, k), hh[k]);
+                a.x += p.x;
+                a.y += p.y;
+            }
+            tt[t] = a;
+        }
         __syncthreads();
+        // ||u - V h||² = ||u||² - 2 Re(hᴴh1) + Re(hᴴ G h)
+        double s1 = 0.0, s2 = 0.0;
+        for (int i = 0; i <= j; ++i) {
+            s1 += hh[i].x * h1[2 * i] + hh[i].y * h1[2 * i + 1];
+            s2 += hh[i].x * tt[i].x + hh[i].y * tt[i].y;
+        }
+        beta2 = unorm2 - 2.0 * s1 + s2;
     } else {
+        if (t <= j) hh[t] = make_double2(h1[2 * t], h1[2 * t + 1]);
+        __syncthreads();
         double hn = 0.0;
-        for (int i = 0; i <= j; ++i) hn += h1[2 * i] * h1[2 * i] + h1[2 * i + 1] * h1[2 * i + 1];
+        for (int i = 0; i <= j; ++i) hn += hh[i].x * hh[i].x + hh[i].y * hh[i].y;
         beta2 = unorm2 - hn;
     }
     double beta = beta2 > 0.0 ? sqrt(beta2) : 0.0;
-    // happy breakdown: the new direction vanishes relative to the matvec output
-    const bool brk = !(beta > 1e-14 * sqrt(unorm2)) || !(beta > 1e-300);
+    // happy breakdown: the new direction vanishes relative to the product.  beta²
+    // is a difference of terms of size up to a few ||u||², whose FP64 rounding is
+    // about 1e-14 ||u||²; below 1e-13 ||u||² (beta below 3e-7 ||u||) it is not
+    // resolved and the direction counts as vanished.  The FP64 true residual of
+    // the refinement loop decides whether the column is really converged.
+    const bool brk = !(beta2 > 1e-13 * unorm2) || !(beta > 1e-300);
     if (brk) beta = 0.0;
     const double inv = brk ? 0.0 : 1.0 / beta;
     for (int k = 0; k < kArnE; ++k) {
@@ -260,17 +314,16 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
         for (int i = 0; i < MAXJ; ++i) {
             if (i <= j) {
                 const double2 v = Acc<C>::w(V[(size_t)i * vstride + n]);
-                const double hr = h1[2 * i], hi = h1[2 * i + 1];
-                up.x -= hr * v.x - hi * v.y;
-                up.y -= hr * v.y + hi * v.x;
+                const double2 h = hh[i];
+                up.x -= h.x * v.x - h.y * v.y;
+                up.y -= h.x * v.y + h.y * v.x;
             }
         }
         u[n] = narrow<C>(make_double2(up.x * inv, up.y * inv));
     }
     if (c == c0) {
-        if (threadIdx.x <= j)
-            H[((size_t)w * (m + 1) + threadIdx.x) * m + j] = make_double2(h1[2 * threadIdx.x], h1[2 * threadIdx.x + 1]);
-        if (threadIdx.x == 0) H[((size_t)w * (m + 1) + j + 1) * m + j] = make_double2(beta, 0.0);
+        if (t <= j) H[((size_t)w * (m + 1) + t) * m + j] = hh[t];
+        if (t == 0) H[((size_t)w * (m + 1) + j + 1) * m + j] = make_double2(beta, 0.0);
     }
 }
 
@@ -555,36 +608,30 @@ int arnoldi_chunks(size_t N) { return (int)((N + kArnChunk - 1) / kArnChunk); }
 template<typename C, int MAXJ>
 static hipError_t arnoldi_t(C* Vb, int j, const Cols& c, double2* H, int m, const int* state, int orth,
                             hipStream_t s) {
-    const int stride = 2 * m + 3;
-    const int cnt = 2 * (j + 1) + 1;
+    const int stride = 4 * m + 3;
+    const int cnt = orth == 2 ? 4 * (j + 1) + 1 : 2 * (j + 1) + 1;
     const dim3 grid((unsigned)c.nch);
     // columns of a few chunks: every workgroup reduces its column's partials itself
-    // (no reduction launches); long columns: one reduction workgroup per column
+    // (no reduction launch); long columns: one reduction workgroup per column
     const int inl = c.maxch <= 16 ? 1 : 0;
-    hipLaunchKernelGGL((arnoldi_dots_kernel<C, MAXJ, 1>), grid, dim3(kArnT), 0, s, (const C*)Vb, j, c.S, c.off, c.N,
-                       c.choff, c.W, state, (const double*)nullptr, (const double*)nullptr, c.part1, c.nch, stride,
-                       inl);
+    if (orth == 2)
+        hipLaunchKernelGGL((arnoldi_dots_kernel<C, MAXJ, 1>), grid, dim3(kArnT), 0, s, (const C*)Vb, j, c.S, c.off,
+                           c.N, c.choff, c.W, state, c.part1, c.nch);
+    else
+        hipLaunchKernelGGL((arnoldi_dots_kernel<C, MAXJ, 0>), grid, dim3(kArnT), 0, s, (const C*)Vb, j, c.S, c.off,
+                           c.N, c.choff, c.W, state, c.part1, c.nch);
     if (!inl)
         hipLaunchKernelGGL(arnoldi_reduce_kernel, dim3(c.W), dim3(256), 0, s, (const double*)c.part1, c.nch, c.choff,
                            state, stride, cnt, c.hsum1);
-    if (orth == 2) {
-        hipLaunchKernelGGL((arnoldi_dots_kernel<C, MAXJ, 2>), grid, dim3(kArnT), 0, s, (const C*)Vb, j, c.S, c.off,
-                           c.N, c.choff, c.W, state, (const double*)c.hsum1, (const double*)c.part1, c.part2, c.nch,
-                           stride, inl);
-        if (!inl)
-            hipLaunchKernelGGL(arnoldi_reduce_kernel, dim3(c.W), dim3(256), 0, s, (const double*)c.part2, c.nch,
-                               c.choff, state, stride, cnt, c.hsum2);
-    }
     hipLaunchKernelGGL((arnoldi_update_kernel<C, MAXJ>), grid, dim3(kArnT), 0, s, Vb, j, c.S, c.off, c.N, c.choff,
-                       c.W, H, m, state, orth, (const double*)c.hsum1, (const double*)c.hsum2,
-                       (const double*)c.part1, (const double*)c.part2, c.nch, stride, inl);
+                       c.W, H, m, state, orth, (const double*)c.hsum1, (const double*)c.part1, c.nch, stride, inl,
+                       c.gram);
     return hipGetLastError();
 }
 
 template<typename C>
 hipError_t k_arnoldi(void* Vb, int j, const Cols& c, double2* H, int m, const int* state, int orth, hipStream_t s) {
-    if (c.nch <= 0 || !c.choff || !c.part1 || !c.hsum1 || (orth == 2 && (!c.part2 || !c.hsum2)))
-        return hipErrorInvalidValue;
+    if (c.nch <= 0 || !c.choff || !c.part1 || !c.hsum1 || (orth == 2 && !c.gram)) return hipErrorInvalidValue;
     if (j + 1 > m || m > 31) return hipErrorInvalidValue;
     const int need = j + 1;
     C* V = (C*)Vb;

@@ -276,10 +276,11 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
                     zsrc = zdst;
                 }
                 STCHK(batch_matvec(c, act, zsrc, vnext, nullptr, 1.0, 0.0, prec));
-                // algorithmic traffic of one step: (orth + 1) passes over the q+2 vectors and one
-                // write for every iterating column, one write (the zeroed slot) for the others
+                // algorithmic traffic of one step: two passes over the q+2 vectors (the second
+                // projection of orth == 2 comes from the Gram matrix) and one write for every
+                // iterating column, one write (the zeroed slot) for the others
                 const double iter_elems = Wt == 1 ? (double)w.S : run_elems;
-                const double bytes = (double)eb * (iter_elems * ((o.orth + 1) * (q + 2) + 1) + ((double)w.S - iter_elems));
+                const double bytes = (double)eb * (iter_elems * (2 * (q + 2) + 1) + ((double)w.S - iter_elems));
                 const int pr = c->prof_begin(PK_ARNOLDI, prec, bytes, 0);
                 HIPCHK(k_arnoldi<C>(w.Vb, q, cols, w.H, m, w.state, o.orth, s), "arnoldi");
                 c->prof_end(pr);
@@ -398,9 +399,10 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     std::vector<int> hchoff(Wk + 1, 0);
     for (int i = 0; i < Wk; ++i) hchoff[i + 1] = hchoff[i] + arnoldi_chunks((size_t)hkN[i]);
     const int nch = hchoff[Wk];
-    const size_t partb = align_up((size_t)nch * (2 * m + 3) * sizeof(double));
-    const size_t hsb = align_up((size_t)Wk * (2 * m + 3) * sizeof(double));
-    size_t small = align_up((Wt + 1) * sizeof(int)) + 2 * partb + 2 * hsb + align_up(sizeof(size_t)) + align_up(sizeof(int)) +
+    const size_t partb = align_up((size_t)nch * (4 * m + 3) * sizeof(double));
+    const size_t hsb = align_up((size_t)Wk * (4 * m + 3) * sizeof(double));
+    const size_t gramb = o.orth == 2 ? align_up((size_t)Wk * (m + 1) * (m + 1) * 16) : 0;
+    size_t small = align_up((Wt + 1) * sizeof(int)) + partb + hsb + gramb + align_up(sizeof(size_t)) + align_up(sizeof(int)) +
                    align_up(Wt * sizeof(double)) + align_up(Wt * sizeof(size_t)) + 5 * align_up(Wt * sizeof(int)) +
                    6 * align_up(Wt * sizeof(double)) + align_up((size_t)Wt * (m + 1) * m * 16) +
                    align_up((size_t)Wt * (m + 1) * 16) + 2 * align_up((size_t)Wt * m * 16) +
@@ -434,9 +436,8 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     char* q = (char*)c->solve_ws2.p;
     int* choff = (int*)q; q += align_up((Wt + 1) * sizeof(int));
     double* part1 = (double*)q; q += partb;
-    double* part2 = (double*)q; q += partb;
     double* hsum1 = (double*)q; q += hsb;
-    double* hsum2 = (double*)q; q += hsb;
+    double2* gram = gramb ? (double2*)q : nullptr; q += gramb;
     size_t* gkoff = (size_t*)q; q += align_up(sizeof(size_t));
     int* gkN = (int*)q; q += align_up(sizeof(int));
     double* gscale = (double*)q; q += align_up(Wt * sizeof(double));
@@ -468,9 +469,8 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     kc.maxch = 0;
     for (int i = 0; i < Wk; ++i) kc.maxch = std::max(kc.maxch, hchoff[i + 1] - hchoff[i]);
     kc.part1 = part1;
-    kc.part2 = part2;
     kc.hsum1 = hsum1;
-    kc.hsum2 = hsum2;
+    kc.gram = gram;
     HIPCHK(hipMemcpyAsync(choff, hchoff.data(), (Wk + 1) * sizeof(int), hipMemcpyHostToDevice, s), "columns");
     if (global) {
         HIPCHK(hipMemcpyAsync(gkoff, hkoff.data(), sizeof(size_t), hipMemcpyHostToDevice, s), "columns");

@@ -18,14 +18,17 @@ from tests.gpu_util import ctx, relerr, to_dev, to_host  # noqa: F401
 pytestmark = pytest.mark.gpu
 
 
-def test_c1_plain_fp64_gmres_matches_lu_and_oracle_iterations(ctx):
-    """4x4 array, b = 24, kd = pi, centre port, GMRES(30), no preconditioner, tol 1e-8."""
+@pytest.mark.parametrize("orth", [2, 1])
+def test_c1_plain_fp64_gmres_matches_lu_and_oracle_iterations(ctx, orth):
+    """4x4 array, b = 24, kd = pi, centre port, GMRES(30), no preconditioner, tol 1e-8;
+    classical Gram-Schmidt twice (the second projection from the Gram matrix) and once,
+    against the oracle's modified Gram-Schmidt."""
     Nx = Ny = 4
     b = 24
     blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0)
     V = synth.port_rhs(Nx, Ny, b, cols=[synth.centre_element(Nx, Ny)])
     ctx.set_blocks(10, blocks)
-    I, info = ctx.solve(10, to_dev(V), tol=1e-8, inner_prec="fp64", precond=0, history_len=40)
+    I, info = ctx.solve(10, to_dev(V), tol=1e-8, inner_prec="fp64", precond=0, history_len=40, orth=orth)
     assert info["status"] == abi.MLFFT_OK and info["converged"].all()
     Z = tp.dense_Z(blocks)
     ref = direct.lu_solve(Z, V)
@@ -35,7 +38,9 @@ def test_c1_plain_fp64_gmres_matches_lu_and_oracle_iterations(ctx):
     ores = krylov.gmres_columns(mv, V, None, tol=1e-8 * 0.9)[0]
     assert info["iters"][0] == ores.iters
     h = info["history"][:info["iters"][0], 0]
-    np.testing.assert_allclose(h, ores.history, rtol=1e-6)
+    # classical Gram-Schmidt applied once loses orthogonality at the 1e-10 level
+    # in FP64 here, which shifts its smallest residual estimates by that much
+    np.testing.assert_allclose(h, ores.history, rtol=1e-6, atol=0.0 if orth == 2 else 1e-9)
 
 
 @pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
