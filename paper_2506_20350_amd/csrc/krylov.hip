@@ -171,28 +171,22 @@ __global__ void __launch_bounds__(256) arnoldi_dots_kernel(const C* __restrict__
     for (int k = 0; k < kArnE; ++k) {
         const size_t n = n0 + (size_t)k * kArnT + threadIdx.x;
         if (n >= N) break;
-        const double2 x = Acc<C>::w(u[n]);
+        // every load is issued unconditionally, its index clamped to j, so that
+        // they are all in flight together; the sums of slots beyond j are unused
         C vv[MAXJ];
-        C vl = narrow<C>(make_double2(0.0, 0.0));
 #pragma unroll
-        for (int i = 0; i < MAXJ; ++i) {
-            if (i <= j) {
-                vv[i] = V[(size_t)i * vstride + n];
-                if (GRAM && i == j) vl = vv[i];
-            }
-        }
+        for (int i = 0; i < MAXJ; ++i) vv[i] = V[(size_t)(i < j ? i : j) * vstride + n];
+        const double2 x = Acc<C>::w(u[n]);
         vals[NV - 1] = fma(x.x, x.x, fma(x.y, x.y, vals[NV - 1]));
-        const double2 y = Acc<C>::w(vl);
+        const double2 y = Acc<C>::w(vv[MAXJ - 1]);       // v_j (j < MAXJ)
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i) {
-            if (i <= j) {
-                const double2 v = Acc<C>::w(vv[i]);
-                vals[2 * i] = fma(v.x, x.x, fma(v.y, x.y, vals[2 * i]));
-                vals[2 * i + 1] = fma(v.x, x.y, fma(-v.y, x.x, vals[2 * i + 1]));
-                if (GRAM) {
-                    vals[2 * MAXJ + 2 * i] = fma(v.x, y.x, fma(v.y, y.y, vals[2 * MAXJ + 2 * i]));
-                    vals[2 * MAXJ + 2 * i + 1] = fma(v.x, y.y, fma(-v.y, y.x, vals[2 * MAXJ + 2 * i + 1]));
-                }
+            const double2 v = Acc<C>::w(vv[i]);
+            vals[2 * i] = fma(v.x, x.x, fma(v.y, x.y, vals[2 * i]));
+            vals[2 * i + 1] = fma(v.x, x.y, fma(-v.y, x.x, vals[2 * i + 1]));
+            if (GRAM) {
+                vals[2 * MAXJ + 2 * i] = fma(v.x, y.x, fma(v.y, y.y, vals[2 * MAXJ + 2 * i]));
+                vals[2 * MAXJ + 2 * i + 1] = fma(v.x, y.y, fma(-v.y, y.x, vals[2 * MAXJ + 2 * i + 1]));
             }
         }
     }
@@ -223,6 +217,7 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
     __shared__ double sm[4 * MAXJ + 1];
     __shared__ double2 hh[MAXJ];
     __shared__ double2 tt[MAXJ];
+    __shared__ double2 gs[MAXJ * MAXJ];
     const int c = blockIdx.x;
     const int w = chunk_column(choff, W, c);
     const int c0 = choff[w], nch = choff[w + 1] - c0;
@@ -251,16 +246,24 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
     double beta2;
     if (orth == 2) {
         // Gram matrix of the stored basis: column k at Gw[k (m+1) + i] for i <= k;
-        // column j (this step's) is read from the fresh sums, the others from
-        // the earlier steps
+        // column j (this step's) comes from the fresh sums, the others from the
+        // earlier steps.  The (j+1)² entries are gathered into LDS in one round
+        // of loads.
         double2* Gw = gram + (size_t)w * (m + 1) * (m + 1);
         const double* gj = sm + J2 + 1;
         if (c == c0 && t <= j) Gw[(size_t)j * (m + 1) + t] = make_double2(gj[2 * t], gj[2 * t + 1]);
-        auto G = [&](int i, int k) -> double2 {
-            if (i <= k) return k == j ? make_double2(gj[2 * i], gj[2 * i + 1]) : Gw[(size_t)k * (m + 1) + i];
-            const double2 g = i == j ? make_double2(gj[2 * k], gj[2 * k + 1]) : Gw[(size_t)i * (m + 1) + k];
-            return make_double2(g.x, -g.y);
-        };
+        for (int e = t; e < J * J; e += blockDim.x) {
+            const int i = e / J, k = e - i * J;
+            double2 g;
+            if (i <= k) g = k == j ? make_double2(gj[2 * i], gj[2 * i + 1]) : Gw[(size_t)k * (m + 1) + i];
+            else {
+                g = i == j ? make_double2(gj[2 * k], gj[2 * k + 1]) : Gw[(size_t)i * (m + 1) + k];
+                g.y = -g.y;
+            }
+            gs[i * MAXJ + k] = g;
+        }
+        __syncthreads();
+        auto G = [&](int i, int k) -> double2 { return gs[i * MAXJ + k]; };
         // h = h1 + (h1 - G h1)
         if (t <= j) {
             double2 a = make_double2(0.0, 0.0);
@@ -271,6 +274,7 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
             }
             hh[t] = make_double2(2.0 * h1[2 * t] - a.x, 2.0 * h1[2 * t + 1] - a.y);
         }
+        if (t > j && t < MAXJ) hh[t] = make_double2(0.0, 0.0);
         __syncthreads();
         // G h
         if (t <= j) {
@@ -292,6 +296,7 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
         beta2 = unorm2 - 2.0 * s1 + s2;
     } else {
         if (t <= j) hh[t] = make_double2(h1[2 * t], h1[2 * t + 1]);
+        if (t > j && t < MAXJ) hh[t] = make_double2(0.0, 0.0);
         __syncthreads();
         double hn = 0.0;
         for (int i = 0; i <= j; ++i) hn += hh[i].x * hh[i].x + hh[i].y * hh[i].y;
@@ -309,15 +314,17 @@ __global__ void __launch_bounds__(256) arnoldi_update_kernel(C* __restrict__ Vb,
     for (int k = 0; k < kArnE; ++k) {
         const size_t n = n0 + (size_t)k * kArnT + threadIdx.x;
         if (n >= N) break;
+        // unconditional loads (index clamped to j) with zero coefficients beyond j
+        C vv[MAXJ];
+#pragma unroll
+        for (int i = 0; i < MAXJ; ++i) vv[i] = V[(size_t)(i < j ? i : j) * vstride + n];
         double2 up = Acc<C>::w(u[n]);
 #pragma unroll
         for (int i = 0; i < MAXJ; ++i) {
-            if (i <= j) {
-                const double2 v = Acc<C>::w(V[(size_t)i * vstride + n]);
-                const double2 h = hh[i];
-                up.x -= h.x * v.x - h.y * v.y;
-                up.y -= h.x * v.y + h.y * v.x;
-            }
+            const double2 v = Acc<C>::w(vv[i]);
+            const double2 h = hh[i];
+            up.x -= h.x * v.x - h.y * v.y;
+            up.y -= h.x * v.y + h.y * v.x;
         }
         u[n] = narrow<C>(make_double2(up.x * inv, up.y * inv));
     }
@@ -633,12 +640,24 @@ template<typename C>
 hipError_t k_arnoldi(void* Vb, int j, const Cols& c, double2* H, int m, const int* state, int orth, hipStream_t s) {
     if (c.nch <= 0 || !c.choff || !c.part1 || !c.hsum1 || (orth == 2 && !c.gram)) return hipErrorInvalidValue;
     if (j + 1 > m || m > 31) return hipErrorInvalidValue;
-    const int need = j + 1;
+    // the kernels load a fixed number of basis vectors: exactly j + 1 up to 8,
+    // then the next of 12, 16, 24, 32
     C* V = (C*)Vb;
-    if (need <= 4) return arnoldi_t<C, 4>(V, j, c, H, m, state, orth, s);
-    if (need <= 8) return arnoldi_t<C, 8>(V, j, c, H, m, state, orth, s);
-    if (need <= 16) return arnoldi_t<C, 16>(V, j, c, H, m, state, orth, s);
-    if (need <= 32) return arnoldi_t<C, 32>(V, j, c, H, m, state, orth, s);
+    switch (j + 1) {
+        case 1: return arnoldi_t<C, 1>(V, j, c, H, m, state, orth, s);
+        case 2: return arnoldi_t<C, 2>(V, j, c, H, m, state, orth, s);
+        case 3: return arnoldi_t<C, 3>(V, j, c, H, m, state, orth, s);
+        case 4: return arnoldi_t<C, 4>(V, j, c, H, m, state, orth, s);
+        case 5: return arnoldi_t<C, 5>(V, j, c, H, m, state, orth, s);
+        case 6: return arnoldi_t<C, 6>(V, j, c, H, m, state, orth, s);
+        case 7: return arnoldi_t<C, 7>(V, j, c, H, m, state, orth, s);
+        case 8: return arnoldi_t<C, 8>(V, j, c, H, m, state, orth, s);
+        default: break;
+    }
+    if (j + 1 <= 12) return arnoldi_t<C, 12>(V, j, c, H, m, state, orth, s);
+    if (j + 1 <= 16) return arnoldi_t<C, 16>(V, j, c, H, m, state, orth, s);
+    if (j + 1 <= 24) return arnoldi_t<C, 24>(V, j, c, H, m, state, orth, s);
+    if (j + 1 <= 32) return arnoldi_t<C, 32>(V, j, c, H, m, state, orth, s);
     return hipErrorInvalidValue;
 }
 
