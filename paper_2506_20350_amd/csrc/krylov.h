@@ -39,8 +39,9 @@ hipError_t k_givens(double2* H, double* cs, double2* sn, double2* g, int j, int 
 template<typename C> hipError_t k_cycle_start(const void* r, void* v0, const Cols& c, double2* g, int m, int* state,
                                               const double* target, int* kcyc, double* est, hipStream_t s);
 hipError_t k_lsq(const double2* H, const double2* g, double2* y, const int* kcyc, int m, int W, hipStream_t s);
+// out_w (+)= sum_{i < kcyc[w]} y[w][i] B_i[w]; kmax >= every kcyc[w], 1 <= kmax <= m
 template<typename C> hipError_t k_combine(const void* B, const Cols& c, const double2* y, const int* kcyc, int m,
-                                          void* out, int acc, hipStream_t s);
+                                          int kmax, void* out, int acc, hipStream_t s);
 template<typename C> hipError_t k_add_cols(void* dst, const void* src, const Cols& c, hipStream_t s);
 template<typename A, typename B> hipError_t k_scale_cols(const void* src, void* dst, const Cols& c, const double* sc,
                                                          int invert, hipStream_t s);

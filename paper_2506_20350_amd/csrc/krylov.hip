@@ -528,8 +528,10 @@ __global__ void lsq_kernel(const double2* __restrict__ H, const double2* __restr
     for (int i = k; i < m; ++i) yw[i] = make_double2(0.0, 0.0);
 }
 
-// out_w (+)= sum_{i < k_w} y[w][i] B_i[w]  (accumulate != 0 adds to out)
-template<typename C>
+// out_w (+)= sum_{i < k_w} y[w][i] B_i[w]  (accumulate != 0 adds to out).  KB >= every
+// k_w: the KB loads are issued unconditionally (index clamped to k_w - 1) so that
+// they are in flight together, with zero weights beyond k_w.
+template<typename C, int KB>
 __global__ void __launch_bounds__(256) combine_kernel(const C* __restrict__ B, size_t bstride,
                                                       const size_t* __restrict__ coff, const int* __restrict__ cN,
                                                       const double2* __restrict__ y, const int* __restrict__ kcyc,
@@ -539,14 +541,23 @@ __global__ void __launch_bounds__(256) combine_kernel(const C* __restrict__ B, s
     const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (size_t)cN[w]) return;
     const size_t o = coff[w] + n;
-    double2 acc = accumulate ? Acc<C>::w(out[o]) : make_double2(0.0, 0.0);
-    for (int i = 0; i < k; ++i) {
-        const double2 yi = y[(size_t)w * m + i];
-        const double2 b = Acc<C>::w(B[(size_t)i * bstride + o]);
-        acc.x += yi.x * b.x - yi.y * b.y;
-        acc.y += yi.x * b.y + yi.y * b.x;
+    if (k <= 0) {
+        if (!accumulate) out[o] = narrow<C>(make_double2(0.0, 0.0));
+        return;
     }
-    if (k > 0 || !accumulate) out[o] = narrow<C>(acc);
+    C bb[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) bb[i] = B[(size_t)(i < k ? i : k - 1) * bstride + o];
+    double2 acc = accumulate ? Acc<C>::w(out[o]) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+        const double2 yc = y[(size_t)w * m + (i < k ? i : k - 1)];
+        const double f = i < k ? 1.0 : 0.0;
+        const double2 b = Acc<C>::w(bb[i]);
+        acc.x += f * (yc.x * b.x - yc.y * b.y);
+        acc.y += f * (yc.x * b.y + yc.y * b.x);
+    }
+    out[o] = narrow<C>(acc);
 }
 
 // dst += src (per column, same precision)
@@ -694,10 +705,28 @@ hipError_t k_lsq(const double2* H, const double2* g, double2* y, const int* kcyc
 }
 
 template<typename C>
-hipError_t k_combine(const void* B, const Cols& c, const double2* y, const int* kcyc, int m, void* out, int acc,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(combine_kernel<C>, cols_grid(c.maxN, c.W), dim3(256), 0, s, (const C*)B, c.S, c.off, c.N, y,
-                       kcyc, m, (C*)out, acc);
+hipError_t k_combine(const void* B, const Cols& c, const double2* y, const int* kcyc, int m, int kmax, void* out,
+                     int acc, hipStream_t s) {
+    if (kmax < 1 || kmax > m || m > 31) return hipErrorInvalidValue;
+#define COMBINE(KB) \
+    hipLaunchKernelGGL((combine_kernel<C, KB>), cols_grid(c.maxN, c.W), dim3(256), 0, s, (const C*)B, c.S, c.off, \
+                       c.N, y, kcyc, m, (C*)out, acc)
+    switch (kmax) {
+        case 1: COMBINE(1); break;
+        case 2: COMBINE(2); break;
+        case 3: COMBINE(3); break;
+        case 4: COMBINE(4); break;
+        case 5: COMBINE(5); break;
+        case 6: COMBINE(6); break;
+        case 7: COMBINE(7); break;
+        case 8: COMBINE(8); break;
+        default:
+            if (kmax <= 12) COMBINE(12);
+            else if (kmax <= 16) COMBINE(16);
+            else if (kmax <= 24) COMBINE(24);
+            else COMBINE(32);
+    }
+#undef COMBINE
     return hipGetLastError();
 }
 
@@ -728,7 +757,7 @@ hipError_t k_axpy_cols(double2* x, const void* d, const Cols& c, const double* s
     template hipError_t k_arnoldi<C>(void*, int, const Cols&, double2*, int, const int*, int, hipStream_t);       \
     template hipError_t k_cycle_start<C>(const void*, void*, const Cols&, double2*, int, int*, const double*,     \
                                          int*, double*, hipStream_t);                                             \
-    template hipError_t k_combine<C>(const void*, const Cols&, const double2*, const int*, int, void*, int,       \
+    template hipError_t k_combine<C>(const void*, const Cols&, const double2*, const int*, int, int, void*, int,  \
                                      hipStream_t);                                                                \
     template hipError_t k_add_cols<C>(void*, const void*, const Cols&, hipStream_t);                              \
     template hipError_t k_axpy_cols<C>(double2*, const void*, const Cols&, const double*, const int*, int,       \

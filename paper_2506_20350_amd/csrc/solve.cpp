@@ -264,7 +264,8 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
             return e;
         };
         double run_elems = running_elems();
-        for (int j = 0; j < m;) {
+        int j = 0;          // steps taken in this cycle (no column has more)
+        while (j < m) {
             // one Krylov step: z_q = P^{-1} v_q, u = Z z_q, orthogonalise, rotate
             auto step = [&](int q) -> mlfft_status {
                 void* vq = (char*)w.Vb + (size_t)q * vb;
@@ -319,14 +320,14 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
         }
         HIPCHK(k_lsq(w.H, w.g, w.y, w.kcyc, m, Wt, s), "least squares");
         if (w.zstore) {
-            HIPCHK(k_combine<C>(w.Zb, cols, w.y, w.kcyc, m, w.dT, 1, s), "update");
+            HIPCHK(k_combine<C>(w.Zb, cols, w.y, w.kcyc, m, j, w.dT, 1, s), "update");
         } else if (o.precond) {
-            HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, w.tmpT, 0, s), "update");
+            HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, j, w.tmpT, 0, s), "update");
             STCHK(batch_precond(c, segs, o.precond, w.tmpT, w.tmp2T, nullptr, prec, nullptr));
             if (info) info->precond_applies += 1;
             HIPCHK(k_add_cols<C>(w.dT, w.tmp2T, cols, s), "update");
         } else {
-            HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, w.dT, 1, s), "update");
+            HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, j, w.dT, 1, s), "update");
         }
         // Every column reached its target by the residual estimate within this
         // cycle: the FP64 true residual of the outer loop judges the result, so
