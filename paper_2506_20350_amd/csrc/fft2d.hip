@@ -284,6 +284,110 @@ __global__ void __launch_bounds__(512) fft_inv_kernel(FftTask t0, const FftTask*
     dispatch_n<InvY, C, CLS>(t->Ny, tl, wk, tile);
 }
 
+// ---------------------------------------------------------------- inverse, half-height tile
+
+// The padded inverse (FP32) in two halves: the even-ky rows are transformed
+// along x into a tile of Ny rows and then along y into registers; the odd-ky
+// rows follow through the same tile and are added.  The tile is half as tall
+// as the one-pass kernel's, so two workgroups share a CU and one's loads overlap
+// the other's arithmetic.
+template<typename C, int NX>
+struct InvXHalf {
+    static __device__ __forceinline__ void run(const FftTask& tt, Work wk, C* tile, int par) {
+        const FftTask* t = &tt;
+        const int cm = t->cm, b = t->b, W = t->W;
+        const int Px = 2 * NX;
+        const int tid = threadIdx.x;
+        if (tid >= t->Ny * cm) return;
+        const int a = tid / cm, mi = tid - a * cm;
+        if (mi >= wk.mlen) return;
+        const int ky = 2 * a + par;
+        const C* __restrict__ src = static_cast<const C*>(t->in) + (size_t)wk.w * b + wk.m0 + mi;
+        const size_t ks = (size_t)W * b;
+        C v[NX], o[NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            v[i] = src[(size_t)(ky * Px + 2 * i) * ks];
+            o[i] = src[(size_t)(ky * Px + 2 * i + 1) * ks];
+        }
+        Fft<C, NX, 1>::run(v);
+        Fft<C, NX, 1>::run(o);
+        Fft<C, NX, 1>::tw2(o);
+        C* row = tile + a * t->rs + mi;
+#pragma unroll
+        for (int ix = 0; ix < NX; ++ix) row[ix * cm] = cadd(v[ix], o[ix]);
+    }
+};
+
+template<typename C, int NY>
+struct InvYHalf {
+    // par 0: e = the y-transform of the even rows; par 1: out = e + the twiddled
+    // y-transform of the odd rows, cropped, scaled and with the addend
+    static __device__ __forceinline__ void run(const FftTask& tt, Work wk, const C* tile, C* e, int par) {
+        const FftTask* t = &tt;
+        typedef typename CTraits<C>::real R;
+        const int Nx = t->Nx, cm = t->cm, b = t->b;
+        const int tid = threadIdx.x;
+        if (tid >= Nx * cm) return;
+        const int ix = tid / cm, mi = tid - ix * cm;
+        if (mi >= wk.mlen) return;
+        const C* col = tile + ix * cm + mi;
+        const int rs = t->rs;
+        C v[NY];
+#pragma unroll
+        for (int j = 0; j < NY; ++j) v[j] = col[j * rs];
+        Fft<C, NY, 1>::run(v);
+        if (par == 0) {
+#pragma unroll
+            for (int j = 0; j < NY; ++j) e[j] = v[j];
+            return;
+        }
+        Fft<C, NY, 1>::tw2(v);
+#pragma unroll
+        for (int iy = 0; iy < NY; ++iy) v[iy] = cadd(v[iy], e[iy]);
+        const size_t off = ((size_t)wk.w * NY * Nx + ix) * b + wk.m0 + mi;
+        const size_t ys = (size_t)Nx * b;
+        C* __restrict__ dst = static_cast<C*>(t->out) + off;
+        const R alpha = (R)t->alpha;
+        if (t->addend) {
+            const C* __restrict__ add = static_cast<const C*>(t->addend) + off;
+            const R beta = (R)t->beta;
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy) {
+                const C a = add[iy * ys];
+                dst[iy * ys] = cmake<C>(v[iy].x * alpha + a.x * beta, v[iy].y * alpha + a.y * beta);
+            }
+        } else {
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy) dst[iy * ys] = cscale(v[iy], alpha);
+        }
+    }
+};
+
+template<typename C, int CLS>
+__global__ void __launch_bounds__(512) fft_inv_half_kernel(FftTask t0, const FftTask* tasks, int ntasks) {
+    extern __shared__ unsigned char smem_raw[];
+    C* tile = reinterpret_cast<C*>(smem_raw);
+    const int bid = work_index();
+    FftTask tl = ntasks > 0 ? *find_task(tasks, ntasks, bid) : t0;
+    tl.pad = 1;
+    const FftTask* t = &tl;
+    const int local = bid - t->block_begin;
+    Work wk;
+    wk.w = local / t->nmc;
+    const int mc = local - wk.w * t->nmc;
+    wk.m0 = mc * t->cm;
+    wk.mlen = min(t->cm, t->b - wk.m0);
+    C e[32];
+    dispatch_n<InvXHalf, C, CLS>(t->Nx, tl, wk, tile, 0);
+    __syncthreads();
+    dispatch_n<InvYHalf, C, CLS>(t->Ny, tl, wk, (const C*)tile, e, 0);
+    __syncthreads();
+    dispatch_n<InvXHalf, C, CLS>(t->Nx, tl, wk, tile, 1);
+    __syncthreads();
+    dispatch_n<InvYHalf, C, CLS>(t->Ny, tl, wk, (const C*)tile, e, 1);
+}
+
 // ---------------------------------------------------------------- host side
 
 static const size_t kLdsBudget = 160 * 1024;
@@ -380,6 +484,12 @@ static FftKernel pick_kernel(int cls, int pad) {
     return nullptr;
 }
 
+static FftKernel pick_inv_half(int cls) {
+    FftKernel k = cls == 0 ? (FftKernel)fft_inv_half_kernel<float2, 0> : (FftKernel)fft_inv_half_kernel<float2, 1>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+    return k;
+}
+
 template<typename C, int INV>
 static hipError_t launch_t(const FftTask* th, const FftTask* td, int ntasks, hipStream_t s) {
     // the host copy is already planned (cm, nmc, block_begin filled)
@@ -387,10 +497,16 @@ static hipError_t launch_t(const FftTask* th, const FftTask* td, int ntasks, hip
     size_t lds = 0;
     const int eb = sizeof(C);
     const int prec = sizeof(C) == 16 ? P64 : P32;
+    // the padded FP32 inverse runs with the half-height tile, except for the prime
+    // lengths 17..31, whose direct DFTs would then spill registers (the forward,
+    // bound by its scattered spectrum stores, gained nothing from it)
+    bool half = INV && prec == P32 && ntasks > 0 && th[0].pad;
+    for (int i = 0; i < ntasks && half; ++i)
+        half = std::max(len_class(th[i].Nx), len_class(th[i].Ny)) <= 1;
     for (int i = 0; i < ntasks; ++i) {
         const FftTask& t = th[i];
         if (t.pad != th[0].pad) return hipErrorInvalidValue;
-        const int Py = tile_rows(prec, t.pad, t.Ny);
+        const int Py = half ? t.Ny : tile_rows(prec, t.pad, t.Ny);
         grid = t.block_begin + t.nmc * t.W > grid ? t.block_begin + t.nmc * t.W : grid;
         int thr = ((Py > t.Nx ? Py : t.Nx) * t.cm + 63) / 64 * 64;
         if (thr > block) block = thr;
@@ -399,7 +515,7 @@ static hipError_t launch_t(const FftTask* th, const FftTask* td, int ntasks, hip
         cls = std::max(cls, std::max(len_class(t.Nx), len_class(t.Ny)));
     }
     if (grid == 0) return hipSuccess;
-    FftKernel k = pick_kernel<C, INV>(cls, th[0].pad);
+    FftKernel k = half ? pick_inv_half(cls) : pick_kernel<C, INV>(cls, th[0].pad);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, s, th[0], ntasks > 1 ? td : nullptr, ntasks > 1 ? ntasks : 0);
     return hipGetLastError();

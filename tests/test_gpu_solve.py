@@ -386,3 +386,19 @@ def test_batch_with_an_all_zero_array_and_two_refinement_steps(ctx):
     assert torch.count_nonzero(Is[1]) == 0
     assert relerr(to_host(Is[0]), refs[0]) <= 1e-9
     assert np.all(info["relres"] <= 1e-11)
+
+
+@pytest.mark.parametrize("pc", [0, 1])
+def test_fp32_restarted_inner_solve_matches_lu(ctx, pc):
+    """GMRES(3) in FP32: the inner solve restarts, so its restart residual r - Z d runs
+    through the FP32 inverse transform's y = alpha Z x + beta addend epilogue."""
+    Nx, Ny, b = 6, 5, 16
+    blocks = synth.green_blocks(Nx, Ny, b, 0.9 * np.pi, seed=21)
+    V = synth.port_rhs(Nx, Ny, b, cols=[0, 7, 14, 29])
+    ctx.set_blocks(60, blocks)
+    I, info = ctx.solve(60, to_dev(V), tol=1e-10, inner_prec="fp32", precond=pc, restart=3)
+    assert info["status"] == abi.MLFFT_OK
+    assert info["iters"].max() > 3                  # more than one cycle
+    ref = direct.lu_solve(tp.dense_Z(blocks), V)
+    assert relerr(to_host(I), ref) <= 1e-8
+    assert np.all(info["relres"] <= 1e-10)
