@@ -495,7 +495,36 @@ __global__ void __launch_bounds__(256) bgemm_f64_3m_flat_kernel(GemmTask t0, con
             pre[i] = (p < npan && e < have) ? gload(src + e) : make_double2(0.0, 0.0);
         }
     };
+    // The products of a tile are stored one step late, after the loads of the
+    // next tile's prefetch have been issued: the wait for that prefetch (one
+    // counter covers loads and stores) then finds these stores long complete
+    // instead of waiting for stores issued just before it.
+    doublex4 t1[NT / 16], t2[NT / 16], t3[NT / 16];
+    int wdone = -1;
+    auto store = [&]() {
+#pragma unroll
+        for (int cg = 0; cg < NT / 16; ++cg) {
+            const int w = wdone + cg * 16 + j;
+            if (w < W) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = m_base + 4 * r + q;
+                    if (m < b) {
+                        const double re = t1[cg][r] - t2[cg][r];
+                        const double im = t3[cg][r] - t1[cg][r] - t2[cg][r];
+                        gstore(Yk + (size_t)w * b + m, make_double2(re, im));
+                    }
+                }
+            }
+        }
+        wdone = -1;
+    };
     fetch(0);
+    // Everything loaded so far (the stationary G fragments and the first tile) is
+    // waited for here, once: otherwise the compiler's wait before the first use
+    // of a G fragment inside the loop covers the loads of the next tile too, and
+    // the prefetch never overlaps the products.
+    __builtin_amdgcn_s_waitcnt(0);
     for (int w0 = 0; w0 < W; w0 += NT) {
         __syncthreads();
 #pragma unroll
@@ -510,8 +539,8 @@ __global__ void __launch_bounds__(256) bgemm_f64_3m_flat_kernel(GemmTask t0, con
         __syncthreads();
         if (w0 + NT < W) fetch(w0 + NT);
         if (active) {
+            if (wdone >= 0) store();
             const double* __restrict__ xp = xs + pan * NT * ldx;
-            doublex4 t1[NT / 16], t2[NT / 16], t3[NT / 16];
 #pragma unroll
             for (int cg = 0; cg < NT / 16; ++cg) {
                 t1[cg] = doublex4{0, 0, 0, 0};
@@ -529,23 +558,10 @@ __global__ void __launch_bounds__(256) bgemm_f64_3m_flat_kernel(GemmTask t0, con
                     t3[cg] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, u.x + u.y, t3[cg], 0, 0, 0);
                 }
             }
-#pragma unroll
-            for (int cg = 0; cg < NT / 16; ++cg) {
-                const int w = w0 + cg * 16 + j;
-                if (w < W) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int m = m_base + 4 * r + q;
-                        if (m < b) {
-                            const double re = t1[cg][r] - t2[cg][r];
-                            const double im = t3[cg][r] - t1[cg][r] - t2[cg][r];
-                            gstore(Yk + (size_t)w * b + m, make_double2(re, im));
-                        }
-                    }
-                }
-            }
+            wdone = w0;
         }
     }
+    if (active && wdone >= 0) store();
 }
 
 // ------------------------------------------------------------------ BF16
