@@ -92,8 +92,13 @@ GATE = 0.9   # the correction is used only if it lowers the held-out loss to bel
 
 
 def prepare(ctx: Context, cfg: dict, train_grid: int = 20, hidden: int = 64, steps: int = 300, log=None,
-            array_id: int = 100, lr: float = 2e-3):
+            array_id: int = 100, lr: float = 3e-4):
     """Build and train the network for the element of `cfg` (b, kd, seed) on a train_grid^2 array.
+
+    The last layer starts at zero, so Adam's first steps move all its weights by
+    about lr at once; at the benchmark's scale (a correction of a few percent of
+    the preconditioner output) lr = 2e-3 overshoots and the network settles back
+    near the identity, while 3e-4 keeps the held-out loss falling.
 
     Returns a dict with the training record; its "enabled" entry says whether the
     trained correction beat the plain block-circulant output on held-out pairs
