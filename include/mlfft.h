@@ -265,7 +265,7 @@ mlfft_status mlfft_net_train_step(mlfft_ctx ctx, int W, int H, int Wd, const voi
 /* Time the candidate launch shapes of the MLFFT block product (waves per
  * workgroup x columns per LDS tile x product form: four real products, three
  * real products, three real products with a flat assignment of (frequency,
- * 16-row slice) items to eight-wave workgroups) and of the 2-D FFTs (basis functions per
+ * 16-row slice) items to eight- or four-wave workgroups) and of the 2-D FFTs (basis functions per
  * workgroup, for the MLFFT grid and the preconditioner torus) on array
  * array_id with W columns in precision prec, `reps` timed runs each, and keep
  * the fastest for the rest of the process (all contexts).  Blocking; overwrites
@@ -278,7 +278,8 @@ mlfft_status mlfft_tune_report(mlfft_ctx ctx, int array_id, char* buf, size_t n)
 
 /* Re-apply choices from text in the format of mlfft_tune_report(): lines
  * "gemm prec bp waves nt form" (form 0 four products, 1 three products, 2 three
- * products with the flat assignment, which needs prec 1, waves 8, nt 32) and
+ * products with the flat assignment, which takes prec 1 with waves 8 and nt 32
+ * or 16, prec 1 with waves 4 and nt 16, or prec 0 with waves 4 and nt 16) and
  * "fftcm prec pad Nx Ny b cm"; other lines are ignored.  MLFFT_E_ARG for a
  * malformed gemm or fftcm line. */
 mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text);

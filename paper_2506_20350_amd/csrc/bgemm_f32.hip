@@ -37,12 +37,12 @@ static hipError_t launch_3m_cfg(const GemmTask& t0, const GemmTask* td, int n, i
     return hipGetLastError();
 }
 
-template<int BP, int NT, int TAG = 0, int DB = 0>
+template<int BP, int NT, int TAG = 0, int DB = 0, int WAVES = 8>
 static hipError_t launch_3m_flat_cfg(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
     const size_t lds = (size_t)(DB ? 4 : 2) * NT * (2 * BP + 2) * sizeof(float);
-    auto k = bgemm_f32_3m_flat_kernel<BP, NT, TAG, DB>;
+    auto k = bgemm_f32_3m_flat_kernel<BP, NT, TAG, DB, WAVES>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(512), lds, s, t0, td, n);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WAVES), lds, s, t0, td, n);
     return hipGetLastError();
 }
 
@@ -53,8 +53,10 @@ static hipError_t launch_f32(GemmShape sh, int tag, const GemmTask& t0, const Ge
     if (tag)      // preconditioner: fixed shape (flat unless some b is below 97)
         return sh.m3 == 2 ? launch_3m_flat_cfg<B16, 32, 1>(t0, td, n, grid, s)
                           : launch_3m_cfg<B16, 32, 8, 1>(t0, td, n, grid, s);
-    if (sh.m3 == 2)
+    if (sh.m3 == 2) {
+        if (sh.waves == 4) return launch_3m_flat_cfg<B16, 16, 0, 0, 4>(t0, td, n, grid, s);
         return sh.nt == 16 ? launch_3m_flat_cfg<B16, 16, 0, 1>(t0, td, n, grid, s) : launch_3m_flat_cfg<B16, 32>(t0, td, n, grid, s);
+    }
     if (sh.m3) {
         if (sh.waves == 4)
             return sh.nt == 64 ? launch_3m_cfg<B16, 64, 4>(t0, td, n, grid, s) : launch_3m_cfg<B16, 32, 4>(t0, td, n, grid, s);

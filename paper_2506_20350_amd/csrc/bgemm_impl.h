@@ -288,14 +288,16 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_f32_3m_kernel(GemmTask t0, c
 
 // Three-product form with a flat assignment of work to waves.  The K * ns
 // (frequency, 16-row slice) items of a task, ns = ceil(b / 16), are dealt to
-// the waves of consecutive workgroups, eight per workgroup, so that no wave is
-// idle whatever ns is (with one workgroup per frequency row group, b = 200 has
-// 13 slices for 16 wave slots).  A workgroup then spans at most two
-// frequencies and stages the X tiles of both; Gr + Gi is formed from the
-// register-resident Gr, Gi fragments at each reduction step.
-template<int BP, int NT, int TAG, int DB>
-__global__ void __launch_bounds__(512) bgemm_f32_3m_flat_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
-    constexpr int WAVES = 8, NTH = 64 * WAVES;
+// the waves of consecutive workgroups, WAVES (eight or four) per workgroup, so
+// that no wave is idle whatever ns is (with one workgroup per frequency row
+// group, b = 200 has 13 slices for 16 wave slots).  A workgroup then spans at
+// most two frequencies and stages the X tiles of both; Gr + Gi is formed from
+// the register-resident Gr, Gi fragments at each reduction step.  Eight waves
+// fill a CU with one workgroup; four waves with 16-column tiles leave room for
+// two, so one's tile staging overlaps the other's products.
+template<int BP, int NT, int TAG, int DB, int WAVES = 8>
+__global__ void __launch_bounds__(64 * WAVES, 2) bgemm_f32_3m_flat_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
+    constexpr int NTH = 64 * WAVES;
     constexpr int PF = (NT * BP + NTH - 1) / NTH;      // prefetched complex values per thread and panel
     extern __shared__ unsigned char smem_raw[];
     float* xs = reinterpret_cast<float*>(smem_raw);     // [buffer][panel][NT][ldx]

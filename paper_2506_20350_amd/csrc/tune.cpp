@@ -74,12 +74,17 @@ mlfft_status mlfft_autotune(mlfft_ctx ctx, int array_id, int W, int prec, int re
     if (prec != PBF16) {
         for (int m3 : {0, 1, 2}) for (int waves : {4, 8}) {
             if (m3 == 1 && prec != P32) continue;
-            // the flat three-product kernels run eight waves (FP32) or four (FP64)
-            if (m3 == 2 && waves != (prec == P32 ? 8 : 4)) continue;
+            // the flat three-product kernels run eight or four waves (FP32, four with
+            // 16-column tiles only) or four (FP64)
+            if (m3 == 2 && prec == P64 && waves != 4) continue;
             for (int ci = 0; ci < 3; ++ci) {
                 const int nt = ntc[ci];
-                // nt 16 is only a shape of the flat FP32 kernel (double-buffered tiles)
+                // nt 16 is only a shape of the flat FP32 kernel (eight waves: double-buffered
+                // tiles; four waves: single-buffered, two workgroups per CU)
                 if (ci == 2 && !(m3 == 2 && prec == P32)) continue;
+                // four waves: only where the eight-wave flat kernel cannot run (fewer than
+                // seven 16-row slices); at larger b its tiles are re-read from HBM more
+                if (m3 == 2 && prec == P32 && waves == 4 && (nt != 16 || (a->b + 15) / 16 >= 7)) continue;
                 if (m3 == 2 && prec == P64 && nt != 16) continue;
                 if (m3 == 2 && prec == P32 && nt == 64) continue;
                 gemm_set_shape(prec, bp, waves, nt, m3);
@@ -169,7 +174,8 @@ mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text) {
             const bool ok = a1 >= 0 && a1 <= 2 && a2 >= 8 && a2 <= 256 && a2 % 8 == 0 && (a3 == 4 || a3 == 8) &&
                             (a4 == 16 || a4 == 32 || a4 == 64) &&
                             (a5 == 0 || (a5 == 1 && a1 == 1) || (a5 == 2 && a1 == 1 && a3 == 8 && a4 == 32) ||
-                             (a5 == 2 && a1 == 1 && a3 == 8 && a4 == 16) || (a5 == 2 && a1 == 0 && a3 == 4 && a4 == 16));
+                             (a5 == 2 && a1 == 1 && a3 == 8 && a4 == 16) || (a5 == 2 && a1 == 1 && a3 == 4 && a4 == 16) ||
+                             (a5 == 2 && a1 == 0 && a3 == 4 && a4 == 16));
             if (!ok) return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
             gemm_set_shape(a1, a2, a3, a4, a5);
         } else if (sscanf(ln.c_str(), "fftcm %d %d %d %d %d %d", &a1, &a2, &a3, &a4, &a5, &a6) == 6) {

@@ -158,7 +158,7 @@ def test_full_size_30x30_b120_sampled_columns(ctx, prec):
 
 
 @pytest.mark.parametrize("b", [8, 24, 120, 200, 13])
-@pytest.mark.parametrize("shape", ["4 32 1", "8 64 1", "4 64 0", "8 32 0", "8 32 2", "8 16 2"])
+@pytest.mark.parametrize("shape", ["4 32 1", "8 64 1", "4 64 0", "8 32 0", "8 32 2", "8 16 2", "4 16 2"])
 def test_block_product_shapes_match_oracle(ctx, b, shape):
     """Every launch shape the autotuner can pick, including the three-product FP32 form."""
     Nx, Ny, W = 3, 4, 70
