@@ -172,6 +172,8 @@ mlfft_status Ctx::gemm_grouped(int prec, std::vector<GemmTask>& gm, int tag, con
 // occupancy.
 mlfft_status Ctx::fft_grouped(int prec, std::vector<FftTask>& tasks, bool inverse, const char* what) {
     Ctx* c = this;
+    // the transforms of the bf16-product forms are FP32 (and tuned as such)
+    if (prec == PBF16) prec = P32;
     std::map<int, std::vector<FftTask>> groups;
     for (const FftTask& t : tasks) groups[fft_group_key(prec, t)].push_back(t);
     for (auto& kv : groups) {

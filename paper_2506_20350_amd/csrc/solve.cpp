@@ -239,7 +239,9 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
     const int Wt = cols.W;      // Krylov columns (1 in the global mode)
     int* pinned_state = c->pinned_state(Wt);
     if (!pinned_state) return c->fail(MLFFT_E_NOMEM, "pinned host buffer");
-    HIPCHK(hipMemsetAsync(w.dT, 0, vb, s), "zero d");
+    // d starts at zero: the first cycle's combination writes it instead of
+    // adding to it (d_written), and d is cleared only if no cycle ran
+    bool d_written = false;
     HIPCHK(hipMemsetAsync(w.kcyc, 0, Wt * sizeof(int), s), "zero k");
     for (int cyc = 0; cyc < o.max_restarts; ++cyc) {
         const void* res = w.rT;
@@ -319,21 +321,24 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
             run_elems = running_elems();
         }
         HIPCHK(k_lsq(w.H, w.g, w.y, w.kcyc, m, Wt, s), "least squares");
+        const int acc = d_written ? 1 : 0;
         if (w.zstore) {
-            HIPCHK(k_combine<C>(w.Zb, cols, w.y, w.kcyc, m, j, w.dT, 1, s), "update");
+            HIPCHK(k_combine<C>(w.Zb, cols, w.y, w.kcyc, m, j, w.dT, acc, s), "update");
         } else if (o.precond) {
             HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, j, w.tmpT, 0, s), "update");
-            STCHK(batch_precond(c, segs, o.precond, w.tmpT, w.tmp2T, nullptr, prec, nullptr));
+            STCHK(batch_precond(c, segs, o.precond, w.tmpT, d_written ? w.tmp2T : w.dT, nullptr, prec, nullptr));
             if (info) info->precond_applies += 1;
-            HIPCHK(k_add_cols<C>(w.dT, w.tmp2T, cols, s), "update");
+            if (d_written) HIPCHK(k_add_cols<C>(w.dT, w.tmp2T, cols, s), "update");
         } else {
-            HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, j, w.dT, 1, s), "update");
+            HIPCHK(k_combine<C>(w.Vb, cols, w.y, w.kcyc, m, j, w.dT, acc, s), "update");
         }
+        d_written = true;
         // Every column reached its target by the residual estimate within this
         // cycle: the FP64 true residual of the outer loop judges the result, so
         // no inner restart residual is formed.
         if (running == 0) break;
     }
+    if (!d_written) HIPCHK(hipMemsetAsync(w.dT, 0, vb, s), "zero d");
     (void)hstate;
     return MLFFT_OK;
 }
