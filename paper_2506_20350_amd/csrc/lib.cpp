@@ -3,6 +3,7 @@
 // driver lives in solve.cpp.
 #include "lib.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -122,24 +123,43 @@ int prec_elem_bytes(int prec) { return prec == P64 ? 16 : 8; }
 // ------------------------------------------------------------------ matvec core
 
 mlfft_status Ctx::upload_tasks(const void* host, size_t bytes, void** dev) {
-    // Task tables are small and a solve reuses the same few tables every
-    // iteration: keep each distinct table resident on the device, uploaded once
-    // with a blocking copy (so the host blob may be freed at once).
+    // Task tables are small and repeated solves reuse the same tables: each
+    // distinct table is kept resident in a device arena.  A new one is copied
+    // into the pinned staging arena and from there to the device with an
+    // asynchronous copy on the stream, ordered before the launch that reads it,
+    // so the stream does not drain.  A staging slot is written once per arena
+    // cycle; starting a new cycle drains the stream first.
     Ctx* c = this;
     std::string key((const char*)host, bytes);
-    for (auto& e : task_cache)
-        if (e.first == key) { *dev = e.second.p; return MLFFT_OK; }
+    auto it = task_cache.find(key);
+    if (it != task_cache.end()) {
+        *dev = (char*)task_dev.p + it->second;
+        return MLFFT_OK;
+    }
     // a graph capture replays only launches whose tables are already resident
     if (capturing) return fail(MLFFT_E_STATE, "task table not resident during graph capture");
-    if (task_cache.size() >= 256) {
-        HIPCHK(hipStreamSynchronize(stream), "task cache flush");
+    const size_t need = (bytes + 255) / 256 * 256;
+    if (!task_host || task_used + need > task_cap) {
+        HIPCHK(hipStreamSynchronize(stream), "task arena");
         task_cache.clear();
+        task_used = 0;
+        ++g_mem_epoch;                  // graphs may hold addresses of the old tables
+        if (need > task_cap) {
+            const size_t cap = std::max<size_t>(need, std::max<size_t>(8u << 20, 2 * task_cap));
+            if (task_host) (void)hipHostFree(task_host);
+            task_host = nullptr;
+            task_cap = 0;
+            HIPCHK(task_dev.ensure(cap), "task arena");
+            HIPCHK(hipHostMalloc((void**)&task_host, cap, hipHostMallocDefault), "task arena");
+            task_cap = cap;
+        }
     }
-    task_cache.emplace_back(key, Buf());
-    Buf& b = task_cache.back().second;
-    HIPCHK(b.ensure(bytes), "task table");
-    HIPCHK(hipMemcpy(b.p, host, bytes, hipMemcpyHostToDevice), "task table upload");
-    *dev = b.p;
+    std::memcpy(task_host + task_used, host, bytes);
+    HIPCHK(hipMemcpyAsync((char*)task_dev.p + task_used, task_host + task_used, bytes, hipMemcpyHostToDevice, stream),
+           "task table upload");
+    task_cache.emplace(std::move(key), task_used);
+    *dev = (char*)task_dev.p + task_used;
+    task_used += need;
     return MLFFT_OK;
 }
 

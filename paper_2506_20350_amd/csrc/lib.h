@@ -1,6 +1,7 @@
 // Host-side state of the MLFFT library (contexts, arrays, workspaces).
 #pragma once
 #include <map>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -72,7 +73,13 @@ struct mlfft_ctx_s {
     std::string err;
     std::map<int, mlfft::Array> arrays;
     mlfft::Buf spec_a, spec_b;     // spectral workspaces of the matvec / preconditioner
-    std::vector<std::pair<std::string, mlfft::Buf>> task_cache;   // device copies of grouped-launch task tables
+    // Device copies of grouped-launch task tables, by content: offsets into the
+    // device arena task_dev, filled by asynchronous copies from the pinned
+    // staging arena task_host (same layout); task_used bytes of task_cap in use.
+    std::unordered_map<std::string, size_t> task_cache;
+    mlfft::Buf task_dev;
+    unsigned char* task_host = nullptr;
+    size_t task_cap = 0, task_used = 0;
     mlfft::Buf solve_ws;           // Krylov workspace (solve.cpp)
     mlfft::Buf solve_ws2;
     int* pinned = nullptr;         // pinned host buffer for per-column state read-back
@@ -117,7 +124,12 @@ struct mlfft_ctx_s {
     mlfft_status precond_group(const std::vector<mlfft::MatvecItem>& items, int kind, int prec);
     void release_workspaces() {
         graphs_release();
-        spec_a.release(); spec_b.release(); task_cache.clear(); solve_ws.release(); solve_ws2.release();
+        spec_a.release(); spec_b.release(); solve_ws.release(); solve_ws2.release();
+        task_cache.clear();
+        task_dev.release();
+        if (task_host) (void)hipHostFree(task_host);
+        task_host = nullptr;
+        task_cap = task_used = 0;
         if (pinned) (void)hipHostFree(pinned);
         pinned = nullptr;
         pinned_n = 0;
