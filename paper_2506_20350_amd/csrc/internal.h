@@ -27,6 +27,7 @@ struct FftTask {
     int nmc;                // number of m chunks
     int block_begin;        // first workgroup of this task in the grouped grid
     int pad;
+    int reserved = 0;       // fills the tail: a task's bytes are all defined (tables are cached by content)
 };
 
 // One array's share of a grouped per-frequency block product
@@ -39,7 +40,12 @@ struct GemmTask {
     int K, b, W;
     int mgroups;            // workgroups per frequency (row groups)
     int block_begin;
+    int reserved = 0;       // fills the tail, as in FftTask
 };
+
+// no padding bytes: the members add up to the size
+static_assert(sizeof(FftTask) == 5 * 8 + 10 * 4, "FftTask must have no padding");
+static_assert(sizeof(GemmTask) == 4 * 8 + 6 * 4, "GemmTask must have no padding");
 
 enum Prec { P64 = 0, P32 = 1, PBF16 = 2 };
 
