@@ -40,9 +40,10 @@ static hipError_t launch_real(GemmShape sh, int tag, const GemmTask& t0, const G
 template<int BP>
 static hipError_t launch_f64(GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
                              hipStream_t s) {
-    constexpr int B16 = (BP + 15) / 16 * 16;
+    // the flat kernel slices rows at run time and only needs the reduction length
+    // padded to a multiple of 8
     if (sh.m3 == 2)
-        return tag ? launch_3m_flat_cfg<B16, 16, 1>(t0, td, n, grid, s) : launch_3m_flat_cfg<B16, 16>(t0, td, n, grid, s);
+        return tag ? launch_3m_flat_cfg<BP, 16, 1>(t0, td, n, grid, s) : launch_3m_flat_cfg<BP, 16>(t0, td, n, grid, s);
     return launch_real<double, BP>(sh, tag, t0, td, n, grid, s);
 }
 
