@@ -286,6 +286,12 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_f32_3m_kernel(GemmTask t0, c
     }
 }
 
+typedef float mlfft_f4v __attribute__((ext_vector_type(4)));
+// two consecutive complex values with one 16-byte global store (p 16-byte aligned)
+__device__ __forceinline__ void gstore2(float2* p, float2 a, float2 b) {
+    *(MLFFT_GLOBAL mlfft_f4v*)p = mlfft_f4v{a.x, a.y, b.x, b.y};
+}
+
 // Three-product form with a flat assignment of work to waves.  The K * ns
 // (frequency, 16-row slice) items of a task, ns = ceil(b / 16), are dealt to
 // the waves of consecutive workgroups, WAVES (eight or four) per workgroup, so
@@ -320,6 +326,8 @@ __global__ void __launch_bounds__(64 * WAVES, 2) bgemm_f32_3m_flat_kernel(GemmTa
     const int kw = active ? gs / ns : kA;
     const int m_base = (gs - kw * ns) * 16;
     const int pan = kw - kA;
+    // every row of the wave's slice exists and rows of an even b keep 16-byte alignment
+    const bool full16 = m_base + 16 <= b && (b & 1) == 0;
     const int ldx = 2 * BP + 2;
     float ar[BP / 4], ai[BP / 4];
     {
@@ -409,14 +417,20 @@ __global__ void __launch_bounds__(64 * WAVES, 2) bgemm_f32_3m_flat_kernel(GemmTa
             for (int cg = 0; cg < NT / 16; ++cg) {
                 const int w = w0 + cg * 16 + j;
                 if (w < W) {
+                    float2 o[4];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int m = m_base + 4 * q + r;
-                        if (m < b) {
-                            const float re = t1[cg][r] - t2[cg][r];
-                            const float im = t3[cg][r] - t1[cg][r] - t2[cg][r];
-                            gstore(Yk + (size_t)w * b + m, make_float2(re, im));
-                        }
+                    for (int r = 0; r < 4; ++r)
+                        o[r] = make_float2(t1[cg][r] - t2[cg][r], t3[cg][r] - t1[cg][r] - t2[cg][r]);
+                    const int m0 = m_base + 4 * q;
+                    float2* dst = Yk + (size_t)w * b + m0;
+                    if (full16) {
+                        // the lane's four rows are 32 contiguous bytes: two 16-byte stores
+                        gstore2(dst, o[0], o[1]);
+                        gstore2(dst + 2, o[2], o[3]);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (m0 + r < b) gstore(dst + r, o[r]);
                     }
                 }
             }
