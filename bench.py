@@ -375,8 +375,9 @@ def main():
                     help="only run a plain 1 GiB device copy kernel (for HBM counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this build "
-              "(the path would shard right-hand sides across GPUs, see the design notes).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported (across GPUs the solve "
+              "would shard by right-hand side: every GPU holding the spectra and solving its share of "
+              "the columns).", file=sys.stderr)
         sys.exit(2)
 
     import torch

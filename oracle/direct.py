@@ -25,8 +25,8 @@ class SingularSection(np.linalg.LinAlgError):
 
 def _inv_checked(A: np.ndarray, what: str, rcond_min: float) -> np.ndarray:
     # The recursion needs every leading block section nonsingular; the paper
-    # states it for invertible blocks, the bordering steps need more (reading
-    # documented in the design notes): check the reciprocal condition number.
+    # states it for invertible blocks, the bordering steps need more (our
+    # reading): check the reciprocal condition number.
     c = np.linalg.cond(A, 1)
     if not np.isfinite(c) or 1.0 / c < rcond_min:
         raise SingularSection(f"{what} is singular (rcond {0.0 if not np.isfinite(c) else 1.0 / c:.2e})")
