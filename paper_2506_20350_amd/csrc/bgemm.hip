@@ -25,6 +25,10 @@ static GemmShape default_shape(int prec, int bp) {
 GemmShape gemm_shape(int prec, int bp, int tag) {
     if (tag) {
         if (prec == P64) return GemmShape{4, 16, 2};
+        // the FP32 preconditioner product takes the tile shape tuned for the MLFFT
+        // product of the same b when that is an eight-wave flat shape
+        const GemmShape& o = g_shape_override[prec][bp / 8];
+        if (prec == P32 && o.m3 == 2 && o.waves == 8) return o;
         return GemmShape{8, prec == P32 ? 32 : 64, prec == P32 ? 2 : 0};
     }
     const GemmShape& o = g_shape_override[prec][bp / 8];

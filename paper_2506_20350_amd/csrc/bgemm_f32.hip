@@ -53,7 +53,8 @@ static hipError_t launch_f32(GemmShape sh, int tag, const GemmTask& t0, const Ge
     // the flat kernels slice rows at run time and only need the reduction
     // length padded to a multiple of 8 (b = 200: 50 reduction steps, not 52)
     if (tag)      // preconditioner: fixed shape (flat unless some b is below 97)
-        return sh.m3 == 2 ? launch_3m_flat_cfg<BP, 32, 1>(t0, td, n, grid, s)
+        return sh.m3 == 2 ? (sh.nt == 16 ? launch_3m_flat_cfg<BP, 16, 1, 1>(t0, td, n, grid, s)
+                                         : launch_3m_flat_cfg<BP, 32, 1>(t0, td, n, grid, s))
                           : launch_3m_cfg<B16, 32, 8, 1>(t0, td, n, grid, s);
     if (sh.m3 == 2) {
         if (sh.waves == 4) return launch_3m_flat_cfg<BP, 16, 0, 0, 4>(t0, td, n, grid, s);
