@@ -58,6 +58,7 @@ FORMS = {
 DTYPE = {"fp32": "f32+f64", "bf16": "bf16xf32+f64", "fp64": "f64", "learned": "f32+bf16+f64",
          "learned_forced": "f32+bf16+f64", "fp32_global": "f32+f64"}
 GATED = {}   # form -> replacement options when the learned correction is gated off
+PC_BF16 = [0]   # 1: FP32 inner forms run the preconditioner's block product in bf16 (--pc-prec bf16)
 
 
 def log(*a):
@@ -72,6 +73,8 @@ def timed_solves(ctx, aid, Vd, steps, warmup, form, tol, torch, inner_tol=None, 
         opts["orth"] = orth
     if inner_tol is not None and opts["inner_prec"] != "fp64":
         opts["inner_tol"] = inner_tol
+    if PC_BF16[0] and opts["inner_prec"] == "fp32":
+        opts["pc_bf16"] = 1
     I = torch.zeros_like(Vd)
     info = None
     for _ in range(warmup):
@@ -219,6 +222,8 @@ def bench_batch(a, torch):
     form = a.form if a.form in ("fp32", "fp64", "bf16") else "fp32"
     opts = dict(FORMS[form])
     opts.pop("label")
+    if PC_BF16[0] and opts["inner_prec"] == "fp32":
+        opts["pc_bf16"] = 1
     tune_s = None
     if not a.no_tune:
         # the block-product shape is tuned per padded b: one representative array (the largest) per b
@@ -277,7 +282,7 @@ def bench_batch(a, torch):
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype=DTYPE[form], data="synthetic",
                config=dict(workload=f"64 arrays, Nx,Ny in [4,24], b in {{24,48,64,96}}, kd in [pi/2,pi], "
                                     f"{Wt} port RHS in one batched solve, {FORMS[form]['label']}, tol {a.tol:g}",
-                           arrays=len(specs), W_total=Wt, form=form, tol=a.tol),
+                           arrays=len(specs), W_total=Wt, form=form, tol=a.tol, pc_prec=a.pc_prec),
                roofline=roof,
                roofline_kernel=dict(name=dom["name"], prec=dom["prec"], launches=dom["launches"],
                                     avg_ms=round(dom["ms"] / dom["launches"], 4)),
@@ -361,6 +366,8 @@ def main():
                          "c1, c2: latency of the small cases, eager and with graph-captured Krylov steps")
     ap.add_argument("--form", choices=sorted(FORMS), default="learned")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--pc-prec", choices=["fp32", "bf16"], default="bf16",
+                    help="block-product precision of the preconditioner in the FP32 inner forms")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="residual reduction asked of each FP32 inner solve (library default if omitted)")
     ap.add_argument("--compare", default="fp64,fp32,learned_forced,fp32_global",
@@ -379,6 +386,7 @@ def main():
               "would shard by right-hand side: every GPU holding the spectra and solving its share of "
               "the columns).", file=sys.stderr)
         sys.exit(2)
+    PC_BF16[0] = int(a.pc_prec == "bf16")
 
     import torch
     if a.calib_copy:
@@ -448,7 +456,8 @@ def main():
                vs_baseline=None, dtype=DTYPE[a.form], data="synthetic",
                config=dict(workload=f"{Nx}x{Ny} array, b={b}, kd={cfg['kd']:.4f}, {W} port RHS, "
                                     f"{FORMS[a.form]['label']}, tol {a.tol:g}",
-                           Nx=Nx, Ny=Ny, b=b, W=W, form=a.form, tol=a.tol, orth=a.orth or 2),
+                           Nx=Nx, Ny=Ny, b=b, W=W, form=a.form, tol=a.tol, orth=a.orth or 2,
+                           pc_prec=a.pc_prec),
                roofline=roof,
                roofline_kernel=dict(name=dom["name"], prec=dom["prec"], launches=dom["launches"],
                                     avg_ms=round(dom["ms"] / dom["launches"], 4),

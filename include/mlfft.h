@@ -164,6 +164,15 @@ typedef struct {
                             until it holds; info->iters and info->history then report the
                             global iteration for every column.  MLFFT_E_ARG if the batch has
                             more than 2^31-1 unknowns in all. */
+    int pc_bf16;         /* 1: an MLFFT_FP32 inner solve runs the per-frequency product of its
+                            preconditioner (kinds 1, 2 and the block-circulant part of 3) with
+                            bf16 inverse blocks and bf16-rounded vectors, FP32 accumulation (the
+                            FFTs stay FP32).  Honoured only while the preconditioned directions
+                            are stored (always for kind 3; for kinds 1 and 2 when the workspace
+                            fits), since the solution is then formed from the very directions
+                            the Arnoldi process saw; otherwise the product stays FP32.  The FP64
+                            true residual still decides convergence.  0 (default): the product
+                            runs in the inner precision.  Ignored for other inner precisions. */
 } mlfft_solve_opts;
 
 typedef struct {

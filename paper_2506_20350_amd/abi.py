@@ -49,7 +49,7 @@ class SolveOpts(ctypes.Structure):
                 ("inner_prec", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("precond", ctypes.c_int), ("orth", ctypes.c_int), ("x0_given", ctypes.c_int),
                 ("record_history", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("mode", ctypes.c_int)]
+                ("mode", ctypes.c_int), ("pc_bf16", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

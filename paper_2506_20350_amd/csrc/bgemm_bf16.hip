@@ -13,8 +13,31 @@ static hipError_t launch_b16_cfg(const GemmTask& t0, const GemmTask* td, int n, 
     return hipGetLastError();
 }
 
+template<int BP, int TAG>
+static hipError_t launch_b16_flat_cfg(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
+    constexpr int NT = 32;
+    const size_t lds = (size_t)4 * NT * (BP + 4) * sizeof(uint32_t);
+    auto k = bgemm_bf16_flat_kernel<BP, NT, TAG>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(512), lds, s, t0, td, n);
+    return hipGetLastError();
+}
+
+// the flat kernel needs ceil(b/16) >= 7 (b >= 97), so reduction lengths from 112 up
+#define MLFFT_BP16_FLAT(X) X(112) X(128) X(144) X(160) X(176) X(192) X(208) X(224) X(240) X(256)
+
 hipError_t launch_bgemm_bf16(int bp, GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
                              hipStream_t s) {
+    if (sh.m3 == 2) {
+        if (sh.waves != 8 || sh.nt != 32) return hipErrorInvalidValue;
+        switch (bp) {
+#define F16(B) case B: return tag ? launch_b16_flat_cfg<B, 1>(t0, td, n, grid, s) \
+                                  : launch_b16_flat_cfg<B, 0>(t0, td, n, grid, s);
+            MLFFT_BP16_FLAT(F16)
+#undef F16
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (bp) {
 #define C16(B) case B: return tag ? launch_b16_cfg<B, 1>(t0, td, n, grid, sh.waves, s) \
                                   : launch_b16_cfg<B, 0>(t0, td, n, grid, sh.waves, s);

@@ -667,4 +667,157 @@ __global__ void __launch_bounds__(512) bgemm_bf16_kernel(GemmTask t0, const Gemm
     }
 }
 
+
+// BF16 inputs, FP32 accumulation, with the flat assignment of the FP32
+// three-product kernel: K * ceil(b/16) (frequency, 16-row slice) items dealt to
+// eight waves, at most two frequencies per workgroup, X tiles double-buffered
+// through LDS with the next tile prefetched in registers.  The complex product
+// runs as a real one of twice the size: A row 2i is (Re G[m], -Im G[m]) and row
+// 2i+1 is (Im G[m], Re G[m]) over the interleaved (Re X, Im X) reduction, so a
+// 16-row MFMA tile covers eight complex rows and a wave's slice is two such
+// halves, both kept in registers.  X is rounded to bf16 as it is staged (one
+// packed (re, im) word per complex value), and each B fragment read from LDS
+// feeds the products of both halves.  The lane's outputs of one half are rows
+// m and m+1 (re, im, re, im) of one column: a single 16-byte store.
+template<int BP, int NT, int TAG>
+__global__ void __launch_bounds__(512) bgemm_bf16_flat_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
+    constexpr int WAVES = 8;
+    constexpr int NTH = 64 * WAVES;
+    constexpr int PF = (NT * BP + NTH - 1) / NTH;      // prefetched complex values per thread and panel
+    constexpr int LDX = BP + 4;                        // packed words per LDS row (16-byte skew)
+    extern __shared__ unsigned char smem_raw[];
+    uint32_t* xs = reinterpret_cast<uint32_t*>(smem_raw);     // [buffer][panel][NT][LDX]
+    const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
+    const int b = t.b, W = t.W, K = t.K;
+    const int ns = (b + 15) >> 4;
+    const int total = K * ns;
+    const int nwg = (total + WAVES - 1) / WAVES;
+    const int local = blockIdx.x - t.block_begin;
+    // consecutive slice groups on one XCD, so the workgroups sharing a frequency share its L2
+    const int per = nwg >> 3;
+    const int grp = local < per * 8 ? (local & 7) * per + (local >> 3) : local;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gs0 = grp * WAVES;
+    const int kA = gs0 / ns;
+    const int kB = min((gs0 + WAVES - 1) / ns, K - 1);
+    const int npan = kB != kA ? 2 : 1;
+    const int gs = gs0 + wave;
+    const bool active = gs < total;
+    const int kw = active ? gs / ns : kA;
+    const int m_base = (gs - kw * ns) * 16;
+    const int pan = kw - kA;
+    const int j = lane & 15, q = lane >> 4;
+    // A fragments of the two 8-row halves for all BP/16 reduction steps (16 complex columns each)
+    ushortx8 a0[BP / 16], a1[BP / 16];
+    {
+        const uint32_t* __restrict__ Gk = static_cast<const uint32_t*>(t.G) + (size_t)kw * t.gstride;
+        const int pr = j & 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int m = m_base + 8 * h + (j >> 1);
+#pragma unroll
+            for (int s = 0; s < BP / 16; ++s) {
+                ushortx8 v;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int n = 16 * s + 4 * q + e;
+                    uint32_t g = 0;
+                    if (active && m < b && n < b) g = gload(Gk + (size_t)m * b + n);
+                    const unsigned short gr = (unsigned short)(g & 0xffffu), gi = (unsigned short)(g >> 16);
+                    if (pr == 0) { v[2 * e] = gr; v[2 * e + 1] = (unsigned short)(gi ^ 0x8000u); }
+                    else         { v[2 * e] = gi; v[2 * e + 1] = gr; }
+                }
+                if (h == 0) a0[s] = v; else a1[s] = v;
+            }
+        }
+    }
+    // reduction padding n in [b, BP) of every row of both buffers and panels
+    const int padn = BP - b;
+    for (int e = threadIdx.x; e < 4 * NT * padn; e += NTH) {
+        const int pw = e / padn, n = b + (e - pw * padn);
+        xs[pw * LDX + n] = 0u;
+    }
+    const int tile = NT * b;
+    const float2* __restrict__ Xa = static_cast<const float2*>(t.X) + (size_t)kA * W * b;
+    const float2* __restrict__ Xb = static_cast<const float2*>(t.X) + (size_t)kB * W * b;
+    float2* __restrict__ Yk = static_cast<float2*>(t.Y) + (size_t)kw * W * b;
+    float2 pre[2 * PF];
+    auto fetch = [&](int w0) {
+        const int have = min(NT, W - w0) * b;
+#pragma unroll
+        for (int i = 0; i < 2 * PF; ++i) {
+            const int e = threadIdx.x + (i % PF) * NTH;
+            const int p = i / PF;
+            const float2* __restrict__ src = (p ? Xb : Xa) + (size_t)w0 * b;
+            pre[i] = (p < npan && e < have) ? gload(src + e) : make_float2(0.f, 0.f);
+        }
+    };
+    auto stage = [&](uint32_t* buf) {
+#pragma unroll
+        for (int i = 0; i < 2 * PF; ++i) {
+            const int e = threadIdx.x + (i % PF) * NTH;
+            const int p = i / PF;
+            if (p < npan && e < tile) {
+                const int w = e / b, n = e - w * b;
+                buf[(p * NT + w) * LDX + n] =
+                    (uint32_t)f32_to_bf16_bits(pre[i].x) | ((uint32_t)f32_to_bf16_bits(pre[i].y) << 16);
+            }
+        }
+    };
+    const int bufsz = 2 * NT * LDX;
+    const bool even_b = (b & 1) == 0;
+    fetch(0);
+    __syncthreads();                      // padding zeroed
+    stage(xs);
+    if (NT < W) fetch(NT);
+    __syncthreads();
+    for (int w0 = 0, it = 0; w0 < W; w0 += NT, ++it) {
+        const uint32_t* cur = xs + (it & 1) * bufsz;
+        if (active) {
+            const uint32_t* __restrict__ xp = cur + pan * NT * LDX;
+            floatx4 c0[NT / 16], c1[NT / 16];
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) {
+                c0[cg] = floatx4{0, 0, 0, 0};
+                c1[cg] = floatx4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int s = 0; s < BP / 16; ++s) {
+#pragma unroll
+                for (int cg = 0; cg < NT / 16; ++cg) {
+                    const ushortx8 bv = *reinterpret_cast<const ushortx8*>(&xp[(cg * 16 + j) * LDX + 16 * s + 4 * q]);
+                    c0[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, a0[s]), __builtin_bit_cast(bf16x8, bv), c0[cg], 0, 0, 0);
+                    c1[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, a1[s]), __builtin_bit_cast(bf16x8, bv), c1[cg], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) {
+                const int w = w0 + cg * 16 + j;
+                if (w < W) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const floatx4 acc = h ? c1[cg] : c0[cg];
+                        const int m = m_base + 8 * h + 2 * q;
+                        float2* dst = Yk + (size_t)w * b + m;
+                        const float2 y0 = make_float2(acc[0], acc[1]), y1 = make_float2(acc[2], acc[3]);
+                        if (even_b && m + 1 < b) {
+                            gstore2(dst, y0, y1);
+                        } else {
+                            if (m < b) gstore(dst, y0);
+                            if (m + 1 < b) gstore(dst + 1, y1);
+                        }
+                    }
+                }
+            }
+        }
+        if (w0 + NT < W) {
+            stage(xs + ((it + 1) & 1) * bufsz);
+            if (w0 + 2 * NT < W) fetch(w0 + 2 * NT);
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace mlfft

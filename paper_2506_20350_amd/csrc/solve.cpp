@@ -85,6 +85,7 @@ extern "C" mlfft_status mlfft_solve_default_opts(mlfft_solve_opts* o) {
     o->record_history = 0;
     o->use_graph = 0;
     o->mode = 0;
+    o->pc_bf16 = 0;
     return MLFFT_OK;
 }
 
@@ -101,6 +102,7 @@ static mlfft_status check_opts(Ctx* c, const mlfft_solve_opts& o) {
     if (o.orth != 1 && o.orth != 2) return c->fail(MLFFT_E_ARG, "orth must be 1 or 2");
     if (o.use_graph != 0 && o.use_graph != 1) return c->fail(MLFFT_E_ARG, "use_graph must be 0 or 1");
     if (o.mode != 0 && o.mode != 1) return c->fail(MLFFT_E_ARG, "mode must be 0 (per right-hand side) or 1 (global)");
+    if (o.pc_bf16 != 0 && o.pc_bf16 != 1) return c->fail(MLFFT_E_ARG, "pc_bf16 must be 0 or 1");
     if (o.precond == 3 && !c->net_ready()) return c->fail(MLFFT_E_STATE, "learned preconditioner requested but no network is loaded");
     return MLFFT_OK;
 }
@@ -118,13 +120,13 @@ static mlfft_status batch_matvec(Ctx* c, std::vector<Seg>& segs, const void* x, 
 
 // z = P^{-1} r (kind 1 / 2), or the learned correction of the block-circulant output (kind 3)
 static mlfft_status batch_precond(Ctx* c, std::vector<Seg>& segs, int kind, const void* r, void* z, void* scratch,
-                                  int prec, int* fallbacks, int* net_applies = nullptr) {
+                                  int prec, int* fallbacks, int* net_applies = nullptr, int pc_prec = -1) {
     const int eb = prec_elem_bytes(prec);
     std::vector<MatvecItem> items;
     void* dst = kind == 3 ? scratch : z;
     for (auto& s : segs)
         items.push_back(MatvecItem{s.arr, s.W, (const char*)r + s.off * eb, (char*)dst + s.off * eb, nullptr, 1.0, 0.0});
-    STCHK(c->precond_group(items, kind == 3 ? 1 : kind, prec));
+    STCHK(c->precond_group(items, kind == 3 ? 1 : kind, pc_prec < 0 ? prec : pc_prec));
     if (kind == 3) {
         for (auto& s : segs) {
             mlfft_status st = c->net_correct(s.arr, s.W, (const char*)scratch + s.off * eb, (char*)z + s.off * eb, prec,
@@ -147,7 +149,7 @@ static std::string graph_key(Ctx* c, const std::vector<Seg>& segs, const Work& w
     std::string k;
     auto put = [&k](const void* p, size_t n) { k.append((const char*)p, n); };
     const int hl = (info && o.record_history) ? info->history_len : 0;
-    const int ints[] = {j, prec, o.precond, o.orth, o.restart, w.Wt, hl, o.mode};
+    const int ints[] = {j, prec, o.precond, o.orth, o.restart, w.Wt, hl, o.mode, o.pc_bf16};
     put(ints, sizeof ints);
     const void* ptrs[] = {c->solve_ws.p, c->solve_ws2.p, c->pinned, c->spec_a.p, c->spec_b.p};
     put(ptrs, sizeof ptrs);
@@ -236,6 +238,9 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
     const int eb = prec_elem_bytes(prec);
     const size_t vb = w.S * eb;
     const bool flexible = o.precond == 3;
+    // product precision of the preconditioner inside the Krylov steps: bf16 only
+    // when the solution is formed from the stored preconditioned directions
+    const int pc_prec = (o.pc_bf16 && prec == P32 && o.precond && w.zstore) ? PBF16 : prec;
     const int Wt = cols.W;      // Krylov columns (1 in the global mode)
     int* pinned_state = c->pinned_state(Wt);
     if (!pinned_state) return c->fail(MLFFT_E_NOMEM, "pinned host buffer");
@@ -275,7 +280,7 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
                 const void* zsrc = vq;
                 if (o.precond) {
                     void* zdst = w.zstore ? (char*)w.Zb + (size_t)q * vb : w.tmp2T;
-                    STCHK(batch_precond(c, act, o.precond, vq, zdst, w.tmpT, prec, nullptr, nullptr));
+                    STCHK(batch_precond(c, act, o.precond, vq, zdst, w.tmpT, prec, nullptr, nullptr, pc_prec));
                     zsrc = zdst;
                 }
                 STCHK(batch_matvec(c, act, zsrc, vnext, nullptr, 1.0, 0.0, prec));

@@ -34,3 +34,16 @@ def test_calls_on_null_context_are_argument_errors():
     assert L.mlfft_destroy(None) == abi.MLFFT_OK
     assert L.mlfft_matvec(None, 0, 1, None, None, 0) == abi.MLFFT_E_ARG
     assert L.mlfft_set_blocks(None, 0, 1, 1, 1, None, 0) == abi.MLFFT_E_ARG
+
+
+def test_default_solve_options_fill_exactly_the_binding_layout():
+    """mlfft_solve_default_opts writes every field of the header's struct and nothing past
+    the binding's copy of it (a field added on one side only would show here)."""
+    n = ctypes.sizeof(abi.SolveOpts)
+    buf = (ctypes.c_ubyte * (n + 64))(*([0xA5] * (n + 64)))
+    assert abi.lib().mlfft_solve_default_opts(ctypes.cast(buf, ctypes.POINTER(abi.SolveOpts))) == abi.MLFFT_OK
+    assert bytes(buf[n:]) == b"\xa5" * 64
+    o = abi.SolveOpts.from_buffer(buf)
+    assert (o.restart, o.max_restarts, o.tol, o.inner_prec, o.max_outer, o.precond, o.orth) == \
+        (30, 100, 1e-6, abi.MLFFT_FP32, 10, 1, 2)
+    assert (o.x0_given, o.record_history, o.use_graph, o.mode, o.pc_bf16) == (0, 0, 0, 0, 0)

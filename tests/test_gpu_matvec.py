@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import direct
 from oracle import precond as opc
 from oracle import toeplitz as tp
 from paper_2506_20350_amd import abi, synth
@@ -226,3 +227,46 @@ def test_empty_and_overlapping_arguments(ctx):
     with pytest.raises(abi.MlfftError) as e:
         abi.mlfft_matvec(ctx.h, 53, 2, x.data_ptr(), x.data_ptr(), 7)
     assert e.value.status == abi.MLFFT_E_ARG
+
+
+@pytest.mark.parametrize("b", [97, 112, 200, 255, 256])
+def test_bf16_flat_block_product_matches_oracle_and_eight_row_kernel(ctx, b):
+    """The flat bf16 block product (b >= 97; 16-row slices, 32-column tiles): against the oracle
+    at the bf16 bound, against the eight-row bf16 kernel on the same bf16 inputs to FP32
+    accumulation accuracy, and in the preconditioner product.  W = 70 spans three tiles with a
+    ragged tail; odd b takes the single-value stores."""
+    Nx, Ny, W = 3, 4, 70
+    blocks = synth.random_blocks(Nx, Ny, b, seed=b + 2)
+    ctx.set_blocks(54, blocks)
+    X = synth.random_vectors(Nx * Ny * b, W, seed=7)
+    ref = tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)
+    y_flat = to_host(ctx.matvec(54, to_dev(X, torch.complex64), prec="bf16"))
+    assert relerr(y_flat, ref) <= TOL["bf16"]
+    bp = (b + 15) // 16 * 16
+    abi.mlfft_tune_import(ctx.h, f"gemm 2 {bp} 8 64 0\n")
+    try:
+        y_rows = to_host(ctx.matvec(54, to_dev(X, torch.complex64), prec="bf16"))
+    finally:
+        abi.mlfft_tune_import(ctx.h, f"gemm 2 {bp} 8 32 2\n")
+    assert relerr(y_flat, y_rows) <= 1e-6
+    R = synth.random_vectors(Nx * Ny * b, W, seed=6)
+    z = to_host(ctx.precond_apply(54, to_dev(R, torch.complex64), kind=1, prec="bf16"))
+    assert relerr(z, opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)) <= TOL["bf16"]
+
+
+def test_bf16_flat_block_product_in_a_batched_solve(ctx):
+    """Two arrays whose b pad to the same bf16 reduction length (112) share one flat launch
+    (two tasks); the bf16 inner solve with FP64 refinement still meets LU."""
+    specs = [(3, 3, 100, 0), (2, 4, 110, 1)]
+    ids, Vs, refs = [], [], []
+    for i, (Nx, Ny, b, seed) in enumerate(specs):
+        blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=seed)
+        ctx.set_blocks(60 + i, blocks)
+        V = synth.port_rhs(Nx, Ny, b)
+        ids.append(60 + i)
+        Vs.append(to_dev(V))
+        refs.append(direct.lu_solve(tp.dense_Z(blocks), V))
+    Is, info = ctx.solve_batch(ids, Vs, tol=1e-10, inner_prec="bf16", precond=1)
+    assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-10)
+    for I, ref in zip(Is, refs):
+        assert relerr(to_host(I), ref) <= 1e-8

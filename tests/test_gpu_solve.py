@@ -59,6 +59,38 @@ def test_small_array_all_ports_match_lu(ctx, inner, pc):
         assert info["outer"].max() >= 2          # refinement actually worked
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("pc", [1, 2])
+def test_bf16_preconditioner_product_matches_lu(ctx, pc, mode):
+    """FP32 inner solve with the preconditioner's block product in bf16 (pc_bf16 = 1): the
+    solution still meets LU after refinement, the option really changes the preconditioned
+    directions (results differ from the FP32 product's), and the iteration count stays within
+    two of the FP32 product's (bf16 rounding perturbs the approximate inverse by ~2^-9)."""
+    Nx, Ny, b = 10, 10, 64
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0)
+    V = synth.port_rhs(Nx, Ny, b)
+    ctx.set_blocks(31, blocks)
+    ref = direct.lu_solve(tp.dense_Z(blocks), V)
+    out = {}
+    for pc_bf16 in (0, 1):
+        I, info = ctx.solve(31, to_dev(V), tol=1e-10, inner_prec="fp32", precond=pc, mode=mode, pc_bf16=pc_bf16)
+        assert info["status"] == abi.MLFFT_OK, info
+        assert np.all(info["relres"] <= 1e-10)
+        assert relerr(to_host(I), ref) <= 1e-8
+        out[pc_bf16] = (to_host(I), info)
+    assert not np.array_equal(out[0][0], out[1][0])
+    assert out[1][1]["iters"].max() <= out[0][1]["iters"].max() + 2
+
+
+def test_bf16_preconditioner_option_is_validated(ctx):
+    blocks = synth.green_blocks(3, 3, 8, np.pi, seed=0)
+    ctx.set_blocks(32, blocks)
+    V = synth.port_rhs(3, 3, 8)
+    with pytest.raises(abi.MlfftError, match="pc_bf16") as e:
+        ctx.solve(32, to_dev(V), tol=1e-8, inner_prec="fp32", precond=1, pc_bf16=2)
+    assert e.value.status == abi.MLFFT_E_ARG
+
+
 def test_c2_fp32_refined_block_circulant_matches_lu(ctx):
     """10x10 array, b = 64, 100 port excitations, FP32 inner + FP64 refinement to 1e-8."""
     Nx = Ny = 10
@@ -308,14 +340,16 @@ def test_full_size_30x30_b200_autotuned_sampled_columns(ctx):
     for prec in (0, 1):
         abi.mlfft_autotune(ctx.h, 18, Nx * Ny, prec, 1)
     V = synth.port_rhs(Nx, Ny, b)
-    I, info = ctx.solve(18, to_dev(V), tol=1e-6, inner_prec="fp32", precond=1)
-    assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-6)
     cols = [0, 437]
     Gh = tp.spectra(blocks, 2 * Ny, 2 * Nx)
     mv = lambda X: tp.matvec_spectral(Gh, X, Nx, Ny)
     Sinv = precond.strang_inverse_spectrum(blocks)
     ref = krylov.gmres_columns(mv, V[cols[1:]], lambda X: precond.strang_apply(Sinv, X), tol=1e-12)[0].x
-    assert relerr(to_host(I)[cols[1]], ref) <= 2e-6       # relres <= 1e-6 and cond(Z) ~ 1.5
+    # the preconditioner's block product in FP32 and in bf16 (both benchmark options)
+    for pc_bf16 in (0, 1):
+        I, info = ctx.solve(18, to_dev(V), tol=1e-6, inner_prec="fp32", precond=1, pc_bf16=pc_bf16)
+        assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-6)
+        assert relerr(to_host(I)[cols[1]], ref) <= 2e-6   # relres <= 1e-6 and cond(Z) ~ 1.5
     # the same tuned block-product shape in a plain FP32 matvec, sampled columns against the oracle
     y = to_host(ctx.matvec(18, to_dev(V, torch.complex64), prec="fp32"))
     assert relerr(y[cols], mv(V[cols])) <= 1e-5
