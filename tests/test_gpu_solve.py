@@ -82,6 +82,29 @@ def test_bf16_preconditioner_product_matches_lu(ctx, pc, mode):
     assert out[1][1]["iters"].max() <= out[0][1]["iters"].max() + 2
 
 
+def test_bf16_preconditioner_product_under_the_learned_correction(ctx):
+    """Flexible GMRES with a (small, random) learned correction of the block-circulant output,
+    whose block product runs in bf16 (b = 100: the flat bf16 kernel): the refined solution meets
+    LU, and it differs from the FP32-product solve, so the option reached the flexible path."""
+    Nx, Ny, b = 3, 3, 100
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=2)
+    V = synth.port_rhs(Nx, Ny, b)
+    ctx.set_blocks(33, blocks)
+    abi.mlfft_net_create(ctx.h, b, 16)
+    ws = learned.he_init(b, 16, seed=4)
+    ws[-16 * 2 * b * 9:] = np.random.default_rng(5).standard_normal(16 * 2 * b * 9).astype(np.float32) * 0.01
+    abi.mlfft_net_set_weights(ctx.h, ws)
+    ref = direct.lu_solve(tp.dense_Z(blocks), V)
+    out = {}
+    for pc_bf16 in (0, 1):
+        I, info = ctx.solve(33, to_dev(V), tol=1e-10, inner_prec="fp32", precond=3, pc_bf16=pc_bf16)
+        assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-10), info
+        assert info["net_applies"] > 0
+        assert relerr(to_host(I), ref) <= 1e-8
+        out[pc_bf16] = to_host(I)
+    assert not np.array_equal(out[0], out[1])
+
+
 def test_bf16_preconditioner_option_is_validated(ctx):
     blocks = synth.green_blocks(3, 3, 8, np.pi, seed=0)
     ctx.set_blocks(32, blocks)
