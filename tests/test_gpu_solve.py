@@ -105,6 +105,36 @@ def test_bf16_preconditioner_product_under_the_learned_correction(ctx):
     assert not np.array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_bf16_preconditioner_product_in_a_batch_of_two_kernels(ctx, use_graph):
+    """An uneven batch whose preconditioner products run in bf16 through both kernels (b = 64:
+    the eight-row kernel; b = 100: the flat kernel), eagerly and with graph-captured steps
+    (graphs must equal the eager solve bit for bit); every array meets its LU solution."""
+    specs = [(4, 3, 64, 3), (3, 3, 100, 4)]
+    ids, Vs, refs = [], [], []
+    for i, (Nx, Ny, b, seed) in enumerate(specs):
+        blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=seed)
+        ctx.set_blocks(34 + i, blocks)
+        V = synth.port_rhs(Nx, Ny, b)
+        ids.append(34 + i)
+        Vs.append(to_dev(V))
+        refs.append(direct.lu_solve(tp.dense_Z(blocks), V))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        I0, info0 = ctx.solve_batch(ids, Vs, tol=1e-10, inner_prec="fp32", precond=1, pc_bf16=1)
+        assert info0["status"] == abi.MLFFT_OK and np.all(info0["relres"] <= 1e-10)
+        for I, ref in zip(I0, refs):
+            assert relerr(to_host(I), ref) <= 1e-8
+        if use_graph:
+            for rep in range(3):
+                I1, info1 = ctx.solve_batch(ids, Vs, tol=1e-10, inner_prec="fp32", precond=1, pc_bf16=1,
+                                            use_graph=1)
+                side.synchronize()
+                assert info1["status"] == abi.MLFFT_OK, rep
+                for a, b in zip(I1, I0):
+                    assert torch.equal(a, b), rep
+
+
 def test_bf16_preconditioner_option_is_validated(ctx):
     blocks = synth.green_blocks(3, 3, 8, np.pi, seed=0)
     ctx.set_blocks(32, blocks)
