@@ -19,7 +19,8 @@ static GemmShape g_shape_override[3][33];      // [prec][bp/8]; waves == 0: not 
 static GemmShape default_shape(int prec, int bp) {
     if (prec == P64) return GemmShape{8, bp > 128 ? 16 : 32, 0};
     if (prec == P32) return GemmShape{8, bp > 160 ? 32 : 64, 0};
-    // BF16: the flat kernel (32-column tiles) wherever it applies, see launch_shape
+    // BF16: the eight-wave flat kernel (32-column tiles) for b >= 97, the four-wave one
+    // (16-column tiles) for b >= 33, see launch_shape
     return GemmShape{8, 32, 2};
 }
 
@@ -30,6 +31,8 @@ GemmShape gemm_shape(int prec, int bp, int tag) {
         // product of the same b when that is an eight-wave flat shape
         const GemmShape& o = g_shape_override[prec][bp / 8];
         if (prec == P32 && o.m3 == 2 && o.waves == 8) return o;
+        // the bf16 preconditioner product takes a tuned or imported flat shape
+        if (prec == PBF16 && o.m3 == 2) return o;
         return GemmShape{8, 32, 2};
     }
     const GemmShape& o = g_shape_override[prec][bp / 8];
@@ -38,8 +41,9 @@ GemmShape gemm_shape(int prec, int bp, int tag) {
 
 void gemm_set_shape(int prec, int bp, int waves, int nt, int m3) {
     if (prec < 0 || prec > 2 || bp < 8 || bp > 256 || bp % 8) return;
-    // BF16 has the eight-row kernel (m3 = 0) and the flat kernel with 32-column tiles only
-    if (prec == PBF16 && (m3 == 1 || (m3 == 2 && (waves != 8 || nt != 32)))) return;
+    // BF16 has the eight-row kernel (m3 = 0) and the flat kernel with eight waves and
+    // 32-column tiles or four waves and 16-column tiles
+    if (prec == PBF16 && (m3 == 1 || (m3 == 2 && !((waves == 8 && nt == 32) || (waves == 4 && nt == 16))))) return;
     g_shape_override[prec][bp / 8] = GemmShape{waves, nt, m3};
 }
 
@@ -74,9 +78,13 @@ static GemmShape launch_shape(int prec, const GemmTask* tasks, int ntasks, int t
         int bmin = 1 << 30;
         for (int i = 0; i < ntasks; ++i) bmin = std::min(bmin, tasks[i].b);
         // waves - 1 consecutive slices must not reach a third frequency
-        if ((bmin + 15) / 16 < sh.waves - 1)
-            sh = prec == P32 ? GemmShape{8, 32, 1} : prec == P64 ? GemmShape{8, bpm > 128 ? 16 : 32, 0}
-                                                   : GemmShape{8, 64, 0};
+        if ((bmin + 15) / 16 < sh.waves - 1) {
+            // bf16: the four-wave flat kernel down to 3 slices (b >= 33), a third faster than
+            // the eight-row kernel at b = 64 and 96; below that the eight-row kernel
+            if (prec == PBF16 && sh.waves == 8 && (bmin + 15) / 16 >= 3) sh = GemmShape{4, 16, 2};
+            else sh = prec == P32 ? GemmShape{8, 32, 1} : prec == P64 ? GemmShape{8, bpm > 128 ? 16 : 32, 0}
+                                                        : GemmShape{8, 64, 0};
+        }
     }
     return sh;
 }

@@ -13,26 +13,34 @@ static hipError_t launch_b16_cfg(const GemmTask& t0, const GemmTask* td, int n, 
     return hipGetLastError();
 }
 
-template<int BP, int TAG>
+template<int BP, int TAG, int NT, int WAVES>
 static hipError_t launch_b16_flat_cfg(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
-    constexpr int NT = 32;
     const size_t lds = (size_t)4 * NT * (BP + 4) * sizeof(uint32_t);
-    auto k = bgemm_bf16_flat_kernel<BP, NT, TAG>;
+    auto k = bgemm_bf16_flat_kernel<BP, NT, TAG, WAVES>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(512), lds, s, t0, td, n);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * WAVES), lds, s, t0, td, n);
     return hipGetLastError();
 }
 
-// the flat kernel needs ceil(b/16) >= 7 (b >= 97), so reduction lengths from 112 up
-#define MLFFT_BP16_FLAT(X) X(112) X(128) X(144) X(160) X(176) X(192) X(208) X(224) X(240) X(256)
+template<int BP, int TAG>
+static hipError_t launch_b16_flat(GemmShape sh, const GemmTask& t0, const GemmTask* td, int n, int grid,
+                                  hipStream_t s) {
+    if (sh.waves == 8 && sh.nt == 32) return launch_b16_flat_cfg<BP, TAG, 32, 8>(t0, td, n, grid, s);
+    if (sh.waves == 4 && sh.nt == 16) return launch_b16_flat_cfg<BP, TAG, 16, 4>(t0, td, n, grid, s);
+    return hipErrorInvalidValue;
+}
+
+// the eight-wave flat kernel needs ceil(b/16) >= 7 (b >= 97), the four-wave one
+// ceil(b/16) >= 3 (b >= 33); reduction lengths from 48 up
+#define MLFFT_BP16_FLAT(X) X(48) X(64) X(80) X(96) X(112) X(128) X(144) X(160) X(176) X(192) X(208) X(224) \
+    X(240) X(256)
 
 hipError_t launch_bgemm_bf16(int bp, GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
                              hipStream_t s) {
     if (sh.m3 == 2) {
-        if (sh.waves != 8 || sh.nt != 32) return hipErrorInvalidValue;
         switch (bp) {
-#define F16(B) case B: return tag ? launch_b16_flat_cfg<B, 1>(t0, td, n, grid, s) \
-                                  : launch_b16_flat_cfg<B, 0>(t0, td, n, grid, s);
+#define F16(B) case B: return tag ? launch_b16_flat<B, 1>(sh, t0, td, n, grid, s) \
+                                  : launch_b16_flat<B, 0>(sh, t0, td, n, grid, s);
             MLFFT_BP16_FLAT(F16)
 #undef F16
             default: return hipErrorInvalidValue;

@@ -670,7 +670,9 @@ __global__ void __launch_bounds__(512) bgemm_bf16_kernel(GemmTask t0, const Gemm
 
 // BF16 inputs, FP32 accumulation, with the flat assignment of the FP32
 // three-product kernel: K * ceil(b/16) (frequency, 16-row slice) items dealt to
-// eight waves, at most two frequencies per workgroup, X tiles double-buffered
+// the WAVES waves of a workgroup (eight with 32-column tiles, or four with
+// 16-column tiles so that two workgroups share a CU), at most two frequencies
+// per workgroup, X tiles double-buffered
 // through LDS with the next tile prefetched in registers.  The complex product
 // runs as a real one of twice the size: A row 2i is (Re G[m], -Im G[m]) and row
 // 2i+1 is (Im G[m], Re G[m]) over the interleaved (Re X, Im X) reduction, so a
@@ -679,9 +681,8 @@ __global__ void __launch_bounds__(512) bgemm_bf16_kernel(GemmTask t0, const Gemm
 // packed (re, im) word per complex value), and each B fragment read from LDS
 // feeds the products of both halves.  The lane's outputs of one half are rows
 // m and m+1 (re, im, re, im) of one column: a single 16-byte store.
-template<int BP, int NT, int TAG>
-__global__ void __launch_bounds__(512) bgemm_bf16_flat_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
-    constexpr int WAVES = 8;
+template<int BP, int NT, int TAG, int WAVES = 8>
+__global__ void __launch_bounds__(64 * WAVES) bgemm_bf16_flat_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
     constexpr int NTH = 64 * WAVES;
     constexpr int PF = (NT * BP + NTH - 1) / NTH;      // prefetched complex values per thread and panel
     constexpr int LDX = BP + 4;                        // packed words per LDS row (16-byte skew)

@@ -175,7 +175,8 @@ mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text) {
                             (a4 == 16 || a4 == 32 || a4 == 64) &&
                             (a5 == 0 || (a5 == 1 && a1 == 1) || (a5 == 2 && a1 == 1 && a3 == 8 && a4 == 32) ||
                              (a5 == 2 && a1 == 1 && a3 == 8 && a4 == 16) || (a5 == 2 && a1 == 1 && a3 == 4 && a4 == 16) ||
-                             (a5 == 2 && a1 == 0 && a3 == 4 && a4 == 16) || (a5 == 2 && a1 == 2 && a3 == 8 && a4 == 32));
+                             (a5 == 2 && a1 == 0 && a3 == 4 && a4 == 16) || (a5 == 2 && a1 == 2 && a3 == 8 && a4 == 32) ||
+                             (a5 == 2 && a1 == 2 && a3 == 4 && a4 == 16));
             if (!ok) return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
             gemm_set_shape(a1, a2, a3, a4, a5);
         } else if (sscanf(ln.c_str(), "fftcm %d %d %d %d %d %d", &a1, &a2, &a3, &a4, &a5, &a6) == 6) {

@@ -229,28 +229,31 @@ def test_empty_and_overlapping_arguments(ctx):
     assert e.value.status == abi.MLFFT_E_ARG
 
 
-@pytest.mark.parametrize("b", [97, 112, 200, 255, 256])
-def test_bf16_flat_block_product_matches_oracle_and_eight_row_kernel(ctx, b):
-    """The flat bf16 block product (b >= 97; 16-row slices, 32-column tiles): against the oracle
-    at the bf16 bound, against the eight-row bf16 kernel on the same bf16 inputs to FP32
-    accumulation accuracy, and in the preconditioner product.  W = 70 spans three tiles with a
-    ragged tail; odd b takes the single-value stores."""
+@pytest.mark.parametrize("shape", ["8 32 2", "4 16 2"])
+@pytest.mark.parametrize("b", [40, 64, 97, 112, 200, 255, 256])
+def test_bf16_flat_block_product_matches_oracle_and_eight_row_kernel(ctx, b, shape):
+    """The flat bf16 block product (16-row slices; eight waves with 32-column tiles for b >= 97,
+    four waves with 16-column tiles for b >= 33): against the oracle at the bf16 bound, against
+    the eight-row bf16 kernel on the same bf16 inputs to FP32 accumulation accuracy, and in the
+    preconditioner product.  W = 70 spans several tiles with a ragged tail; odd b takes the
+    single-value stores."""
     Nx, Ny, W = 3, 4, 70
     blocks = synth.random_blocks(Nx, Ny, b, seed=b + 2)
     ctx.set_blocks(54, blocks)
     X = synth.random_vectors(Nx * Ny * b, W, seed=7)
     ref = tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)
-    y_flat = to_host(ctx.matvec(54, to_dev(X, torch.complex64), prec="bf16"))
-    assert relerr(y_flat, ref) <= TOL["bf16"]
     bp = (b + 15) // 16 * 16
-    abi.mlfft_tune_import(ctx.h, f"gemm 2 {bp} 8 64 0\n")
+    R = synth.random_vectors(Nx * Ny * b, W, seed=6)
+    abi.mlfft_tune_import(ctx.h, f"gemm 2 {bp} {shape}\n")
     try:
+        y_flat = to_host(ctx.matvec(54, to_dev(X, torch.complex64), prec="bf16"))
+        z = to_host(ctx.precond_apply(54, to_dev(R, torch.complex64), kind=1, prec="bf16"))
+        abi.mlfft_tune_import(ctx.h, f"gemm 2 {bp} 8 64 0\n")
         y_rows = to_host(ctx.matvec(54, to_dev(X, torch.complex64), prec="bf16"))
     finally:
         abi.mlfft_tune_import(ctx.h, f"gemm 2 {bp} 8 32 2\n")
+    assert relerr(y_flat, ref) <= TOL["bf16"]
     assert relerr(y_flat, y_rows) <= 1e-6
-    R = synth.random_vectors(Nx * Ny * b, W, seed=6)
-    z = to_host(ctx.precond_apply(54, to_dev(R, torch.complex64), kind=1, prec="bf16"))
     assert relerr(z, opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)) <= TOL["bf16"]
 
 
