@@ -106,11 +106,12 @@ def test_bf16_preconditioner_product_under_the_learned_correction(ctx):
 
 
 @pytest.mark.parametrize("use_graph", [0, 1])
-def test_bf16_preconditioner_product_in_a_batch_of_two_kernels(ctx, use_graph):
-    """An uneven batch whose preconditioner products run in bf16 through both kernels (b = 64:
-    the eight-row kernel; b = 100: the flat kernel), eagerly and with graph-captured steps
-    (graphs must equal the eager solve bit for bit); every array meets its LU solution."""
-    specs = [(4, 3, 64, 3), (3, 3, 100, 4)]
+def test_bf16_preconditioner_product_in_a_batch_of_three_kernels(ctx, use_graph):
+    """An uneven batch whose preconditioner products run in bf16 through all three kernels
+    (b = 24: the eight-row kernel; b = 64: the four-wave flat kernel; b = 100: the eight-wave
+    flat kernel), eagerly and with graph-captured steps (graphs must equal the eager solve bit
+    for bit); every array meets its LU solution."""
+    specs = [(4, 3, 24, 2), (4, 3, 64, 3), (3, 3, 100, 4)]
     ids, Vs, refs = [], [], []
     for i, (Nx, Ny, b, seed) in enumerate(specs):
         blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=seed)
