@@ -377,7 +377,8 @@ def main():
     ap.add_argument("--orth", type=int, default=None, choices=[1, 2],
                     help="Gram-Schmidt passes of the Arnoldi step (library default if omitted)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cols", type=int, default=3)
+    ap.add_argument("--cpu-cols", type=int, default=10,
+                    help="port columns of the bounded CPU-oracle sample (about 12 s of host work at 30x30 b=200)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy kernel (for HBM counter calibration)")
     a = ap.parse_args()
