@@ -439,6 +439,9 @@ def main():
         train_info = learned.prepare(ctx, cfg, steps=a.train_steps, log=log)
         if not train_info["enabled"]:
             GATED["learned"] = dict(precond=1)
+            FORMS["learned"]["label"] = ("FP32 inner GMRES(30) + FP64 refinement, block-circulant preconditioner "
+                                         "(the learned correction was trained and then gated off: it did not lower "
+                                         "the held-out loss below the gate)")
     I, infos, dt, stats = timed_solves(ctx, 0, Vd, a.steps, a.warmup, a.form, a.tol, torch, a.inner_tol, a.orth)
     conv = [int(np.sum(inf["relres"] <= a.tol)) for inf in infos]
     value = sum(conv) / dt
@@ -470,6 +473,8 @@ def main():
                max_relres=float(last["relres"].max()), converged_per_step=conv)
     if train_info is not None:
         out["learned"] = train_info
+        out["config"]["learned_enabled"] = bool(train_info["enabled"])
+        out["config"]["form_run"] = "learned" if (a.form != "learned" or train_info["enabled"]) else "fp32"
         out["fallbacks"] = int(last["fallbacks"])
     comps = [] if a.compare == "none" else [f for f in a.compare.split(",") if f and f != a.form]
     if comps:
@@ -485,11 +490,14 @@ def main():
         log("[bench] CPU baseline (oracle) on a bounded sample")
         cb, cols, res, mv, pc = cpu_baseline(blocks, V, cfg, a.tol, a.cpu_cols)
         out["cpu_baseline"] = cb
-        # error of the GPU solution against the oracle's FP64 solution at 1e-12 (first sampled column)
+        # error of the GPU solution against the oracle's FP64 solution at 1e-12: the largest
+        # per-column relative error over every sampled column
         from oracle import krylov
-        ref = krylov.gmres_columns(mv, V[cols[:1]], pc, tol=1e-12)[0].x
-        got = I[cols[0]].cpu().numpy()
-        out["err_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        refs = krylov.gmres_columns(mv, V[cols], pc, tol=1e-12)
+        got = I.cpu().numpy()
+        out["err_vs_oracle"] = max(float(np.linalg.norm(got[c] - r.x) / np.linalg.norm(r.x))
+                                   for c, r in zip(cols, refs))
+        out["err_vs_oracle_cols"] = [int(c) for c in cols]
         log(f"[bench] cpu baseline {cb['value']} RHS/s on {cb['cores']} cores; err vs oracle {out['err_vs_oracle']:.2e}")
     print(json.dumps(out), flush=True)
     ctx.close()

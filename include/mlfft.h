@@ -23,9 +23,12 @@
  *    PyTorch current stream).  Calls documented as asynchronous return before
  *    the work finishes; blocking calls synchronise the stream before returning.
  *  - A context is not thread safe; the caller serialises calls on it.
- *  - The library allocates its own device memory (spectra, preconditioner,
- *    spectral and Krylov workspaces) with hipMalloc outside of the matvec and
- *    preconditioner hot paths, and frees it in mlfft_destroy().
+ *  - Every device buffer of the library (spectra, preconditioner, spectral and
+ *    Krylov workspaces, network state) comes from the caller's allocator given
+ *    to mlfft_create() and goes back to it; the library never calls hipMalloc.
+ *    Buffers grow on demand and are kept for later calls; they are released by
+ *    mlfft_drop_array() (an array's spectra and factors) and mlfft_destroy().
+ *    An allocation the allocator refuses ends the call with MLFFT_E_NOMEM.
  */
 #ifndef MLFFT_H
 #define MLFFT_H
@@ -54,9 +57,25 @@ typedef enum {
     MLFFT_FP32_BF16GEMM = 2  /* complex64 data, FP32 FFTs, block product with bf16 inputs and FP32 accumulation */
 } mlfft_prec;
 
+/* Device allocator of the caller.  alloc_fn returns `bytes` bytes of device
+ * memory of the context's device, aligned to at least 256 bytes, usable by work
+ * enqueued on the context's stream, or NULL if it cannot (the library then
+ * reports MLFFT_E_NOMEM); free_fn gives such a pointer back.  free_fn may be
+ * called while work enqueued earlier on the context's stream still reads the
+ * buffer: the allocator must not hand that memory to work that is not ordered
+ * after it on that stream (a stream-ordered allocator, or a caching allocator
+ * keyed by the stream such as PyTorch's, does this), or must synchronise the
+ * stream first. */
+typedef void* (*mlfft_alloc_fn)(size_t bytes, void* user);
+typedef void (*mlfft_free_fn)(void* ptr, void* user);
+
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
- * (a hipStream_t; NULL = the default stream).  *out receives the handle. */
-mlfft_status mlfft_create(int device, void* hip_stream, mlfft_ctx* out);
+ * (a hipStream_t; NULL = the default stream), drawing all device memory from
+ * alloc_fn / free_fn (both required; `user` is passed through to them).
+ * *out receives the handle.  Sec. III-C hands GMRES a function for the
+ * product and one for the preconditioner; a context holds both. */
+mlfft_status mlfft_create(int device, void* hip_stream, mlfft_alloc_fn alloc_fn, mlfft_free_fn free_fn, void* user,
+                          mlfft_ctx* out);
 
 /* Free every device buffer the context owns and the context itself.  NULL is accepted. */
 mlfft_status mlfft_destroy(mlfft_ctx ctx);
@@ -115,6 +134,23 @@ mlfft_status mlfft_array_info(mlfft_ctx ctx, int array_id, mlfft_array_info_t* o
  * MLFFT_FP64, complex64 otherwise.  x and y must not overlap.
  * Asynchronous on the context's stream. */
 mlfft_status mlfft_matvec(mlfft_ctx ctx, int array_id, int W, const void* x, void* y, mlfft_prec prec);
+
+/* y = alpha Z_A x + beta v for W columns: the MLFFT product of mlfft_matvec with
+ * its result scaled and added to v in the inverse transform's epilogue (the true
+ * residual V - Z_A I of Sec. III, "ZI = V", is alpha = -1, beta = 1).  v may be
+ * NULL (then y = alpha Z_A x).  Layout and precision rules as for mlfft_matvec;
+ * x, v and y must not overlap.  Non-finite alpha or beta: MLFFT_E_ARG.  Asynchronous. */
+mlfft_status mlfft_matvec_axpby(mlfft_ctx ctx, int array_id, int W, double alpha, const void* x, double beta,
+                                const void* v, void* y, mlfft_prec prec);
+
+/* out = alpha x + beta y over n complex values (y may be NULL), with x and y of
+ * precision in_prec and out of precision out_prec (MLFFT_FP64 = complex128,
+ * MLFFT_FP32 = complex64; the combination is formed in FP64 and rounded once).
+ * Forms the error x* - x_k and the precision casts of training pairs.  out may
+ * be x or y itself when the precisions match; other overlaps: MLFFT_E_ARG.
+ * Asynchronous. */
+mlfft_status mlfft_axpby(mlfft_ctx ctx, size_t n, double alpha, const void* x, double beta, const void* y,
+                         int in_prec, void* out, int out_prec);
 
 /* z = P^{-1} r with P the preconditioner `kind`:
  *   1 = two-level Strang block circulant: z = IFFT2(S_hat(k)^{-1} FFT2(r)) on the
@@ -188,6 +224,10 @@ typedef struct {
     int matvecs_inner;   /* out: batched MLFFT products in the inner precision */
     int precond_applies; /* out: batched preconditioner applies */
     int net_applies;     /* out: batched network corrections */
+    int pc_switched;     /* out: 1 if the solve turned the learned correction (precond 3) off and went on
+                            with the plain block-circulant preconditioner, because a refinement step left
+                            the FP64 true residual of the columns it solved above half of its previous
+                            2-norm (each inner solve asks for a reduction of at least 0.3) */
 } mlfft_solve_info;
 
 /* Fill *opts with the defaults above. */
@@ -234,9 +274,12 @@ mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids
  * [c_out][c_in][3][3] row-major.  One network per context.
  */
 
-/* Create (or replace) the context's network for b basis functions per cell;
- * all weights start at zero (the correction is then the identity). */
-mlfft_status mlfft_net_create(mlfft_ctx ctx, int b, int hidden);
+/* Create (or replace) the context's network for b basis functions per cell.
+ * The first three layers start He-normal (standard deviation sqrt(2 / (9 c_in)))
+ * from a counter-based generator (splitmix64 of (seed, weight index), Box-Muller);
+ * the last layer starts at zero, so the correction starts as the identity.
+ * seed = 0: every weight starts at zero. */
+mlfft_status mlfft_net_create(mlfft_ctx ctx, int b, int hidden, unsigned seed);
 
 /* Number of FP32 weights of the network (0 without a network). */
 size_t mlfft_net_num_weights(mlfft_ctx ctx);

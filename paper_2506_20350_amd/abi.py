@@ -57,7 +57,12 @@ class SolveInfo(ctypes.Structure):
                 ("relres", ctypes.POINTER(ctypes.c_double)), ("converged", ctypes.POINTER(ctypes.c_int)),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int),
                 ("fallbacks", ctypes.c_int), ("matvecs64", ctypes.c_int), ("matvecs_inner", ctypes.c_int),
-                ("precond_applies", ctypes.c_int), ("net_applies", ctypes.c_int)]
+                ("precond_applies", ctypes.c_int), ("net_applies", ctypes.c_int), ("pc_switched", ctypes.c_int)]
+
+
+# device allocator callbacks of mlfft_create
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 _P = ctypes.c_void_p
@@ -65,7 +70,7 @@ _I = ctypes.c_int
 _ST = ctypes.c_int
 
 _SIGNATURES = {
-    "mlfft_create": (_ST, [_I, _P, ctypes.POINTER(_P)]),
+    "mlfft_create": (_ST, [_I, _P, ALLOC_FN, FREE_FN, _P, ctypes.POINTER(_P)]),
     "mlfft_destroy": (_ST, [_P]),
     "mlfft_last_error": (ctypes.c_char_p, [_P]),
     "mlfft_set_stream": (_ST, [_P, _P]),
@@ -73,12 +78,14 @@ _SIGNATURES = {
     "mlfft_drop_array": (_ST, [_P, _I]),
     "mlfft_array_info": (_ST, [_P, _I, ctypes.POINTER(ArrayInfo)]),
     "mlfft_matvec": (_ST, [_P, _I, _I, _P, _P, _I]),
+    "mlfft_matvec_axpby": (_ST, [_P, _I, _I, ctypes.c_double, _P, ctypes.c_double, _P, _P, _I]),
+    "mlfft_axpby": (_ST, [_P, ctypes.c_size_t, ctypes.c_double, _P, ctypes.c_double, _P, _I, _P, _I]),
     "mlfft_precond_apply": (_ST, [_P, _I, _I, _I, _P, _P, _I]),
     "mlfft_solve_default_opts": (_ST, [ctypes.POINTER(SolveOpts)]),
     "mlfft_solve": (_ST, [_P, _I, _I, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
     "mlfft_solve_batch": (_ST, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_P),
                                 ctypes.POINTER(_P), ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]),
-    "mlfft_net_create": (_ST, [_P, _I, _I]),
+    "mlfft_net_create": (_ST, [_P, _I, _I, ctypes.c_uint]),
     "mlfft_net_set_weights": (_ST, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
     "mlfft_net_get_weights": (_ST, [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
     "mlfft_net_num_weights": (ctypes.c_size_t, [_P]),
@@ -124,9 +131,10 @@ def check(ctx, status: int, what: str = "") -> int:
     return status
 
 
-def mlfft_create(device: int = 0, stream: int = 0):
+def mlfft_create(device: int, stream: int, alloc_fn: ALLOC_FN, free_fn: FREE_FN, user: int = 0):
+    """alloc_fn / free_fn: ALLOC_FN / FREE_FN callbacks; the caller keeps them alive until mlfft_destroy."""
     h = ctypes.c_void_p()
-    st = lib().mlfft_create(device, stream or None, ctypes.byref(h))
+    st = lib().mlfft_create(device, stream or None, alloc_fn, free_fn, user or None, ctypes.byref(h))
     if st != MLFFT_OK:
         raise MlfftError(st, lib().mlfft_last_error(None).decode())
     return h
@@ -156,6 +164,16 @@ def mlfft_array_info(ctx, array_id: int) -> ArrayInfo:
 
 def mlfft_matvec(ctx, array_id: int, W: int, x_ptr: int, y_ptr: int, prec: int):
     return check(ctx, lib().mlfft_matvec(ctx, array_id, W, x_ptr, y_ptr, prec))
+
+
+def mlfft_matvec_axpby(ctx, array_id: int, W: int, alpha: float, x_ptr: int, beta: float, v_ptr, y_ptr: int,
+                       prec: int):
+    return check(ctx, lib().mlfft_matvec_axpby(ctx, array_id, W, alpha, x_ptr, beta, v_ptr or None, y_ptr, prec))
+
+
+def mlfft_axpby(ctx, n: int, alpha: float, x_ptr: int, beta: float, y_ptr, in_prec: int, out_ptr: int,
+                out_prec: int):
+    return check(ctx, lib().mlfft_axpby(ctx, n, alpha, x_ptr, beta, y_ptr or None, in_prec, out_ptr, out_prec))
 
 
 def mlfft_precond_apply(ctx, array_id: int, kind: int, W: int, r_ptr: int, z_ptr: int, prec: int):
@@ -206,8 +224,8 @@ def mlfft_profile_read(ctx) -> list:
                  bytes=buf[i].bytes, flops=buf[i].flops) for i in range(min(n.value, 32))]
 
 
-def mlfft_net_create(ctx, b: int, hidden: int):
-    return check(ctx, lib().mlfft_net_create(ctx, b, hidden))
+def mlfft_net_create(ctx, b: int, hidden: int, seed: int = 0):
+    return check(ctx, lib().mlfft_net_create(ctx, b, hidden, seed))
 
 
 def mlfft_net_num_weights(ctx) -> int:

@@ -24,14 +24,53 @@ def _prec(p) -> int:
 
 
 class Context:
-    """One library context on one device, enqueueing on the current PyTorch stream."""
+    """One library context on one device, enqueueing on the current PyTorch stream.
 
-    def __init__(self, device: int = 0):
+    Every device buffer the library holds comes from PyTorch's caching allocator
+    (on the stream the context enqueues on), so it shows in
+    torch.cuda.memory_allocated() and is returned to PyTorch's pool when the
+    library frees it.
+    """
+
+    def __init__(self, device: int = 0, max_bytes: int = None):
+        """max_bytes: optional cap on the device memory the library may hold at once; an
+        allocation beyond it is refused and the call reports MLFFT_E_NOMEM."""
         self.device = device
         self.torch_device = torch.device("cuda", device)
-        stream = torch.cuda.current_stream(self.torch_device).cuda_stream
-        self.h = abi.mlfft_create(device, stream)
+        self._stream = torch.cuda.current_stream(self.torch_device)
+        self._live = {}
+        self.max_bytes = max_bytes
+
+        def alloc(nbytes, user):
+            if self.max_bytes is not None and self.library_bytes() + int(nbytes) > self.max_bytes:
+                return None
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self._stream)
+            except Exception:          # out of memory: the library reports MLFFT_E_NOMEM
+                return None
+            self._live[p] = (int(nbytes), self._stream)
+            return p
+
+        def free(p, user):
+            rec = self._live.pop(p, None)
+            if rec is None:
+                return
+            # PyTorch reuses a freed block for later work on the stream it was allocated on;
+            # if the context has moved to another stream since, the library's work on the
+            # block is only ordered on the new stream, so wait for it first
+            if rec[1] != self._stream:
+                self._stream.synchronize()
+            torch.cuda.caching_allocator_delete(p)
+
+        # the callbacks must outlive the context
+        self._alloc_cb = abi.ALLOC_FN(alloc)
+        self._free_cb = abi.FREE_FN(free)
+        self.h = abi.mlfft_create(device, self._stream.cuda_stream, self._alloc_cb, self._free_cb)
         self.arrays = {}
+
+    def library_bytes(self) -> int:
+        """Device bytes the library currently holds (all drawn from PyTorch's allocator)."""
+        return int(sum(n for n, _ in self._live.values()))
 
     def close(self):
         if self.h is not None:
@@ -45,7 +84,8 @@ class Context:
             pass
 
     def sync_stream(self):
-        abi.mlfft_set_stream(self.h, torch.cuda.current_stream(self.torch_device).cuda_stream)
+        self._stream = torch.cuda.current_stream(self.torch_device)
+        abi.mlfft_set_stream(self.h, self._stream.cuda_stream)
 
     # ---------------------------------------------------------------- arrays
     def set_blocks(self, array_id: int, blocks) -> None:
@@ -132,7 +172,8 @@ class Context:
         out = dict(status=status, iters=arrs["iters"].copy(), outer=arrs["outer"].copy(),
                    relres=arrs["relres"].copy(), converged=arrs["converged"].astype(bool),
                    fallbacks=info.fallbacks, matvecs64=info.matvecs64, matvecs_inner=info.matvecs_inner,
-                   precond_applies=info.precond_applies, net_applies=info.net_applies)
+                   precond_applies=info.precond_applies, net_applies=info.net_applies,
+                   pc_switched=info.pc_switched)
         if history_len:
             out["history"] = arrs["history"].reshape(history_len, Wt).copy()
         return out

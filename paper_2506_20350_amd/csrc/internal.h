@@ -91,5 +91,8 @@ hipError_t launch_fill_identity_fallback(double2* Sinv, const double2* R00inv, c
 
 namespace mlfft {
 hipError_t launch_nonfinite(const double* a, size_t n, int* flag, hipStream_t s);
+// out = alpha * x + beta * y over n complex values (y may be NULL); in_prec / out_prec: P64 or P32
+hipError_t launch_axpby(int in_prec, const void* x, const void* y, double alpha, double beta, int out_prec, void* out,
+                        size_t n, hipStream_t s);
 hipError_t launch_replicate(double2* dst, const double2* src, int nb, int bb, hipStream_t s);
 }  // namespace mlfft

@@ -37,9 +37,10 @@ hipError_t Buf::ensure(size_t bytes) {
     if (n >= bytes && p) return hipSuccess;
     release();
     if (bytes == 0) return hipSuccess;
+    if (!al || !al->fn) return hipErrorInvalidValue;     // a buffer never bound to an allocator
     ++g_mem_epoch;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) { p = nullptr; n = 0; return e; }
+    p = al->fn(bytes, al->user);
+    if (!p) { n = 0; return hipErrorOutOfMemory; }
     n = bytes;
     return hipSuccess;
 }
@@ -47,7 +48,7 @@ hipError_t Buf::ensure(size_t bytes) {
 void Buf::release() {
     if (p) {
         ++g_mem_epoch;
-        (void)hipFree(p);
+        al->fr(p, al->user);
     }
     p = nullptr;
     n = 0;
@@ -214,7 +215,8 @@ mlfft_status Ctx::fft_grouped(int prec, std::vector<FftTask>& tasks, bool invers
 }
 
 // y = alpha * Z x + beta * addend over a group of arrays (one grouped launch per phase)
-mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec) {
+mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec, void* ws_a, void* ws_b,
+                                size_t ws_bytes) {
     Ctx* c = this;
     const int nt = (int)items.size();
     if (nt == 0) return MLFFT_OK;
@@ -228,24 +230,35 @@ mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec) {
         need += (size_t)a->K * a->b * items[i].W * eb;
         need = (need + 255) / 256 * 256;
     }
-    HIPCHK(spec_a.ensure(need), "spectral workspace");
-    HIPCHK(spec_b.ensure(need), "spectral workspace");
+    char* sa;
+    char* sb;
+    if (ws_a || ws_b) {
+        if (!ws_a || !ws_b || need > ws_bytes)
+            return fail(MLFFT_E_ARG, "spectral workspace of %zu bytes needed, %zu supplied", need, ws_bytes);
+        sa = (char*)ws_a;
+        sb = (char*)ws_b;
+    } else {
+        HIPCHK(spec_a.ensure(need), "spectral workspace");
+        HIPCHK(spec_b.ensure(need), "spectral workspace");
+        sa = (char*)spec_a.p;
+        sb = (char*)spec_b.p;
+    }
     std::vector<FftTask> fw(nt), iv(nt);
     std::vector<GemmTask> gm(nt);
     for (int i = 0; i < nt; ++i) {
         const MatvecItem& it = items[i];
         const Array* a = it.arr;
         FftTask t{};
-        t.in = it.x; t.out = (char*)spec_a.p + off[i]; t.addend = nullptr; t.alpha = 1.0; t.beta = 0.0;
+        t.in = it.x; t.out = sa + off[i]; t.addend = nullptr; t.alpha = 1.0; t.beta = 0.0;
         t.Nx = a->Nx; t.Ny = a->Ny; t.b = a->b; t.W = it.W; t.pad = 1;
         fw[i] = t;
         GemmTask g{};
         g.G = prec == P64 ? a->G64.p : prec == P32 ? a->G32.p : a->G16.p;
-        g.X = (char*)spec_a.p + off[i]; g.Y = (char*)spec_b.p + off[i];
+        g.X = sa + off[i]; g.Y = sb + off[i];
         g.K = a->K; g.b = a->b; g.W = it.W; g.gstride = (long)a->b * a->b;
         gm[i] = g;
         FftTask u{};
-        u.in = (char*)spec_b.p + off[i]; u.out = it.y; u.addend = it.addend;
+        u.in = sb + off[i]; u.out = it.y; u.addend = it.addend;
         u.alpha = it.alpha / (double)a->K; u.beta = it.beta;
         u.Nx = a->Nx; u.Ny = a->Ny; u.b = a->b; u.W = it.W; u.pad = 1;
         iv[i] = u;
@@ -361,7 +374,7 @@ static mlfft_status build_array(Ctx* c, Array& a, const double2* Rdev) {
     const int nly = 2 * Ny - 1, nlx = 2 * Nx - 1;
     hipStream_t s = c->stream;
     // spectra on the (2Ny) x (2Nx) grid
-    Buf T;
+    Buf T(&c->alloc);
     const size_t tb = (size_t)nly * a.Px * bb * sizeof(double2);
     HIPCHK(T.ensure(tb), "spectra scratch");
     HIPCHK(a.G64.ensure((size_t)a.K * bb * sizeof(double2)), "spectra");
@@ -376,13 +389,13 @@ static mlfft_status build_array(Ctx* c, Array& a, const double2* Rdev) {
     std::vector<double> wx, wy;
     strang_weights(Nx, wx);
     strang_weights(Ny, wy);
-    Buf Wt;
+    Buf Wt(&c->alloc);
     HIPCHK(Wt.ensure((wx.size() + wy.size()) * sizeof(double)), "weights");
     HIPCHK(hipMemcpyAsync(Wt.p, wx.data(), wx.size() * sizeof(double), hipMemcpyHostToDevice, s), "weights");
     HIPCHK(hipMemcpyAsync((double*)Wt.p + wx.size(), wy.data(), wy.size() * sizeof(double),
                           hipMemcpyHostToDevice, s), "weights");
     const int Kp = Nx * Ny;
-    Buf Sh, Aw, rc, inf;
+    Buf Sh(&c->alloc), Aw(&c->alloc), rc(&c->alloc), inf(&c->alloc);
     HIPCHK(Sh.ensure((size_t)Kp * bb * sizeof(double2)), "preconditioner scratch");
     HIPCHK(launch_lag_dft_x(Rdev, (double2*)T.p, nly, nlx, -(Nx - 1), Nx, (double*)Wt.p, bb, s), "strang x");
     HIPCHK(launch_lag_dft_y((double2*)T.p, (double2*)Sh.p, nly, -(Ny - 1), Ny, Nx, (double*)Wt.p + wx.size(), bb, s),
@@ -436,9 +449,11 @@ static mlfft_status build_array(Ctx* c, Array& a, const double2* Rdev) {
 
 extern "C" {
 
-mlfft_status mlfft_create(int device, void* hip_stream, mlfft_ctx* out) {
+mlfft_status mlfft_create(int device, void* hip_stream, mlfft_alloc_fn alloc_fn, mlfft_free_fn free_fn, void* user,
+                          mlfft_ctx* out) {
     if (!out) { g_create_error = "out is NULL"; return MLFFT_E_ARG; }
     *out = nullptr;
+    if (!alloc_fn || !free_fn) { g_create_error = "alloc_fn and free_fn must not be NULL"; return MLFFT_E_ARG; }
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess || device < 0 || device >= n) {
@@ -451,6 +466,10 @@ mlfft_status mlfft_create(int device, void* hip_stream, mlfft_ctx* out) {
     Ctx* c = new Ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    c->alloc.fn = alloc_fn;
+    c->alloc.fr = free_fn;
+    c->alloc.user = user;
+    for (Buf* b : {&c->spec_a, &c->spec_b, &c->task_dev, &c->solve_ws, &c->solve_ws2}) b->bind(&c->alloc);
     *out = c;
     return MLFFT_OK;
 }
@@ -492,13 +511,13 @@ mlfft_status mlfft_set_blocks(mlfft_ctx ctx, int array_id, int Nx, int Ny, int b
         for (size_t i = 0; i < 2 * nblk; ++i)
             if (!std::isfinite(h[i])) return c->fail(MLFFT_E_ARG, "blocks contain a non-finite value at %zu", i / 2);
     }
-    Buf R;
+    Buf R(&c->alloc);
     HIPCHK(R.ensure(nblk * sizeof(double2)), "block upload");
     HIPCHK(hipMemcpyAsync(R.p, blocks, nblk * sizeof(double2),
                           blocks_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream),
            "block upload");
     if (blocks_on_device) {
-        Buf flag;
+        Buf flag(&c->alloc);
         HIPCHK(flag.ensure(sizeof(int)), "flag");
         HIPCHK(hipMemsetAsync(flag.p, 0, sizeof(int), c->stream), "flag");
         HIPCHK(launch_nonfinite((const double*)R.p, 2 * nblk, (int*)flag.p, c->stream), "finite check");
@@ -514,6 +533,7 @@ mlfft_status mlfft_set_blocks(mlfft_ctx ctx, int array_id, int Nx, int Ny, int b
         c->arrays.erase(old);
     }
     Array a;
+    a.bind(&c->alloc);
     a.Nx = Nx; a.Ny = Ny; a.b = b;
     a.Px = 2 * Nx; a.Py = 2 * Ny; a.K = a.Px * a.Py;
     mlfft_status st = build_array(c, a, (const double2*)R.p);
@@ -601,6 +621,49 @@ mlfft_status mlfft_matvec(mlfft_ctx ctx, int array_id, int W, const void* x, voi
     std::vector<MatvecItem> items(1);
     items[0] = MatvecItem{a, W, x, y, nullptr, 1.0, 0.0};
     return c->matvec_group(items, prec);
+}
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    return (const char*)a < (const char*)b + nb && (const char*)b < (const char*)a + na;
+}
+
+mlfft_status mlfft_matvec_axpby(mlfft_ctx ctx, int array_id, int W, double alpha, const void* x, double beta,
+                                const void* v, void* y, mlfft_prec prec) {
+    if (!ctx) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    Array* a = c->find(array_id);
+    if (!a) return c->fail(MLFFT_E_STATE, "unknown array id %d", array_id);
+    if (W < 0) return c->fail(MLFFT_E_ARG, "W must be >= 0");
+    if (prec < MLFFT_FP64 || prec > MLFFT_FP32_BF16GEMM) return c->fail(MLFFT_E_ARG, "invalid precision");
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return c->fail(MLFFT_E_ARG, "alpha and beta must be finite");
+    if (W == 0) return MLFFT_OK;
+    if (!x || !y) return c->fail(MLFFT_E_ARG, "x or y is NULL");
+    const size_t vb = (size_t)a->Nx * a->Ny * a->b * W * prec_elem_bytes(prec);
+    if (overlap(x, vb, y, vb)) return c->fail(MLFFT_E_ARG, "x and y overlap");
+    if (v && overlap(v, vb, y, vb)) return c->fail(MLFFT_E_ARG, "v and y overlap");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    std::vector<MatvecItem> items(1);
+    items[0] = MatvecItem{a, W, x, y, v, alpha, v ? beta : 0.0};
+    return c->matvec_group(items, prec);
+}
+
+mlfft_status mlfft_axpby(mlfft_ctx ctx, size_t n, double alpha, const void* x, double beta, const void* y,
+                         int in_prec, void* out, int out_prec) {
+    if (!ctx) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    if ((in_prec != MLFFT_FP64 && in_prec != MLFFT_FP32) || (out_prec != MLFFT_FP64 && out_prec != MLFFT_FP32))
+        return c->fail(MLFFT_E_ARG, "precisions must be MLFFT_FP64 or MLFFT_FP32");
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return c->fail(MLFFT_E_ARG, "alpha and beta must be finite");
+    if (n == 0) return MLFFT_OK;
+    if (!x || !out) return c->fail(MLFFT_E_ARG, "x or out is NULL");
+    const size_t ib = n * prec_elem_bytes(in_prec), ob = n * prec_elem_bytes(out_prec);
+    // out may be x or y itself (each element is read before it is written), but no partial overlap
+    if (overlap(x, ib, out, ob) && !(x == out && ib == ob)) return c->fail(MLFFT_E_ARG, "x and out partially overlap");
+    if (y && overlap(y, ib, out, ob) && !(y == out && ib == ob))
+        return c->fail(MLFFT_E_ARG, "y and out partially overlap");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    HIPCHK(launch_axpby(in_prec, x, y, alpha, beta, out_prec, out, n, c->stream), "axpby");
+    return MLFFT_OK;
 }
 
 mlfft_status mlfft_precond_apply(mlfft_ctx ctx, int array_id, int kind, int W, const void* r, void* z,

@@ -14,18 +14,31 @@ namespace mlfft {
 // graph holds raw device addresses and is valid only while this is unchanged.
 extern unsigned long g_mem_epoch;
 
+// The caller's device allocator (mlfft_create): every device buffer of the
+// library comes from it and goes back to it.
+struct Alloc {
+    mlfft_alloc_fn fn = nullptr;
+    mlfft_free_fn fr = nullptr;
+    void* user = nullptr;
+};
+
+// A device buffer drawn from the context's allocator.  bind() names the
+// allocator; ensure() grows the buffer (contents are not kept).
 struct Buf {
     void* p = nullptr;
     size_t n = 0;
+    const Alloc* al = nullptr;
     Buf() = default;
+    explicit Buf(const Alloc* a) : al(a) {}
     Buf(const Buf&) = delete;
     Buf& operator=(const Buf&) = delete;
-    Buf(Buf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    Buf(Buf&& o) noexcept : p(o.p), n(o.n), al(o.al) { o.p = nullptr; o.n = 0; }
     Buf& operator=(Buf&& o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) { release(); p = o.p; n = o.n; al = o.al; o.p = nullptr; o.n = 0; }
         return *this;
     }
     ~Buf() { release(); }
+    void bind(const Alloc* a) { al = a; }
     hipError_t ensure(size_t bytes);
     void release();
 };
@@ -39,6 +52,9 @@ struct Array {
     double pc_min_rcond = 1.0;
     size_t bytes() const;
     void release();
+    void bind(const Alloc* a) {
+        for (Buf* b : {&G64, &G32, &G16, &S64, &S32, &S16, &K64, &K32, &K16}) b->bind(a);
+    }
 };
 
 // y = alpha * Op(x) + beta * addend for one array (W columns)
@@ -70,6 +86,7 @@ enum ProfKind { PK_FFT_FWD = 0, PK_GEMM, PK_FFT_INV, PK_PC_FFT_FWD, PK_PC_GEMM, 
 struct mlfft_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    mlfft::Alloc alloc;            // the caller's device allocator
     std::string err;
     std::map<int, mlfft::Array> arrays;
     mlfft::Buf spec_a, spec_b;     // spectral workspaces of the matvec / preconditioner
@@ -120,7 +137,10 @@ struct mlfft_ctx_s {
     mlfft_status upload_tasks(const void* host, size_t bytes, void** dev);
     mlfft_status gemm_grouped(int prec, std::vector<mlfft::GemmTask>& gm, int tag, const char* what);
     mlfft_status fft_grouped(int prec, std::vector<mlfft::FftTask>& tasks, bool inverse, const char* what);
-    mlfft_status matvec_group(const std::vector<mlfft::MatvecItem>& items, int prec);
+    // ws_a, ws_b: spectral workspaces of ws_bytes each supplied by the caller (both NULL: the
+    // context's own spec_a, spec_b, grown as needed)
+    mlfft_status matvec_group(const std::vector<mlfft::MatvecItem>& items, int prec, void* ws_a = nullptr,
+                              void* ws_b = nullptr, size_t ws_bytes = 0);
     mlfft_status precond_group(const std::vector<mlfft::MatvecItem>& items, int kind, int prec);
     void release_workspaces() {
         graphs_release();

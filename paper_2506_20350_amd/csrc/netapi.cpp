@@ -148,7 +148,24 @@ static mlfft_status pack_all(Ctx* c, Net& n) {
 
 extern "C" {
 
-mlfft_status mlfft_net_create(mlfft_ctx ctx, int b, int hidden) {
+// splitmix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", 2014) of a counter: the i-th 64-bit value of stream `seed`
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// standard normal number i of stream seed (Box-Muller on two counter-based uniforms in (0, 1))
+static double normal_draw(uint64_t seed, uint64_t i) {
+    const uint64_t base = splitmix64(seed) ^ (i * 2);
+    const double u1 = ((splitmix64(base) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    const double u2 = ((splitmix64(base ^ 1) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+mlfft_status mlfft_net_create(mlfft_ctx ctx, int b, int hidden, unsigned seed) {
     if (!ctx) return MLFFT_E_ARG;
     Ctx* c = ctx;
     if (b < 1 || b > 256) return c->fail(MLFFT_E_ARG, "b must be in [1, 256]");
@@ -157,6 +174,14 @@ mlfft_status mlfft_net_create(mlfft_ctx ctx, int b, int hidden) {
     HIPCHK(hipStreamSynchronize(c->stream), "net create");
     c->net_release();
     Net* n = new Net();
+    for (Buf* x : {&n->wmaster, &n->m, &n->v, &n->dw, &n->out, &n->yhat, &n->scale, &n->phase, &n->tgt, &n->g0, &n->g1,
+                   &n->loss, &n->fb})
+        x->bind(&c->alloc);
+    for (int l = 0; l < 4; ++l) {
+        n->wbf[l].bind(&c->alloc);
+        n->dwp[l].bind(&c->alloc);
+        n->act[l].bind(&c->alloc);
+    }
     n->b = b;
     n->hidden = hidden;
     const int ch[5] = {2 * b, hidden, hidden, hidden, 2 * b};
@@ -175,7 +200,16 @@ mlfft_status mlfft_net_create(mlfft_ctx ctx, int b, int hidden) {
     HIPCHK(n->m.ensure(off * 4), "weights");
     HIPCHK(n->v.ensure(off * 4), "weights");
     HIPCHK(n->dw.ensure(off * 4), "weights");
-    HIPCHK(hipMemsetAsync(n->wmaster.p, 0, off * 4, c->stream), "weights");
+    // He-normal weights (standard deviation sqrt(2 / (9 c_in))) for the first three
+    // layers from the seed, zeros for the last one; seed 0: all zeros
+    std::vector<float> w0(off, 0.f);
+    if (seed != 0)
+        for (int l = 0; l < 3; ++l) {
+            const double sd = std::sqrt(2.0 / (9.0 * n->cin[l]));
+            const size_t cnt = (size_t)n->cin[l] * n->cout[l] * 9;
+            for (size_t i = 0; i < cnt; ++i) w0[n->woff[l] + i] = (float)(sd * normal_draw(seed, n->woff[l] + i));
+        }
+    HIPCHK(hipMemcpyAsync(n->wmaster.p, w0.data(), off * 4, hipMemcpyHostToDevice, c->stream), "weights");
     HIPCHK(hipMemsetAsync(n->m.p, 0, off * 4, c->stream), "weights");
     HIPCHK(hipMemsetAsync(n->v.p, 0, off * 4, c->stream), "weights");
     for (int l = 0; l < 4; ++l) {

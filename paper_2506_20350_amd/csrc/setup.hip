@@ -101,6 +101,41 @@ hipError_t launch_cast_c64_to_bf16(const double2* a, uint32_t* b, size_t n, hipS
     return hipGetLastError();
 }
 
+// out = alpha * x + beta * y elementwise over n complex values (y may be NULL),
+// reading TI and writing TO (complex128 or complex64; the sum is formed in FP64)
+template<typename TI, typename TO>
+__global__ void axpby_kernel(const TI* x, const TI* y, double alpha, double beta,
+                             TO* out, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double re = alpha * (double)x[i].x, im = alpha * (double)x[i].y;
+        if (y) {
+            re += beta * (double)y[i].x;
+            im += beta * (double)y[i].y;
+        }
+        TO o;
+        o.x = re;
+        o.y = im;
+        out[i] = o;
+    }
+}
+
+hipError_t launch_axpby(int in_prec, const void* x, const void* y, double alpha, double beta, int out_prec, void* out,
+                        size_t n, hipStream_t s) {
+    if (in_prec == P64 && out_prec == P64)
+        hipLaunchKernelGGL((axpby_kernel<double2, double2>), grid_for(n), dim3(256), 0, s, (const double2*)x,
+                           (const double2*)y, alpha, beta, (double2*)out, n);
+    else if (in_prec == P64)
+        hipLaunchKernelGGL((axpby_kernel<double2, float2>), grid_for(n), dim3(256), 0, s, (const double2*)x,
+                           (const double2*)y, alpha, beta, (float2*)out, n);
+    else if (out_prec == P64)
+        hipLaunchKernelGGL((axpby_kernel<float2, double2>), grid_for(n), dim3(256), 0, s, (const float2*)x,
+                           (const float2*)y, alpha, beta, (double2*)out, n);
+    else
+        hipLaunchKernelGGL((axpby_kernel<float2, float2>), grid_for(n), dim3(256), 0, s, (const float2*)x,
+                           (const float2*)y, alpha, beta, (float2*)out, n);
+    return hipGetLastError();
+}
+
 // Gauss-Jordan inversion with partial pivoting of nb independent b x b complex
 // matrices, one workgroup per matrix.  A is destroyed (used as the left half of
 // the augmented matrix in place: the inverse is built in Ainv).  rcond[i] is the

@@ -151,8 +151,14 @@ static std::string graph_key(Ctx* c, const std::vector<Seg>& segs, const Work& w
     const int hl = (info && o.record_history) ? info->history_len : 0;
     const int ints[] = {j, prec, o.precond, o.orth, o.restart, w.Wt, hl, o.mode, o.pc_bf16};
     put(ints, sizeof ints);
-    const void* ptrs[] = {c->solve_ws.p, c->solve_ws2.p, c->pinned, c->spec_a.p, c->spec_b.p};
+    const void* ptrs[] = {c->solve_ws.p, c->solve_ws2.p, c->pinned, c->spec_a.p, c->spec_b.p,
+                          // the carved workspace (its offsets move with the in-place / staged layout and
+                          // with the stored preconditioned directions) and the scale of the Krylov columns'
+                          // right-hand sides (||V|| at x = 0, ||r|| afterwards), which the rotations read
+                          w.v64, w.x64, w.r64, w.rT, w.dT, w.tmpT, w.tmp2T, w.Vb, w.Zb, w.kscale, w.H, w.g, w.hist};
     put(ptrs, sizeof ptrs);
+    const int flags[] = {w.zstore ? 1 : 0};
+    put(flags, sizeof flags);
     put(&w.S, sizeof w.S);
     for (const Seg& sg : segs) {
         put(&sg.arr, sizeof sg.arr);
@@ -429,6 +435,18 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     }
     w.zstore = zstore;
     HIPCHK(c->solve_ws2.ensure(small), "Krylov workspace");
+    // The spectral workspaces of the largest product of the solve (the FP64 true
+    // residual of every array) are reserved here as well, so that a solve too large
+    // for the device fails with MLFFT_E_NOMEM before anything is enqueued.
+    {
+        size_t need = 0;
+        for (const Seg& sg : segs) {
+            need += (size_t)sg.arr->K * sg.arr->b * sg.W * 16;
+            need = align_up(need);
+        }
+        HIPCHK(c->spec_a.ensure(need), "spectral workspace");
+        HIPCHK(c->spec_b.ensure(need), "spectral workspace");
+    }
     char* p = (char*)c->solve_ws.p;
     if (in_place) {
         w.v64 = (double2*)const_cast<void*>(segs[0].V);    // read only
@@ -518,6 +536,14 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     // update is masked to the solved columns, so the residual of an array with
     // no solved column is still current
     std::vector<Seg> rsegs = segs;
+    // The learned correction is judged by the FP64 true residual: an inner solve asks
+    // every column it solves for a reduction of at least 0.3, so a refinement step
+    // that leaves the residual of those columns above half of what it was (2-norm
+    // over them) means the corrected preconditioner does not work for this system;
+    // the remaining steps then use the plain block-circulant preconditioner.
+    mlfft_solve_opts oi = o;
+    std::vector<double> hprev(Wt, 0.0);
+    std::vector<char> solved_prev(Wt, 0);
     for (int outer = 0; outer < o.max_outer; ++outer) {
         const double2* rsrc = w.r64;
         if (outer == 0 && !o.x0_given) {
@@ -537,6 +563,15 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
             HIPCHK(k_colnorm<double2>(w.r64, cols, w.rnorm, s), "norms");
             HIPCHK(hipMemcpyAsync(hr.data(), w.rnorm, Wt * sizeof(double), hipMemcpyDeviceToHost, s), "norms");
             HIPCHK(hipStreamSynchronize(s), "norms");
+        }
+        if (oi.precond == 3 && outer > 0) {
+            double r2 = 0.0, p2 = 0.0;
+            for (int i = 0; i < Wt; ++i)
+                if (solved_prev[i]) { r2 += hr[i] * hr[i]; p2 += hprev[i] * hprev[i]; }
+            if (p2 > 0.0 && r2 > 0.25 * p2) {
+                oi.precond = 1;
+                if (info) info->pc_switched = 1;
+            }
         }
         int active = 0;
         for (int i = 0; i < Wt; ++i) {
@@ -579,8 +614,12 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
             HIPCHK((k_scale_cols<double2, double2>(rsrc, w.rT, cols, scale, 1, s)), "scale r");
         else
             HIPCHK((k_scale_cols<double2, float2>(rsrc, w.rT, cols, scale, 1, s)), "scale r");
-        mlfft_status st = prec == P64 ? inner_solve<double2>(c, segs, w, kc, o, prec, info, hstate)
-                                      : inner_solve<float2>(c, segs, w, kc, o, prec, info, hstate);
+        for (int i = 0; i < Wt; ++i) {
+            solved_prev[i] = hstate[i] ? 1 : 0;
+            hprev[i] = hr[i];
+        }
+        mlfft_status st = prec == P64 ? inner_solve<double2>(c, segs, w, kc, oi, prec, info, hstate)
+                                      : inner_solve<float2>(c, segs, w, kc, oi, prec, info, hstate);
         if (st < 0) return st;
         const int assign = x_written ? 0 : 1;
         if (prec == P64)
@@ -673,6 +712,7 @@ mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids
         info->matvecs_inner = 0;
         info->precond_applies = 0;
         info->net_applies = 0;
+        info->pc_switched = 0;
         if (!info->history) info->history_len = 0;
     }
     HIPCHK(hipSetDevice(c->device), "set device");

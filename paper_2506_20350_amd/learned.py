@@ -22,46 +22,42 @@ from . import abi, synth
 from .api import Context
 
 
-def he_init(b: int, hidden: int, seed: int) -> np.ndarray:
-    """He-normal FP32 weights for the first three layers, zeros for the last one (flat layout of the ABI)."""
-    rng = np.random.default_rng(seed)
-    ch = [2 * b, hidden, hidden, hidden, 2 * b]
-    parts = []
-    for l in range(4):
-        n = ch[l + 1] * ch[l] * 9
-        if l == 3:
-            parts.append(np.zeros(n, np.float32))
-        else:
-            parts.append((rng.standard_normal(n) * math.sqrt(2.0 / (9 * ch[l]))).astype(np.float32))
-    return np.concatenate(parts)
-
-
 def make_pairs(ctx: Context, array_id: int, Nx: int, Ny: int, b: int, iters: int = 4, n_random: int = 64,
                seed: int = 0, log=None):
-    """Pairs (y_k, e_k) as complex64 device tensors of shape (P, Nx*Ny*b) from GMRES iterates 0..iters-1."""
+    """Pairs (y_k, e_k) as complex64 device tensors of shape (P, Nx*Ny*b) from GMRES iterates 0..iters-1.
+
+    x* is the FP64 solve to 1e-12; x_k the k-step block-circulant GMRES iterate
+    (x_0 = 0).  r_k = v - Z x_k is one fused product (mlfft_matvec_axpby),
+    y_k = P^{-1} r_k the FP64 preconditioner, and the complex64 pairs are written
+    by mlfft_axpby (y_k cast, e_k = x* - x_k formed and cast in one pass).
+    """
     N = Nx * Ny * b
     V = synth.port_rhs(Nx, Ny, b)
     if n_random:
         V = np.concatenate([V, synth.random_vectors(N, n_random, seed=seed + 7)])
     Vd = torch.from_numpy(V).cuda()
+    W = Vd.shape[0]
     xs, info = ctx.solve(array_id, Vd, tol=1e-12, inner_prec="fp64", precond=1, max_outer=4)
-    ys, es = [], []
+    Y = torch.empty((iters * W, N), dtype=torch.complex64, device=Vd.device)
+    E = torch.empty_like(Y)
+    rk = torch.empty_like(Vd)
+    yk = torch.empty_like(Vd)
+    xk = torch.zeros_like(Vd)
     for k in range(iters):
-        if k == 0:
-            xk = torch.zeros_like(Vd)
-        else:
+        if k > 0:
             xk, _ = ctx.solve(array_id, Vd, tol=1e-14, inner_prec="fp64", precond=1, restart=k, max_restarts=1,
                               max_outer=1)
-        rk = torch.empty_like(Vd)
-        ctx.matvec(array_id, xk, rk)
-        rk = Vd - rk
-        yk = ctx.precond_apply(array_id, rk, kind=1)
-        ys.append(yk.to(torch.complex64))
-        es.append((xs - xk).to(torch.complex64))
+        ctx.sync_stream()
+        abi.mlfft_matvec_axpby(ctx.h, array_id, W, -1.0, xk.data_ptr(), 1.0, Vd.data_ptr(), rk.data_ptr(),
+                               abi.MLFFT_FP64)
+        ctx.precond_apply(array_id, rk, yk, kind=1)
+        abi.mlfft_axpby(ctx.h, W * N, 1.0, yk.data_ptr(), 0.0, None, abi.MLFFT_FP64,
+                        Y[k * W:(k + 1) * W].data_ptr(), abi.MLFFT_FP32)
+        abi.mlfft_axpby(ctx.h, W * N, 1.0, xs.data_ptr(), -1.0, xk.data_ptr(), abi.MLFFT_FP64,
+                        E[k * W:(k + 1) * W].data_ptr(), abi.MLFFT_FP32)
         if log:
-            log(f"[learned] pairs from iterate {k}: |r|/|v| median "
-                f"{float(torch.median(torch.linalg.norm(rk, dim=1) / torch.linalg.norm(Vd, dim=1))):.2e}")
-    return torch.cat(ys), torch.cat(es), info
+            log(f"[learned] pairs from iterate {k}")
+    return Y, E, info
 
 
 def train(ctx: Context, Y: torch.Tensor, E: torch.Tensor, Nx: int, Ny: int, steps: int = 300, batch: int = 16,
@@ -110,8 +106,7 @@ def prepare(ctx: Context, cfg: dict, train_grid: int = 20, hidden: int = 64, ste
     n = train_grid
     t0 = time.perf_counter()
     ctx.set_blocks(array_id, synth.green_blocks(n, n, b, kd, seed=seed))
-    abi.mlfft_net_create(ctx.h, b, hidden)
-    abi.mlfft_net_set_weights(ctx.h, he_init(b, hidden, seed=seed + 11))
+    abi.mlfft_net_create(ctx.h, b, hidden, seed + 11)
     Y, E, _ = make_pairs(ctx, array_id, n, n, b, log=log)
     hist, v0, v1 = train(ctx, Y, E, n, n, steps=steps, lr=lr, log=log)
     abi.mlfft_drop_array(ctx.h, array_id)

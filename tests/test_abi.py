@@ -23,10 +23,16 @@ def test_every_exported_call_has_a_binding_signature():
         assert n in abi._SIGNATURES, n
 
 
-def test_create_rejects_null_out_pointer_without_touching_a_gpu():
-    st = abi.lib().mlfft_create(0, None, None)
+def test_create_rejects_null_out_pointer_and_missing_allocator_without_touching_a_gpu():
+    alloc = abi.ALLOC_FN(lambda n, u: None)
+    free = abi.FREE_FN(lambda p, u: None)
+    st = abi.lib().mlfft_create(0, None, alloc, free, None, None)
     assert st == abi.MLFFT_E_ARG
     assert b"NULL" in abi.lib().mlfft_last_error(None)
+    h = ctypes.c_void_p()
+    st = abi.lib().mlfft_create(0, None, abi.ALLOC_FN(), free, None, ctypes.byref(h))
+    assert st == abi.MLFFT_E_ARG and not h.value
+    assert b"alloc_fn" in abi.lib().mlfft_last_error(None)
 
 
 def test_calls_on_null_context_are_argument_errors():
@@ -47,3 +53,15 @@ def test_default_solve_options_fill_exactly_the_binding_layout():
     assert (o.restart, o.max_restarts, o.tol, o.inner_prec, o.max_outer, o.precond, o.orth) == \
         (30, 100, 1e-6, abi.MLFFT_FP32, 10, 1, 2)
     assert (o.x0_given, o.record_history, o.use_graph, o.mode, o.pc_bf16) == (0, 0, 0, 0, 0)
+
+
+def test_no_device_allocation_call_in_the_library_sources():
+    """Every device buffer comes from the caller's allocator: no hipMalloc / hipFree in csrc/."""
+    import glob
+    import os
+    srcs = glob.glob(os.path.join(abi.PKG, "csrc", "*.cpp")) + glob.glob(os.path.join(abi.PKG, "csrc", "*.hip")) + \
+        glob.glob(os.path.join(abi.PKG, "csrc", "*.h"))
+    for f in srcs:
+        txt = open(f).read()
+        for bad in ("hipMalloc(", "hipMallocAsync", "hipFree(", "hipExtMalloc", "hipMallocManaged"):
+            assert bad not in txt, (f, bad)

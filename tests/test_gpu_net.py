@@ -5,9 +5,19 @@ accumulation; the oracle rounds the same operands to bf16 and accumulates in
 FP64.  A hidden activation rounds to bf16 after an FP32 sum on the GPU and after
 an FP64 sum in the oracle, so an activation lying within ~1e-6 (relative) of a
 bf16 rounding boundary can round to neighbouring bf16 values on the two sides
-(one bf16 ulp = 2^-8 relative).  That happens for a fraction ~1e-6 / 2^-8 of
-the activations and moves the norm-wise output by far less than 1e-3, which
-is the bar used for whole-network quantities.
+(one bf16 ulp = 2^-8 relative).  These rounding decisions, not the arithmetic,
+separate the two sides on random weights, so two kinds of test are run:
+
+* exactly representable cases: sparse weights of +-2^-e and inputs that are
+  small dyadic rationals, so that every convolution sum is exact in FP32 (and
+  every activation exact in bf16) on both sides.  No rounding decision can
+  differ, and the forward pass must agree to 1e-6 and the gradients to the
+  1e-4 bar of the gradient pin (the only rounding left is FP32's in the loss
+  scale and in the backward sums);
+* random weights, where the boundary flips are real.  Measured on the MI355X:
+  forward outputs differ by 4e-8 to 4e-5 per image (the larger values where a
+  hidden activation flipped), gradients by at most 7e-7 per layer.  Forward
+  outputs are held to 1e-3 per image, gradients to the 1e-4 bar.
 """
 import numpy as np
 import pytest
@@ -43,7 +53,75 @@ def rand_weights(b, H, seed, last_scale=0.2):
     return [w.astype(np.float32).astype(np.float64) for w in ws]
 
 
-@pytest.mark.parametrize("b,H,Ny,Nx,W", [(3, 8, 4, 5, 3), (12, 64, 6, 6, 2), (1, 4, 1, 1, 2), (24, 32, 9, 7, 1)])
+def exact_weights(b, H, seed, taps=4):
+    """Weights with `taps` non-zero entries +-2^-e per output channel (e = 2, 1, 1, 2 by layer)."""
+    rng = np.random.default_rng(seed)
+    ch = [2 * b, H, H, H, 2 * b]
+    ws = []
+    for l, e in enumerate((2, 1, 1, 2)):
+        w = np.zeros((ch[l + 1], ch[l], 3, 3))
+        for co in range(ch[l + 1]):
+            for _ in range(taps):
+                w[co, rng.integers(ch[l]), rng.integers(3), rng.integers(3)] = rng.choice([-1.0, 1.0]) * 2.0 ** -e
+        ws.append(w)
+    return ws
+
+
+def exact_columns(N, W, seed):
+    """Columns y whose normalisation is exact: entry 0 is 2 (the strict maximum, phase 0) and
+    4^k - 4 other entries are +-1 or +-i, so ||y|| = 2^k; targets e with small integer parts."""
+    rng = np.random.default_rng(seed)
+    k = 1
+    while 4 ** (k + 1) - 3 <= N:
+        k += 1
+    y = np.zeros((W, N), np.complex128)
+    for w in range(W):
+        y[w, 0] = 2.0
+        idx = 1 + rng.permutation(N - 1)[:4 ** k - 4]
+        y[w, idx] = rng.choice(np.array([1, -1, 1j, -1j]), size=idx.size)
+    e = rng.integers(-2, 3, (W, N)) + 1j * rng.integers(-2, 3, (W, N))
+    return y, e.astype(np.complex128)
+
+
+@pytest.mark.parametrize("b,H,Ny,Nx,W", [(200, 64, 4, 5, 2), (3, 8, 4, 5, 3), (24, 32, 9, 7, 1)])
+def test_network_forward_exactly_representable_matches_oracle(ctx, b, H, Ny, Nx, W):
+    """Includes the channel count of the 30x30, b = 200 network (2b = 400 inputs, H = 64)."""
+    ws = exact_weights(b, H, seed=b + 1)
+    abi.mlfft_net_create(ctx.h, b, H)
+    abi.mlfft_net_set_weights(ctx.h, flat(ws))
+    rng = np.random.default_rng(2)
+    x = rng.integers(-4, 5, (W, Ny, Nx, 2 * b)).astype(np.float32) / 32
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xd)
+    ctx.sync_stream()
+    abi.mlfft_net_forward(ctx.h, W, Ny, Nx, xd.data_ptr(), out.data_ptr())
+    ref, _ = onet.net_forward(x.astype(np.float64), ws, bf16=True)
+    assert np.linalg.norm(ref) > 0
+    assert relerr(to_host(out).real, ref) <= 1e-6
+
+
+@pytest.mark.parametrize("b,H,Nx,Ny,W", [(3, 8, 5, 4, 3), (8, 16, 6, 6, 4), (200, 64, 4, 4, 2)])
+def test_gradients_exactly_representable_match_oracle_at_1e4(ctx, b, H, Nx, Ny, W):
+    """The gradient pin's 1e-4 bar (FP32 GPU gradients against the FP64 oracle), on a case where
+    no bf16 rounding decision can differ; includes the 30x30, b = 200 channel count."""
+    ws = exact_weights(b, H, seed=3 * b + H)
+    abi.mlfft_net_create(ctx.h, b, H)
+    abi.mlfft_net_set_weights(ctx.h, flat(ws))
+    N = Nx * Ny * b
+    y, e = exact_columns(N, W, seed=b)
+    yd, ed = to_dev(y, torch.complex64), to_dev(e, torch.complex64)
+    ctx.sync_stream()
+    g, loss = abi.mlfft_net_grads(ctx.h, W, Ny, Nx, yd.data_ptr(), ed.data_ptr())
+    lref, gref = onet.loss_and_grads(y, e, ws, Nx, Ny, b, bf16=True)
+    assert abs(loss - lref) <= 1e-6 * abs(lref)
+    gg = unflat(g, b, H)
+    for l in range(4):
+        assert np.linalg.norm(gref[l]) > 0, l
+        assert relerr(gg[l].ravel(), gref[l].ravel()) <= 1e-4, l
+
+
+@pytest.mark.parametrize("b,H,Ny,Nx,W", [(3, 8, 4, 5, 3), (12, 64, 6, 6, 2), (1, 4, 1, 1, 2), (24, 32, 9, 7, 1),
+                                         (200, 64, 4, 4, 2)])
 def test_network_forward_matches_oracle(ctx, b, H, Ny, Nx, W):
     ws = rand_weights(b, H, seed=b + H)
     abi.mlfft_net_create(ctx.h, b, H)
@@ -58,7 +136,7 @@ def test_network_forward_matches_oracle(ctx, b, H, Ny, Nx, W):
     assert relerr(to_host(out).real, ref) <= 1e-3
 
 
-@pytest.mark.parametrize("b,H,Nx,Ny,W", [(3, 8, 5, 4, 3), (8, 16, 6, 6, 4)])
+@pytest.mark.parametrize("b,H,Nx,Ny,W", [(3, 8, 5, 4, 3), (8, 16, 6, 6, 4), (200, 64, 4, 4, 2)])
 def test_gradients_match_oracle(ctx, b, H, Nx, Ny, W):
     ws = rand_weights(b, H, seed=7)
     abi.mlfft_net_create(ctx.h, b, H)
@@ -73,7 +151,8 @@ def test_gradients_match_oracle(ctx, b, H, Nx, Ny, W):
     assert abs(loss - lref) <= 1e-4 * abs(lref)
     gg = unflat(g, b, H)
     for l in range(4):
-        assert relerr(gg[l], gref[l]) <= 1e-3, l
+        # the gradient pin's bar; measured per-layer errors are 1e-7 to 7e-7 (b = 3, 8 and 200)
+        assert relerr(gg[l].ravel(), gref[l].ravel()) <= 1e-4, l
 
 
 def test_adam_first_step_closed_form(ctx):
@@ -94,11 +173,38 @@ def test_adam_first_step_closed_form(ctx):
     assert np.max(np.abs(w1 - expect)) <= 1e-6
 
 
+def test_adam_two_steps_closed_form(ctx):
+    """Two Adam steps with gradients g1 (at w0) and g2 (at w1): bias correction of step 2 gives
+    m_hat = (b1 g1 + g2) / (1 + b1) and v_hat = (b2 g1^2 + g2^2) / (1 + b2)."""
+    b, H, Nx, Ny, W = 3, 8, 4, 4, 2
+    ws = rand_weights(b, H, seed=19)
+    abi.mlfft_net_create(ctx.h, b, H)
+    abi.mlfft_net_set_weights(ctx.h, flat(ws))
+    N = Nx * Ny * b
+    y = to_dev(synth.random_vectors(N, W, seed=14), torch.complex64)
+    e = to_dev(synth.random_vectors(N, W, seed=15), torch.complex64)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    ctx.sync_stream()
+    g1, _ = abi.mlfft_net_grads(ctx.h, W, Ny, Nx, y.data_ptr(), e.data_ptr())
+    abi.mlfft_net_train_step(ctx.h, W, Ny, Nx, y.data_ptr(), e.data_ptr(), lr)
+    w1 = abi.mlfft_net_get_weights(ctx.h).astype(np.float64)
+    g2, _ = abi.mlfft_net_grads(ctx.h, W, Ny, Nx, y.data_ptr(), e.data_ptr())
+    abi.mlfft_net_train_step(ctx.h, W, Ny, Nx, y.data_ptr(), e.data_ptr(), lr)
+    w2 = abi.mlfft_net_get_weights(ctx.h).astype(np.float64)
+    g1, g2 = g1.astype(np.float64), g2.astype(np.float64)
+    mh = (b1 * g1 + g2) / (1 + b1)
+    vh = (b2 * g1 ** 2 + g2 ** 2) / (1 + b2)
+    expect = w1 - lr * mh / (np.sqrt(vh) + eps)
+    assert np.max(np.abs(w2 - expect)) <= 1e-6
+    # a bias correction with 1 - b1 in place of 1 - b1^2 would move the weights visibly
+    wrong = w1 - lr * ((b1 * (1 - b1) * g1 + (1 - b1) * g2) / (1 - b1)) / (np.sqrt(vh) + eps)
+    assert np.max(np.abs(wrong - expect)) > 1e-5
+
+
 def test_zero_last_layer_apply_is_identity_and_apply_matches_oracle(ctx):
     Nx, Ny, b, W, H = 5, 4, 6, 3, 16
     ctx.set_blocks(30, synth.green_blocks(Nx, Ny, b, np.pi, seed=0))
-    abi.mlfft_net_create(ctx.h, b, H)
-    abi.mlfft_net_set_weights(ctx.h, learned.he_init(b, H, seed=1))
+    abi.mlfft_net_create(ctx.h, b, H, 1)
     y = synth.random_vectors(Nx * Ny * b, W, seed=6).astype(np.complex64)
     yd = to_dev(y, torch.complex64)
     z = torch.empty_like(yd)
@@ -117,8 +223,7 @@ def test_flexible_gmres_with_identity_correction_matches_plain(ctx):
     Nx, Ny, b = 6, 5, 8
     blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0)
     ctx.set_blocks(31, blocks)
-    abi.mlfft_net_create(ctx.h, b, 8)
-    abi.mlfft_net_set_weights(ctx.h, learned.he_init(b, 8, seed=2))
+    abi.mlfft_net_create(ctx.h, b, 8, 2)
     V = to_dev(synth.port_rhs(Nx, Ny, b))
     I1, i1 = ctx.solve(31, V, tol=1e-10, inner_prec="fp32", precond=1)
     I3, i3 = ctx.solve(31, V, tol=1e-10, inner_prec="fp32", precond=3)
@@ -145,8 +250,7 @@ def test_training_lowers_loss_and_reports_the_iteration_gain(ctx):
     cfg = dict(b=b, kd=np.pi, seed=0)
     n_tr, n_te = 8, 12
     ctx.set_blocks(40, synth.green_blocks(n_tr, n_tr, b, np.pi, seed=0, alpha=1.0))
-    abi.mlfft_net_create(ctx.h, b, H)
-    abi.mlfft_net_set_weights(ctx.h, learned.he_init(b, H, seed=3))
+    abi.mlfft_net_create(ctx.h, b, H, 3)
     Y, E, _ = learned.make_pairs(ctx, 40, n_tr, n_tr, b, iters=4, n_random=32)
     hist, v0, v1 = learned.train(ctx, Y, E, n_tr, n_tr, steps=150, batch=16, lr=2e-3, holdout=16)
     assert v1 < v0

@@ -90,8 +90,8 @@ def test_bf16_preconditioner_product_under_the_learned_correction(ctx):
     blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=2)
     V = synth.port_rhs(Nx, Ny, b)
     ctx.set_blocks(33, blocks)
-    abi.mlfft_net_create(ctx.h, b, 16)
-    ws = learned.he_init(b, 16, seed=4)
+    abi.mlfft_net_create(ctx.h, b, 16, 4)
+    ws = abi.mlfft_net_get_weights(ctx.h)
     ws[-16 * 2 * b * 9:] = np.random.default_rng(5).standard_normal(16 * 2 * b * 9).astype(np.float32) * 0.01
     abi.mlfft_net_set_weights(ctx.h, ws)
     ref = direct.lu_solve(tp.dense_Z(blocks), V)
@@ -253,6 +253,35 @@ def test_full_size_30x30_b120_sampled_columns(ctx, kd):
         assert relerr(to_host(I)[cols], ref) <= 1e-6
 
 
+@pytest.mark.timeout(400)
+def test_full_uneven_batch_of_64_arrays_against_oracle(ctx):
+    """All 64 arrays of the uneven-batch recipe (11 785 ports) in one batched FP32 + FP64-refined
+    solve at the benchmark's tol 1e-6; the centre port of every array is checked against the
+    oracle's FP64 GMRES solution at 1e-12 (relres <= 1e-6 and cond(Z) < 2 bound the error)."""
+    specs = synth.c4_arrays(64, master_seed=0)
+    ids, Vs, blocks_all = [], [], []
+    for i, sp in enumerate(specs):
+        blocks = synth.green_blocks(sp["Nx"], sp["Ny"], sp["b"], sp["kd"], seed=sp["seed"])
+        ctx.set_blocks(200 + i, blocks)
+        ids.append(200 + i)
+        Vs.append(to_dev(synth.port_rhs(sp["Nx"], sp["Ny"], sp["b"])))
+        blocks_all.append(blocks)
+    Is, info = ctx.solve_batch(ids, Vs, tol=1e-6, inner_prec="fp32", precond=1, pc_bf16=1)
+    assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-6)
+    assert info["relres"].size == sum(sp["Nx"] * sp["Ny"] for sp in specs)
+    for i, sp in enumerate(specs):
+        Nx, Ny, b = sp["Nx"], sp["Ny"], sp["b"]
+        col = (Ny // 2) * Nx + Nx // 2
+        V = synth.port_rhs(Nx, Ny, b, cols=[col])
+        Gh = tp.spectra(blocks_all[i], 2 * Ny, 2 * Nx)
+        Sinv = precond.strang_inverse_spectrum(blocks_all[i])
+        ref = krylov.gmres_columns(lambda X: tp.matvec_spectral(Gh, X, Nx, Ny), V,
+                                   lambda X: precond.strang_apply(Sinv, X), tol=1e-12)[0].x
+        assert relerr(to_host(Is[i])[col], ref) <= 2e-6, (i, sp)
+    for i in ids:
+        abi.mlfft_drop_array(ctx.h, i)
+
+
 def test_uneven_batch_like_c4_sampled_against_oracle(ctx):
     """The first 12 arrays of the uneven-batch recipe (Nx, Ny in [4, 24], b in {24, 48, 64, 96},
     kd in [pi/2, pi]) in one batched FP32 + FP64-refined solve; one column of every third array is
@@ -294,8 +323,8 @@ def test_graph_captured_steps_match_eager_on_every_replay(ctx, precond):
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         if precond == 3:
-            abi.mlfft_net_create(ctx.h, 24, 16)
-            ws = learned.he_init(24, 16, seed=4)
+            abi.mlfft_net_create(ctx.h, 24, 16, 4)
+            ws = abi.mlfft_net_get_weights(ctx.h)
             ws[-16 * 48 * 9:] = np.random.default_rng(5).standard_normal(16 * 48 * 9).astype(np.float32) * 0.01
             abi.mlfft_net_set_weights(ctx.h, ws)
         blocks, V = _graph_case(ctx, 70, precond, seed=6)
@@ -311,6 +340,54 @@ def test_graph_captured_steps_match_eager_on_every_replay(ctx, precond):
             assert relerr(to_host(y), to_host(V)) <= 1e-9
     ref = direct.lu_solve(tp.dense_Z(blocks), to_host(V))
     assert relerr(to_host(I0), ref) <= 1e-8
+
+
+def test_graph_replays_follow_the_workspace_layout_and_refinement_scale(ctx):
+    """Captured Krylov steps hold raw workspace addresses, which move between a solve in place
+    (V and I separate), a staged one (I aliasing V) and a staged batch, and the rotations read
+    the scale of the inner right-hand side (||V|| at x = 0, ||r|| in later refinement steps).
+    Alternating those solves with use_graph = 1, several times each, must reproduce the eager
+    solutions, iteration counts and residual histories bit for bit."""
+    Nx, Ny, b = 6, 5, 24
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=8)
+    blocks2 = synth.green_blocks(4, 6, 16, 0.7 * np.pi, seed=9)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ctx.set_blocks(76, blocks)
+        ctx.set_blocks(77, blocks2)
+        V = to_dev(synth.port_rhs(Nx, Ny, b))
+        V2 = to_dev(synth.port_rhs(4, 6, 16))
+        kinds = {
+            "in_place": lambda g: ctx.solve(76, V, torch.zeros_like(V), tol=1e-10, inner_prec="fp32", use_graph=g),
+            "aliased": lambda g: (lambda Vc: ctx.solve(76, Vc, Vc, tol=1e-10, inner_prec="fp32", use_graph=g))(
+                V.clone()),
+            "batch": lambda g: ctx.solve_batch([76, 77], [V, V2], tol=1e-10, inner_prec="fp32", use_graph=g),
+            "bf16_refined": lambda g: ctx.solve(76, V, torch.zeros_like(V), tol=1e-10, inner_prec="bf16",
+                                                use_graph=g, history_len=40),
+        }
+        eager = {}
+        for k, f in kinds.items():
+            I, info = f(0)
+            side.synchronize()
+            eager[k] = ([to_host(x) for x in I] if isinstance(I, list) else to_host(I), info)
+        assert eager["bf16_refined"][1]["outer"].max() >= 2
+        for rep in range(3):
+            for k, f in kinds.items():
+                I, info = f(1)
+                side.synchronize()
+                got = [to_host(x) for x in I] if isinstance(I, list) else to_host(I)
+                ref, rinfo = eager[k]
+                assert info["status"] == abi.MLFFT_OK, (rep, k)
+                if isinstance(got, list):
+                    assert all(np.array_equal(a, c) for a, c in zip(got, ref)), (rep, k)
+                else:
+                    assert np.array_equal(got, ref), (rep, k)
+                assert np.array_equal(info["iters"], rinfo["iters"]), (rep, k)
+                assert np.array_equal(info["relres"], rinfo["relres"]), (rep, k)
+                if "history" in rinfo:
+                    assert np.array_equal(info["history"], rinfo["history"]), (rep, k)
+    ref = direct.lu_solve(tp.dense_Z(blocks), synth.port_rhs(Nx, Ny, b))
+    assert relerr(eager["in_place"][0], ref) <= 1e-8
 
 
 def test_graph_batch_matches_eager_and_null_stream_runs_eagerly(ctx):
@@ -385,9 +462,9 @@ def test_mode_rejects_unknown_value(ctx):
 
 def test_full_size_30x30_b200_autotuned_sampled_columns(ctx):
     """The benchmark configuration: 30x30 array, b = 200, all 900 ports, autotuned launch shapes,
-    FP32 inner + FP64 refinement to the metric's 1e-6; one column checked against the oracle's
-    FP64 GMRES solution at 1e-12 (the oracle needs about a minute of CPU here), and the matvec of
-    the same launch shape on two sampled columns."""
+    FP32 inner + FP64 refinement to the metric's 1e-6; nine columns (the four corner ports, the
+    four edge midpoints and the centre) checked against the oracle's FP64 GMRES solution at 1e-12,
+    and the matvec of the same launch shape on the same columns."""
     Nx = Ny = 30
     b = 200
     blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=0)
@@ -395,16 +472,18 @@ def test_full_size_30x30_b200_autotuned_sampled_columns(ctx):
     for prec in (0, 1):
         abi.mlfft_autotune(ctx.h, 18, Nx * Ny, prec, 1)
     V = synth.port_rhs(Nx, Ny, b)
-    cols = [0, 437]
+    cols = [iy * Nx + ix for iy, ix in [(0, 0), (0, 29), (29, 0), (29, 29), (0, 15), (15, 0), (15, 29), (29, 15),
+                                       (15, 15)]]
     Gh = tp.spectra(blocks, 2 * Ny, 2 * Nx)
     mv = lambda X: tp.matvec_spectral(Gh, X, Nx, Ny)
     Sinv = precond.strang_inverse_spectrum(blocks)
-    ref = krylov.gmres_columns(mv, V[cols[1:]], lambda X: precond.strang_apply(Sinv, X), tol=1e-12)[0].x
+    ref = np.array([r.x for r in krylov.gmres_columns(mv, V[cols], lambda X: precond.strang_apply(Sinv, X),
+                                                      tol=1e-12)])
     # the preconditioner's block product in FP32 and in bf16 (both benchmark options)
     for pc_bf16 in (0, 1):
         I, info = ctx.solve(18, to_dev(V), tol=1e-6, inner_prec="fp32", precond=1, pc_bf16=pc_bf16)
         assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-6)
-        assert relerr(to_host(I)[cols[1]], ref) <= 2e-6   # relres <= 1e-6 and cond(Z) ~ 1.5
+        assert relerr(to_host(I)[cols], ref) <= 2e-6   # relres <= 1e-6 and cond(Z) ~ 1.5
     # the same tuned block-product shape in a plain FP32 matvec, sampled columns against the oracle
     y = to_host(ctx.matvec(18, to_dev(V, torch.complex64), prec="fp32"))
     assert relerr(y[cols], mv(V[cols])) <= 1e-5

@@ -104,3 +104,32 @@ def test_complex_nhwc_roundtrip(b):
     assert t.shape == (2, 3, 4, 2 * b)
     assert t[0, 0, 1, 0] == y[0, b].real and t[0, 0, 1, 1] == y[0, b].imag
     np.testing.assert_array_equal(net.nhwc_to_complex(t), y)
+
+
+def test_adam_two_steps_closed_form():
+    """Step 2 with gradients g1, g2: the bias-corrected moments are m_hat = (b1 g1 + g2) / (1 + b1)
+    and v_hat = (b2 g1^2 + g2^2) / (1 + b2) (divide b1 (1 - b1) g1 + (1 - b1) g2 by 1 - b1^2)."""
+    rng = np.random.default_rng(8)
+    w = [rng.standard_normal((4, 3, 3, 3))]
+    g1 = [rng.standard_normal(w[0].shape)]
+    g2 = [rng.standard_normal(w[0].shape)]
+    opt = net.Adam(w, lr=1e-3)
+    w1 = opt.step(w, g1)
+    w2 = opt.step(w1, g2)
+    b1, b2 = 0.9, 0.999
+    mh = (b1 * g1[0] + g2[0]) / (1 + b1)
+    vh = (b2 * g1[0] ** 2 + g2[0] ** 2) / (1 + b2)
+    np.testing.assert_allclose(w2[0], w1[0] - 1e-3 * mh / (np.sqrt(vh) + 1e-8), rtol=1e-13, atol=1e-15)
+
+
+def test_adam_constant_gradient_moves_every_step_by_lr():
+    """With a constant gradient g the bias-corrected moments are g and g^2 at every step t, so
+    each step moves a weight by lr * g / (|g| + eps); a wrong power of beta in the correction fails."""
+    rng = np.random.default_rng(9)
+    w = [rng.standard_normal((2, 5))]
+    g = [rng.standard_normal((2, 5))]
+    opt = net.Adam(w, lr=2e-3)
+    cur = w
+    for t in range(1, 8):
+        cur = opt.step(cur, g)
+        np.testing.assert_allclose(cur[0], w[0] - t * 2e-3 * g[0] / (np.abs(g[0]) + 1e-8), rtol=0, atol=1e-14)
