@@ -135,6 +135,22 @@ mlfft_status mlfft_array_info(mlfft_ctx ctx, int array_id, mlfft_array_info_t* o
  * Asynchronous on the context's stream. */
 mlfft_status mlfft_matvec(mlfft_ctx ctx, int array_id, int W, const void* x, void* y, mlfft_prec prec);
 
+/* y = Z_A x exactly as mlfft_matvec (same kernels, same results), for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  The two spectral workspaces
+ * of the product come from a fixed array of 2 x 64 MiB in the library's own
+ * device memory (every device the library runs on holds one from module load
+ * until the process ends), never from the allocator: the call allocates
+ * nothing on the device.  Limit: 4 Nx Ny b W x (16 bytes for MLFFT_FP64, 8
+ * otherwise) must not exceed 64 MiB (e.g. W <= 163 at 10 x 10, b = 64 in FP64);
+ * larger products return MLFFT_E_ARG before anything is enqueued.  Every call
+ * on one device shares that device's array: calls that overlap in time on one
+ * device (two contexts or streams running concurrently) race and give wrong
+ * results; calls ordered on one stream are safe.  The array needs no clearing
+ * (each product overwrites the workspace it reads).  Not profiled.  Argument
+ * rules as for mlfft_matvec.  Asynchronous. */
+mlfft_status mlfft_matvec_noalloc(mlfft_ctx ctx, int array_id, int W, const void* x, void* y, mlfft_prec prec);
+
 /* y = alpha Z_A x + beta v for W columns: the MLFFT product of mlfft_matvec with
  * its result scaled and added to v in the inverse transform's epilogue (the true
  * residual V - Z_A I of Sec. III, "ZI = V", is alpha = -1, beta = 1).  v may be

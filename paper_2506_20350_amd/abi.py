@@ -78,6 +78,7 @@ _SIGNATURES = {
     "mlfft_drop_array": (_ST, [_P, _I]),
     "mlfft_array_info": (_ST, [_P, _I, ctypes.POINTER(ArrayInfo)]),
     "mlfft_matvec": (_ST, [_P, _I, _I, _P, _P, _I]),
+    "mlfft_matvec_noalloc": (_ST, [_P, _I, _I, _P, _P, _I]),
     "mlfft_matvec_axpby": (_ST, [_P, _I, _I, ctypes.c_double, _P, ctypes.c_double, _P, _P, _I]),
     "mlfft_axpby": (_ST, [_P, ctypes.c_size_t, ctypes.c_double, _P, ctypes.c_double, _P, _I, _P, _I]),
     "mlfft_precond_apply": (_ST, [_P, _I, _I, _I, _P, _P, _I]),
@@ -164,6 +165,10 @@ def mlfft_array_info(ctx, array_id: int) -> ArrayInfo:
 
 def mlfft_matvec(ctx, array_id: int, W: int, x_ptr: int, y_ptr: int, prec: int):
     return check(ctx, lib().mlfft_matvec(ctx, array_id, W, x_ptr, y_ptr, prec))
+
+
+def mlfft_matvec_noalloc(ctx, array_id: int, W: int, x_ptr: int, y_ptr: int, prec: int):
+    return check(ctx, lib().mlfft_matvec_noalloc(ctx, array_id, W, x_ptr, y_ptr, prec))
 
 
 def mlfft_matvec_axpby(ctx, array_id: int, W: int, alpha: float, x_ptr: int, beta: float, v_ptr, y_ptr: int,

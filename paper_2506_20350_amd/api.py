@@ -40,8 +40,10 @@ class Context:
         self._stream = torch.cuda.current_stream(self.torch_device)
         self._live = {}
         self.max_bytes = max_bytes
+        self.alloc_calls = 0           # allocations the library asked for (granted or refused)
 
         def alloc(nbytes, user):
+            self.alloc_calls += 1
             if self.max_bytes is not None and self.library_bytes() + int(nbytes) > self.max_bytes:
                 return None
             try:

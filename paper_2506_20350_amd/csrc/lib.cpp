@@ -463,6 +463,8 @@ mlfft_status mlfft_create(int device, void* hip_stream, mlfft_alloc_fn alloc_fn,
     }
     e = hipSetDevice(device);
     if (e != hipSuccess) { g_create_error = hipGetErrorString(e); return MLFFT_E_HIP; }
+    e = scratch_init(device);
+    if (e != hipSuccess) { g_create_error = std::string("scratch set-up: ") + hipGetErrorString(e); return MLFFT_E_HIP; }
     Ctx* c = new Ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;

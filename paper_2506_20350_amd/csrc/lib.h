@@ -160,4 +160,9 @@ struct mlfft_ctx_s {
 
 typedef mlfft_ctx_s Ctx;
 
+namespace mlfft {
+// device address of the fixed scratch of mlfft_matvec_noalloc on `device` (the current device)
+hipError_t scratch_init(int device);
+}  // namespace mlfft
+
 int prec_elem_bytes(int prec);
