@@ -172,7 +172,12 @@ mlfft_status mlfft_axpby(mlfft_ctx ctx, size_t n, double alpha, const void* x, d
  *   1 = two-level Strang block circulant: z = IFFT2(S_hat(k)^{-1} FFT2(r)) on the
  *       Ny x Nx torus;
  *   2 = self-block (Kindt) preconditioner P'_K of Sec. III-B: every cell's
- *       b-vector multiplied by R_{0,0}^{-1}.
+ *       b-vector multiplied by R_{0,0}^{-1};
+ *   4 = row preconditioner P'_Z of Sec. III-B: every row of cells (Nx b unknowns)
+ *       multiplied by (T^[1]_0)^{-1}, the inverse of the self interaction of one
+ *       array row (eq. Tblock), as one dense product on MFMA (FP64 for MLFFT_FP64,
+ *       FP32 otherwise).  The inverse is formed on first use (FP64 LU with partial
+ *       pivoting, blocking; MLFFT_E_SINGULAR if its 1-norm rcond is below 1e-14).
  * Layout and precision rules as for mlfft_matvec.  Asynchronous. */
 mlfft_status mlfft_precond_apply(mlfft_ctx ctx, int array_id, int kind, int W, const void* r, void* z,
                                  mlfft_prec prec);
@@ -190,8 +195,9 @@ typedef struct {
                             solve aims at max(inner_tol, 0.3 * tol * ||V_w|| / ||r_w||).  0 (default) = automatic:
                             3e-7 for MLFFT_FP32, 1e-2 for MLFFT_FP32_BF16GEMM; ignored for MLFFT_FP64 */
     int max_outer;       /* FP64 refinement steps (default 10) */
-    int precond;         /* 0 none, 1 block circulant (default), 2 self block (Kindt), 3 learned correction of the
-                            block-circulant output (flexible GMRES; needs a network, see mlfft_net_create) */
+    int precond;         /* 0 none, 1 block circulant (default), 2 self block (Kindt, P'_K), 3 learned correction of
+                            the block-circulant output (flexible GMRES; needs a network, see mlfft_net_create),
+                            4 row preconditioner P'_Z (see mlfft_precond_apply) */
     int orth;            /* 1 classical Gram-Schmidt, 2 classical Gram-Schmidt applied twice (default): the
                             second projection is formed from the FP64 Gram matrix of the stored basis, so
                             both read the basis twice per step; FP64 sums */
@@ -274,6 +280,39 @@ mlfft_status mlfft_solve(mlfft_ctx ctx, int array_id, int W, const void* V, void
 mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids, const int* W,
                                const void* const* V, void* const* I,
                                const mlfft_solve_opts* opts, mlfft_solve_info* info);
+
+/* ------------------------------------------------------------------ direct solver and dense algebra */
+
+/* Z_A I = V by the block Rybicki recursion on level 2 (Sec. III-D, eqs. xmpo, xi,
+ * GM1, HM1, HM, GH): the recursion runs over the Ny rows of the array, its blocks
+ * are the dense level-1 matrices R_p = T^[1]_p (order Nx b, eq. Tblock) formed from
+ * the unique blocks of mlfft_set_blocks, and all W right-hand sides are carried
+ * along.  Every inverse of the recursion (R_0 and the sections D and E of each
+ * order) is formed explicitly in FP64 (LU with partial pivoting) and its 1-norm
+ * reciprocal condition number checked: below 1e-14 the call stops with
+ * MLFFT_E_SINGULAR naming the section (the recursion needs every leading block
+ * section to be invertible).  All products run as FP64 MFMA GEMMs.  V, I: device
+ * complex128, W columns in the vector layout, not overlapping.  min_rcond and
+ * flops (host, may be NULL) receive the smallest rcond met and the floating-point
+ * operations executed (8 per complex multiply-add).  Device memory: about
+ * (4 Ny + 3) (Nx b)^2 x 16 bytes for the duration of the call.  Blocking. */
+mlfft_status mlfft_direct_solve(mlfft_ctx ctx, int array_id, int W, const void* V, void* I, double* min_rcond,
+                                double* flops);
+
+/* C = alpha A B + beta C for column-major complex matrices on the device
+ * (A: M x K, B: K x N, C: M x N, leading dimensions lda >= M, ldb >= K, ldc >= M),
+ * complex128 for MLFFT_FP64 (FP64 MFMA) or complex64 for MLFFT_FP32 (FP32 MFMA).
+ * beta = 0 does not read C.  C must not overlap A or B.  Asynchronous.  The dense
+ * product of the row preconditioner, the direct solver and the border blocks. */
+mlfft_status mlfft_dense_gemm(mlfft_ctx ctx, int prec, int M, int N, int K, double alpha_re, double alpha_im,
+                              const void* A, long lda, const void* B, long ldb, double beta_re, double beta_im, void* C,
+                              long ldc);
+
+/* B <- A^{-1} B for the n x n complex128 matrix A (device, column-major, overwritten
+ * by its LU factors: blocked right-looking LU with partial pivoting, as LAPACK's
+ * zgetrf / zgetrs) and ncols columns of B.  An exactly zero pivot gives
+ * MLFFT_E_SINGULAR.  Blocking. */
+mlfft_status mlfft_dense_solve(mlfft_ctx ctx, int n, void* A, long lda, void* B, long ldb, int ncols);
 
 /* ------------------------------------------------------------------ learned correction */
 /*

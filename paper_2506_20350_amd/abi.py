@@ -274,6 +274,32 @@ def mlfft_net_train_step(ctx, W: int, H: int, Wd: int, y_ptr: int, e_ptr: int, l
     return float(loss.value)
 
 
+_L = ctypes.c_long
+_D = ctypes.c_double
+_SIGNATURES["mlfft_direct_solve"] = (_ST, [_P, _I, _I, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)])
+_SIGNATURES["mlfft_dense_gemm"] = (_ST, [_P, _I, _I, _I, _I, _D, _D, _P, _L, _P, _L, _D, _D, _P, _L])
+_SIGNATURES["mlfft_dense_solve"] = (_ST, [_P, _I, _P, _L, _P, _L, _I])
+
+
+def mlfft_direct_solve(ctx, array_id: int, W: int, V_ptr: int, I_ptr: int):
+    """Returns (smallest rcond of the recursion's inverses, flops executed)."""
+    rc = ctypes.c_double(0.0)
+    fl = ctypes.c_double(0.0)
+    check(ctx, lib().mlfft_direct_solve(ctx, array_id, W, V_ptr, I_ptr, ctypes.byref(rc), ctypes.byref(fl)))
+    return rc.value, fl.value
+
+
+def mlfft_dense_gemm(ctx, prec: int, M: int, N: int, K: int, alpha: complex, A_ptr: int, lda: int, B_ptr: int,
+                     ldb: int, beta: complex, C_ptr: int, ldc: int):
+    alpha, beta = complex(alpha), complex(beta)
+    return check(ctx, lib().mlfft_dense_gemm(ctx, prec, M, N, K, alpha.real, alpha.imag, A_ptr, lda, B_ptr, ldb,
+                                             beta.real, beta.imag, C_ptr, ldc))
+
+
+def mlfft_dense_solve(ctx, n: int, A_ptr: int, lda: int, B_ptr: int, ldb: int, ncols: int):
+    return check(ctx, lib().mlfft_dense_solve(ctx, n, A_ptr, lda, B_ptr, ldb, ncols))
+
+
 _SIGNATURES["mlfft_autotune"] = (_ST, [_P, _I, _I, _I, _I])
 _SIGNATURES["mlfft_tune_report"] = (_ST, [_P, _I, ctypes.c_char_p, ctypes.c_size_t])
 _SIGNATURES["mlfft_tune_import"] = (_ST, [_P, ctypes.c_char_p])

@@ -2,6 +2,7 @@
 // setup), the MLFFT matvec and the preconditioner apply.  The Krylov solver
 // driver lives in solve.cpp.
 #include "lib.h"
+#include "dense.h"
 
 #include <algorithm>
 #include <cmath>
@@ -98,13 +99,15 @@ Array* Ctx::find(int id) {
 }
 
 size_t Array::bytes() const {
-    return G64.n + G32.n + G16.n + S64.n + S32.n + S16.n + K64.n + K32.n + K16.n;
+    return G64.n + G32.n + G16.n + S64.n + S32.n + S16.n + K64.n + K32.n + K16.n + R64.n + Z64.n + Z32.n;
 }
 
 void Array::release() {
     G64.release(); G32.release(); G16.release();
     S64.release(); S32.release(); S16.release();
     K64.release(); K32.release(); K16.release();
+    R64.release(); Z64.release(); Z32.release();
+    row_rcond = 0.0;
 }
 
 #define HIPCHK(call, what)                                   \
@@ -292,6 +295,24 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
     const int nt = (int)items.size();
     if (nt == 0) return MLFFT_OK;
     const int eb = prec_elem_bytes(prec);
+    if (kind == 4) {
+        // row preconditioner P'_Z: every row of cells of every column is one vector of
+        // length Nx b, so the apply is one dense product (T^[1]_0)^{-1} [n x (Ny W)]
+        for (const MatvecItem& it : items) {
+            Array* a = const_cast<Array*>(it.arr);
+            if (it.addend || it.alpha != 1.0) return fail(MLFFT_E_ARG, "row preconditioner apply has no epilogue");
+            STCHK(row_precond_setup(*a));
+            const int n = a->Nx * a->b;
+            const int p = prec == P64 ? 0 : 1;
+            const double bytes = (double)eb * 2 * n * a->Ny * it.W + (p ? 8.0 : 16.0) * n * n;
+            const double flops = 8.0 * n * (double)n * a->Ny * it.W;
+            const int pr = prof_begin(PK_PC_GEMM, prec, bytes, flops);
+            HIPCHK(dense_gemm(p, n, a->Ny * it.W, n, make_double2(1.0, 0.0), p ? a->Z32.p : a->Z64.p, n, 0, it.x, n, 0,
+                              make_double2(0.0, 0.0), it.y, n, 0, 1, stream), "row preconditioner apply");
+            prof_end(pr);
+        }
+        return MLFFT_OK;
+    }
     if (kind == 2) {
         // self block: one b x b product per cell, the whole vector as one frequency
         std::vector<GemmTask> gm(nt);
@@ -540,6 +561,7 @@ mlfft_status mlfft_set_blocks(mlfft_ctx ctx, int array_id, int Nx, int Ny, int b
     a.Px = 2 * Nx; a.Py = 2 * Ny; a.K = a.Px * a.Py;
     mlfft_status st = build_array(c, a, (const double2*)R.p);
     if (st != MLFFT_OK) { a.release(); return st; }
+    a.R64 = std::move(R);           // kept for the direct solver and the row preconditioner
     c->arrays.emplace(array_id, std::move(a));
     return MLFFT_OK;
 }
@@ -674,7 +696,7 @@ mlfft_status mlfft_precond_apply(mlfft_ctx ctx, int array_id, int kind, int W, c
     Ctx* c = ctx;
     Array* a = c->find(array_id);
     if (!a) return c->fail(MLFFT_E_STATE, "unknown array id %d", array_id);
-    if (kind != 1 && kind != 2) return c->fail(MLFFT_E_ARG, "preconditioner kind must be 1 or 2");
+    if (kind != 1 && kind != 2 && kind != 4) return c->fail(MLFFT_E_ARG, "preconditioner kind must be 1, 2 or 4");
     if (W < 0) return c->fail(MLFFT_E_ARG, "W must be >= 0");
     if (prec < MLFFT_FP64 || prec > MLFFT_FP32_BF16GEMM) return c->fail(MLFFT_E_ARG, "invalid precision");
     if (W == 0) return MLFFT_OK;

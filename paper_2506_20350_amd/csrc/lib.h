@@ -48,12 +48,15 @@ struct Array {
     Buf G64, G32, G16;      // block spectra [K][b][b]: complex128, complex64, bf16 pairs
     Buf S64, S32, S16;      // Strang preconditioner inverse spectra [Nx*Ny][b][b]
     Buf K64, K32, K16;      // self-block inverse R_{0,0}^{-1}
+    Buf R64;                // the unique blocks R_{p,q} as given, [p+Ny-1][q+Nx-1][m][n] (direct solver, P'_Z)
+    Buf Z64, Z32;           // row preconditioner P'_Z: (T^[1]_0)^{-1}, (Nx b) x (Nx b) column-major (built on first use)
+    double row_rcond = 0.0; // 1-norm reciprocal condition number of T^[1]_0 (0 until built)
     int pc_fallbacks = 0;
     double pc_min_rcond = 1.0;
     size_t bytes() const;
     void release();
     void bind(const Alloc* a) {
-        for (Buf* b : {&G64, &G32, &G16, &S64, &S32, &S16, &K64, &K32, &K16}) b->bind(a);
+        for (Buf* b : {&G64, &G32, &G16, &S64, &S32, &S16, &K64, &K32, &K16, &R64, &Z64, &Z32}) b->bind(a);
     }
 };
 
@@ -142,6 +145,8 @@ struct mlfft_ctx_s {
     mlfft_status matvec_group(const std::vector<mlfft::MatvecItem>& items, int prec, void* ws_a = nullptr,
                               void* ws_b = nullptr, size_t ws_bytes = 0);
     mlfft_status precond_group(const std::vector<mlfft::MatvecItem>& items, int kind, int prec);
+    // P'_Z of Sec. III-B: (T^[1]_0)^{-1} of array a, built once (dense.cpp)
+    mlfft_status row_precond_setup(mlfft::Array& a);
     void release_workspaces() {
         graphs_release();
         spec_a.release(); spec_b.release(); solve_ws.release(); solve_ws2.release();

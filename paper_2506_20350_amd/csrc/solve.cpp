@@ -98,7 +98,7 @@ static mlfft_status check_opts(Ctx* c, const mlfft_solve_opts& o) {
     if (o.inner_prec != MLFFT_FP64 && (!(o.inner_tol >= 0.0) || !(o.inner_tol < 1.0)))
         return c->fail(MLFFT_E_ARG, "inner_tol must be in [0, 1)");
     if (o.max_outer < 1) return c->fail(MLFFT_E_ARG, "max_outer must be >= 1");
-    if (o.precond < 0 || o.precond > 3) return c->fail(MLFFT_E_ARG, "precond must be 0, 1, 2 or 3");
+    if (o.precond < 0 || o.precond > 4) return c->fail(MLFFT_E_ARG, "precond must be 0, 1, 2, 3 or 4");
     if (o.orth != 1 && o.orth != 2) return c->fail(MLFFT_E_ARG, "orth must be 1 or 2");
     if (o.use_graph != 0 && o.use_graph != 1) return c->fail(MLFFT_E_ARG, "use_graph must be 0 or 1");
     if (o.mode != 0 && o.mode != 1) return c->fail(MLFFT_E_ARG, "mode must be 0 (per right-hand side) or 1 (global)");
