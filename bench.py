@@ -356,14 +356,120 @@ def bench_small(a, torch):
     ctx.close()
 
 
+def bench_direct(a, torch):
+    """The block Rybicki direct solver (Sec. III-D) on one array: all port excitations in one
+    mlfft_direct_solve; every GEMM on FP64 MFMA.  Reports RHS/s and the FP64 MFMA fraction
+    of the whole solve (executed flops, LU and inverses included, over wall time)."""
+    from paper_2506_20350_amd import abi, synth
+    from paper_2506_20350_amd.api import Context
+    Nx, Ny, b = a.direct_shape
+    kd = math.pi
+    blocks = synth.green_blocks(Nx, Ny, b, kd, seed=0)
+    V = synth.port_rhs(Nx, Ny, b)
+    ctx = Context(0)
+    ctx.set_blocks(0, blocks)
+    Vd = torch.from_numpy(V).cuda()
+    I = torch.empty_like(Vd)
+    W = V.shape[0]
+    times, flops, rc = [], 0.0, 0.0
+    for rep in range(a.warmup + a.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.sync_stream()
+        rc, flops = abi.mlfft_direct_solve(ctx.h, 0, W, Vd.data_ptr(), I.data_ptr())
+        torch.cuda.synchronize()
+        if rep >= a.warmup:
+            times.append(time.perf_counter() - t0)
+        log(f"[bench] direct {Nx}x{Ny} b={b}: {times[-1] if times else time.perf_counter() - t0:.3f} s")
+    dt = sum(times) / len(times)
+    # accuracy: the FP64 MLFFT residual of every column
+    r = torch.empty_like(Vd)
+    ctx.sync_stream()
+    abi.mlfft_matvec_axpby(ctx.h, 0, W, -1.0, I.data_ptr(), 1.0, Vd.data_ptr(), r.data_ptr(), abi.MLFFT_FP64)
+    relres = (torch.linalg.norm(r, dim=1) / torch.linalg.norm(Vd, dim=1)).max().item()
+    ach = flops / dt / 1e12
+    out = dict(metric=f"solved RHS/s, direct block Rybicki ({Nx}x{Ny} array, b={b})", value=round(W / dt, 3),
+               unit="RHS/s", n_gpus=1, steps=a.steps, warmup=a.warmup, ms_per_step=round(dt * 1e3, 3),
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload=f"{Nx}x{Ny} array, b={b}, kd={kd:.4f}, {W} port RHS, block Rybicki on level 2 "
+                                    f"(level-1 blocks of order {Nx * b}), FP64", Nx=Nx, Ny=Ny, b=b, W=W),
+               roofline=dict(bound="mfma", achieved=round(ach, 2), peak=PEAK_MFMA_TFLOPS[0], unit="TFLOP/s",
+                             frac=round(ach / PEAK_MFMA_TFLOPS[0], 4), traffic=None,
+                             note="whole solve: executed flops (GEMMs, LUs, inverses) over wall time"),
+               flops=flops, min_rcond=rc, max_relres_fp64=relres)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_pcmodes(a, torch):
+    """The paper's preconditioner and Krylov-mode comparison (Sec. IV, M1 / M2 / M3; Sec. V):
+    P'_K (self block), P'_Z (row) and the block circulant, each with one Krylov space for all
+    ports (global, M1 / M2) and with one per port batched (split), plus M3 proper (P'_K, one
+    port at a time, on a sample of ports), all in FP64 GMRES(30) to tol, at the generator's
+    loading 10x and at 1x (weakly loaded, more iterations)."""
+    from paper_2506_20350_amd import synth
+    from paper_2506_20350_amd.api import Context
+    Nx, Ny, b = a.pcmodes_shape
+    ctx = Context(0)
+    rows = []
+    for alpha in (10.0, 1.0):
+        blocks = synth.green_blocks(Nx, Ny, b, math.pi, seed=0, alpha=alpha)
+        ctx.set_blocks(0, blocks)
+        Vd = torch.from_numpy(synth.port_rhs(Nx, Ny, b)).cuda()
+        W = Vd.shape[0]
+        for name, pc in (("P'_K", 2), ("P'_Z", 4), ("block circulant", 1)):
+            for mode, mname in ((1, "global"), (0, "split, batched")):
+                opts = dict(tol=a.tol, inner_prec="fp64", precond=pc, mode=mode)
+                ctx.solve(0, Vd, **opts)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = ctx.solve(0, Vd, **opts)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                rows.append(dict(loading=alpha, precond=name, mode=mname, iters_mean=float(info["iters"].mean()),
+                                 ms=round(dt * 1e3, 3), rhs_per_s=round(W / dt, 1),
+                                 converged=int(info["converged"].sum()), W=W))
+                log(f"[bench] loading {alpha:g} {name} {mname}: {rows[-1]['iters_mean']:.2f} iterations, "
+                    f"{dt * 1e3:.1f} ms")
+            if pc == 2:
+                # M3: one port at a time (a sample of ports, scaled to all of them)
+                ns = min(W, 16)
+                cols = np.linspace(0, W - 1, ns).astype(int)
+                its = []
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for c in cols:
+                    _, info = ctx.solve(0, Vd[int(c):int(c) + 1].contiguous(), tol=a.tol, inner_prec="fp64",
+                                        precond=pc)
+                    its.append(float(info["iters"][0]))
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / ns * W
+                rows.append(dict(loading=alpha, precond=name, mode="one port at a time (M3)",
+                                 iters_mean=float(np.mean(its)), ms=round(dt * 1e3, 3), rhs_per_s=round(W / dt, 1),
+                                 converged=None, W=W, sample=f"{ns} ports, time scaled to {W}"))
+    out = dict(metric=f"preconditioner / Krylov-mode comparison ({Nx}x{Ny} array, b={b}, FP64 GMRES(30), tol {a.tol:g})",
+               value=None, unit="table", n_gpus=1, steps=1, warmup=1, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload=f"{Nx}x{Ny} array, b={b}, kd=pi, all ports; loading 10x and 1x",
+                           Nx=Nx, Ny=Ny, b=b),
+               rows=rows)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4"] + sorted(SMALL), default="c5",
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4", "direct", "pcmodes"] + sorted(SMALL),
+                    default="c5",
                     help="c5: 30x30 b=200; c3: 30x30 b=120; c4: 64 uneven arrays in one batched solve; "
-                         "c1, c2: latency of the small cases, eager and with graph-captured Krylov steps")
+                         "c1, c2: latency of the small cases, eager and with graph-captured Krylov steps; "
+                         "direct: the block Rybicki direct solver; pcmodes: P'_K / P'_Z / block circulant, "
+                         "global / split / one port at a time")
+    ap.add_argument("--direct-shape", type=int, nargs=3, default=[30, 30, 120], metavar=("NX", "NY", "B"))
+    ap.add_argument("--pcmodes-shape", type=int, nargs=3, default=[16, 16, 48], metavar=("NX", "NY", "B"))
     ap.add_argument("--form", choices=sorted(FORMS), default="learned")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--pc-prec", choices=["fp32", "bf16"], default="bf16",
@@ -404,6 +510,10 @@ def main():
 
     if a.workload == "c4":
         return bench_batch(a, torch)
+    if a.workload == "direct":
+        return bench_direct(a, torch)
+    if a.workload == "pcmodes":
+        return bench_pcmodes(a, torch)
     if a.workload in SMALL:
         return bench_small(a, torch)
     cfg = WORKLOADS[a.workload]

@@ -216,10 +216,11 @@ typedef struct {
     int mode;            /* 0 (default): one Krylov space per right-hand side (the paper's split
                             mode with all columns batched); 1: global GMRES (eq. ZIVvec), one
                             Krylov space for all W columns (of all arrays of a batch) with
-                            Frobenius inner products; each inner solve aims at
-                            ||R||_F <= f * tol * ||V||_F.  The outer FP64 loop still requires
-                            every column's own relres <= tol and repeats the global inner solve
-                            until it holds; info->iters and info->history then report the
+                            Frobenius inner products; an inner solve aims at
+                            ||R||_F <= f * tol * ||V||_F, and once that holds at
+                            ||R||_F <= f * tol * min ||V_w|| over the columns still above tol.
+                            The outer FP64 loop requires every column's own relres <= tol and
+                            repeats the global inner solve until it holds; info->iters and info->history then report the
                             global iteration for every column.  MLFFT_E_ARG if the batch has
                             more than 2^31-1 unknowns in all. */
     int pc_bf16;         /* 1: an MLFFT_FP32 inner solve runs the per-frequency product of its

@@ -592,10 +592,20 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
         else active_segs(segs, w, hstate.data(), Wt, rsegs);
         const double* scale = r_is_v ? w.vnorm : w.rnorm;
         if (global) {
-            // one inner solve of Z D = R / ||R||_F over all columns, to the Frobenius target
-            double v2 = 0.0, r2 = 0.0;
-            for (int i = 0; i < Wt; ++i) { v2 += hv[i] * hv[i]; r2 += hr[i] * hr[i]; }
-            const double need = (prec == P64 ? 0.9 : 0.3) * o.tol * std::sqrt(v2 / r2);
+            // one inner solve of Z D = R / ||R||_F over all columns.  The first aims at the
+            // Frobenius target ||R||_F <= f tol ||V||_F of the vectorised method; once that
+            // is met, columns still above their own tol are served by aiming the next solve
+            // at ||R||_F <= f tol min ||V_i|| over the unconverged columns, which bounds
+            // every column's residual (the Frobenius target would then ask for nothing).
+            double v2 = 0.0, r2 = 0.0, vmin = HUGE_VAL;
+            for (int i = 0; i < Wt; ++i) {
+                v2 += hv[i] * hv[i];
+                r2 += hr[i] * hr[i];
+                if (hv[i] > 0.0 && hr[i] > o.tol * hv[i]) vmin = std::min(vmin, hv[i]);
+            }
+            const double f = prec == P64 ? 0.9 : 0.3;
+            const bool frob_met = std::sqrt(r2) <= f * o.tol * std::sqrt(v2);
+            const double need = frob_met ? f * o.tol * vmin / std::sqrt(r2) : f * o.tol * std::sqrt(v2 / r2);
             ht[0] = prec == P64 ? need : std::max(inner_floor, need);
             hstate[0] = 0;
             std::vector<double> hg(Wt, std::sqrt(r2));

@@ -452,6 +452,19 @@ def test_global_mode_fp32_refined_batch_matches_lu(ctx):
     assert len(set(info["iters"].tolist())) == 1
 
 
+@pytest.mark.parametrize("precond", [1, 4])
+def test_global_mode_drives_every_column_below_tol_on_a_weakly_loaded_array(ctx, precond):
+    """Global GMRES reaches the Frobenius target ||R||_F <= f tol ||V||_F with some columns still
+    above their own tol (16 x 16, b = 48, loading 1x); the next outer step then aims below
+    f tol min ||V_w||, so every column converges (the Frobenius target alone would ask the
+    next inner solve for no reduction and the outer loop would stall)."""
+    Nx, Ny, b = 16, 16, 48
+    ctx.set_blocks(85, synth.green_blocks(Nx, Ny, b, np.pi, seed=0, alpha=1.0))
+    V = to_dev(synth.port_rhs(Nx, Ny, b))
+    _, info = ctx.solve(85, V, tol=1e-6, inner_prec="fp64", precond=precond, mode=1)
+    assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-6)
+
+
 def test_mode_rejects_unknown_value(ctx):
     Nx, Ny, b = 3, 3, 4
     ctx.set_blocks(84, synth.green_blocks(Nx, Ny, b, np.pi, seed=0))
