@@ -21,6 +21,10 @@ paper's definitions directly, with no blocking or fusion:
              Strang block-circulant preconditioner (a reading, see its module).
   krylov     restarted right-preconditioned GMRES / flexible GMRES per RHS
              (Sec. III-C) and the global (vectorised) variant (eq. ZIVvec).
+  border     the full matrix with border blocks Z_B, Z_C (eq. Zblock): its
+             blockwise product (eq. ZIVblock), the Schur-complement direct
+             solve around the block Rybicki recursion (Sec. III-E) and the
+             block-diagonal preconditioner P_X (Sec. III-B).
   net        FP64 3x3 convolution network used as a learned correction of the
              block-circulant preconditioner: forward, backward, loss, Adam and
              bfloat16 round-to-nearest-even emulation.

@@ -79,6 +79,60 @@ def green_blocks(Nx: int, Ny: int, b: int, kd: float, seed: int = 0,
     return out
 
 
+def border_blocks(Nx: int, Ny: int, b: int, kd: float, seed: int = 0, per_cell: int = 1,
+                  alpha: float = 10.0) -> tuple:
+    """Border blocks Z_B (Nc x N) and Z_C (Nc x Nc) of the same element model (Sec. I, eq. Zblock).
+
+    The border stands in for the shared-edge region of a connected array that the
+    partition of the paper's mesh leaves outside the Toeplitz part: Nc =
+    2 per_cell (Nx + Ny) basis functions just outside the array's perimeter
+    (per_cell along every cell edge of the four sides, at a quarter cell from
+    the outline), with positions and directions drawn from
+    numpy.random.default_rng(seed + 7919) (offset along the side uniform in the
+    cell, then a N(0,1)^3 direction), coupled to the array bases (cell (iy, ix),
+    basis m at r_m + (ix, iy, 0)) and to each other by the same kernel as
+    green_blocks.  Z_C's self terms use rho = a and get the real loading alpha
+    times its largest off-diagonal magnitude.  Returns row-major complex128
+    arrays: Z_B[i, (iy Nx + ix) b + m] and Z_C[i, j].
+    """
+    r, u = element(b, seed)
+    rng = np.random.default_rng(seed + 7919)
+    pos = []
+    for side in range(4):
+        n_edge = Nx if side < 2 else Ny
+        for c in range(n_edge):
+            for _ in range(per_cell):
+                t = c + rng.random()
+                if side == 0:
+                    pos.append((t, -0.25))
+                elif side == 1:
+                    pos.append((t, Ny + 0.25))
+                elif side == 2:
+                    pos.append((-0.25, t))
+                else:
+                    pos.append((Nx + 0.25, t))
+    Nc = len(pos)
+    rc = np.zeros((Nc, 3))
+    rc[:, :2] = np.array(pos)
+    g = rng.standard_normal((Nc, 3))
+    uc = g / np.linalg.norm(g, axis=1, keepdims=True)
+    k = float(kd)
+    a = 0.02 * (2.0 * math.pi / k)
+    # array basis positions and directions in the vector order (iy Nx + ix) b + m
+    iy, ix = np.meshgrid(np.arange(Ny), np.arange(Nx), indexing="ij")
+    ra = (r[None, None, :, :] + np.stack([ix, iy, np.zeros_like(ix)], axis=-1)[:, :, None, :]).reshape(-1, 3)
+    ua = np.broadcast_to(u, (Ny, Nx, b, 3)).reshape(-1, 3)
+    rho_b = np.linalg.norm(rc[:, None, :] - ra[None, :, :], axis=-1)
+    ZB = (uc @ ua.T) * np.exp(-1j * k * rho_b) / (4.0 * math.pi * rho_b)
+    rho_c = np.linalg.norm(rc[:, None, :] - rc[None, :, :], axis=-1)
+    rho_c[np.diag_indices(Nc)] = a
+    ZC = (uc @ uc.T) * np.exp(-1j * k * rho_c) / (4.0 * math.pi * rho_c)
+    off = np.abs(ZC).copy()
+    off[np.diag_indices(Nc)] = 0.0
+    ZC[np.diag_indices(Nc)] += alpha * float(off.max(initial=0.0))
+    return ZB.astype(np.complex128), ZC.astype(np.complex128)
+
+
 def port_rhs(Nx: int, Ny: int, b: int, cols=None, port: int = 0,
              dtype=np.complex128) -> np.ndarray:
     """Unit port excitations, one column per element (Sec. IV).
