@@ -117,12 +117,32 @@ mlfft_status mlfft_set_blocks(mlfft_ctx ctx, int array_id, int Nx, int Ny, int b
 /* Remove an array and free its buffers. */
 mlfft_status mlfft_drop_array(mlfft_ctx ctx, int array_id);
 
+/* Give array `array_id` the border blocks of the full impedance matrix
+ *     Z = [[Z_A, Z_B^T], [Z_B, Z_C]]   (Sec. I, eq. Zblock):
+ * Nc unknowns outside the Toeplitz part (the border of a connected array that the
+ * mesh partition leaves outside the repeated cells), their coupling with the array
+ * Z_B (Nc x N, N = Nx Ny b) and their self interaction Z_C (Nc x Nc), both row-major
+ * complex128 (Z_B[i][(iy Nx + ix) b + m]), host (on_device = 0) or device pointers;
+ * the library copies them.  From then on every vector of the array has N + Nc entries
+ * per column, [x_A (the vector layout above), x_C], and every call works on the full Z:
+ *  - mlfft_matvec multiplies blockwise (eq. ZIVblock): Z_A x_A by the MLFFT product,
+ *    the border terms Z_B^T x_C, Z_B x_A and Z_C x_C as dense MFMA products;
+ *  - preconditioners 1, 2 and 4 become P_X = blockdiag(P'_X, Z_C) (Sec. III-B), the
+ *    border part applied with Z_C^{-1} (formed here, FP64 LU with partial pivoting);
+ *    the learned correction (3) is not defined with a border (MLFFT_E_ARG);
+ *  - mlfft_solve / mlfft_solve_batch run on the full system;
+ *  - mlfft_direct_solve uses the Schur complement of Sec. III-E.
+ * Nc = 0 removes the border.  Z_C with rcond < 1e-14: MLFFT_E_SINGULAR (no border is
+ * kept).  Non-finite entries: MLFFT_E_ARG.  Blocking. */
+mlfft_status mlfft_set_border(mlfft_ctx ctx, int array_id, int Nc, const void* ZB, const void* ZC, int on_device);
+
 typedef struct {
     int Nx, Ny, b;
     int Px, Py;              /* matvec circulant grid, 2Nx x 2Ny */
     int pc_fallbacks;        /* preconditioner frequencies replaced by the self-block inverse */
     double pc_min_rcond;     /* smallest reciprocal condition number over the preconditioner blocks */
     size_t device_bytes;     /* device memory held for this array */
+    int Nc;                  /* border unknowns (mlfft_set_border), 0 without a border */
 } mlfft_array_info_t;
 
 mlfft_status mlfft_array_info(mlfft_ctx ctx, int array_id, mlfft_array_info_t* out);
@@ -285,6 +305,9 @@ mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids
 /* ------------------------------------------------------------------ direct solver and dense algebra */
 
 /* Z_A I = V by the block Rybicki recursion on level 2 (Sec. III-D, eqs. xmpo, xi,
+ * (with a border, mlfft_set_border: Z I = V by the Schur complement of Sec. III-E,
+ * Z_A [U F] = [V_A Z_B^T] through the recursion, I_C = (Z_C - Z_B F)^{-1}(V_C - Z_B U),
+ * I_A = U - F I_C; vectors of N + Nc entries per column)
  * GM1, HM1, HM, GH): the recursion runs over the Ny rows of the array, its blocks
  * are the dense level-1 matrices R_p = T^[1]_p (order Nx b, eq. Tblock) formed from
  * the unique blocks of mlfft_set_blocks, and all W right-hand sides are carried

@@ -41,7 +41,7 @@ class MlfftError(RuntimeError):
 class ArrayInfo(ctypes.Structure):
     _fields_ = [("Nx", ctypes.c_int), ("Ny", ctypes.c_int), ("b", ctypes.c_int),
                 ("Px", ctypes.c_int), ("Py", ctypes.c_int), ("pc_fallbacks", ctypes.c_int),
-                ("pc_min_rcond", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+                ("pc_min_rcond", ctypes.c_double), ("device_bytes", ctypes.c_size_t), ("Nc", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -276,6 +276,13 @@ def mlfft_net_train_step(ctx, W: int, H: int, Wd: int, y_ptr: int, e_ptr: int, l
 
 _L = ctypes.c_long
 _D = ctypes.c_double
+_SIGNATURES["mlfft_set_border"] = (_ST, [_P, _I, _I, _P, _P, _I])
+
+
+def mlfft_set_border(ctx, array_id: int, Nc: int, ZB_ptr, ZC_ptr, on_device: bool):
+    return check(ctx, lib().mlfft_set_border(ctx, array_id, Nc, ZB_ptr or None, ZC_ptr or None, int(on_device)))
+
+
 _SIGNATURES["mlfft_direct_solve"] = (_ST, [_P, _I, _I, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)])
 _SIGNATURES["mlfft_dense_gemm"] = (_ST, [_P, _I, _I, _I, _I, _D, _D, _P, _L, _P, _L, _D, _D, _P, _L])
 _SIGNATURES["mlfft_dense_solve"] = (_ST, [_P, _I, _P, _L, _P, _L, _I])

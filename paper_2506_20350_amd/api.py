@@ -106,17 +106,44 @@ class Context:
         abi.mlfft_set_blocks(self.h, array_id, Nx, Ny, b, blocks.data_ptr(), on_dev)
         self.arrays[array_id] = (Nx, Ny, b)
 
+    def set_border(self, array_id: int, ZB=None, ZC=None) -> None:
+        """Border blocks of the full matrix (Z_B: (Nc, N), Z_C: (Nc, Nc) complex128, host or device);
+        None removes the border.  Vectors of the array then have N + Nc entries per column."""
+        self.sync_stream()
+        if ZB is None:
+            abi.mlfft_set_border(self.h, array_id, 0, None, None, False)
+            Nx, Ny, b = self.arrays[array_id][:3]
+            self.arrays[array_id] = (Nx, Ny, b)
+            return
+        if isinstance(ZB, np.ndarray):
+            ZB = torch.from_numpy(np.ascontiguousarray(ZB, dtype=np.complex128))
+        if isinstance(ZC, np.ndarray):
+            ZC = torch.from_numpy(np.ascontiguousarray(ZC, dtype=np.complex128))
+        ZB, ZC = ZB.contiguous(), ZC.contiguous()
+        Nx, Ny, b = self.arrays[array_id][:3]
+        Nc = ZC.shape[0]
+        if ZB.dtype != torch.complex128 or ZC.dtype != torch.complex128 or tuple(ZB.shape) != (Nc, Nx * Ny * b) \
+                or tuple(ZC.shape) != (Nc, Nc) or ZB.is_cuda != ZC.is_cuda:
+            raise ValueError("ZB must be complex128 (Nc, N) and ZC complex128 (Nc, Nc), on the same device")
+        self.arrays[array_id] = (Nx, Ny, b)          # the library drops the old border first
+        abi.mlfft_set_border(self.h, array_id, Nc, ZB.data_ptr(), ZC.data_ptr(), ZB.is_cuda)
+        self.arrays[array_id] = (Nx, Ny, b, Nc)
+
+    def vec_len(self, array_id: int) -> int:
+        a = self.arrays[array_id]
+        return a[0] * a[1] * a[2] + (a[3] if len(a) > 3 else 0)
+
     def info(self, array_id: int) -> abi.ArrayInfo:
         return abi.mlfft_array_info(self.h, array_id)
 
     def _check_vec(self, array_id: int, t: torch.Tensor, prec: int, name: str) -> int:
-        Nx, Ny, b = self.arrays[array_id]
+        n = self.vec_len(array_id)
         if not t.is_cuda or t.device.index != self.device:
             raise ValueError(f"{name} must be on cuda:{self.device}")
         if t.dtype != PREC_DTYPE[prec]:
             raise ValueError(f"{name} must be {PREC_DTYPE[prec]} for this precision")
-        if not t.is_contiguous() or t.dim() != 2 or t.shape[1] != Nx * Ny * b:
-            raise ValueError(f"{name} must be a contiguous (W, {Nx * Ny * b}) tensor")
+        if not t.is_contiguous() or t.dim() != 2 or t.shape[1] != n:
+            raise ValueError(f"{name} must be a contiguous (W, {n}) tensor")
         return t.shape[0]
 
     # ---------------------------------------------------------------- operators

@@ -30,6 +30,9 @@ hipError_t dense_norm1(const double2* A, long lda, int m, int n, double* work, d
 hipError_t dense_axpby2d(int prec, int m, int n, double2 alpha, const void* X, long ldx, double2 beta, const void* Y,
                          long ldy, void* out, long ldo, hipStream_t s);
 
+// out (n x m) = A^T for the m x n matrix A (complex128; no conjugation)
+hipError_t dense_transpose(const double2* A, long lda, int m, int n, double2* out, long ldo, hipStream_t s);
+
 // A = the m x n identity (prec 0: complex128, 1: complex64)
 hipError_t dense_identity(int prec, void* A, long lda, int m, int n, hipStream_t s);
 

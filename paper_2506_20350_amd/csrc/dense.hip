@@ -355,6 +355,16 @@ __global__ void axpby2d_kernel(int m, int n, double2 alpha, const C* X, long ldx
     }
 }
 
+// out (n x m, column-major, ld ldo) = A^T for the m x n column-major A (ld lda)
+template<typename C>
+__global__ void transpose_kernel(const C* A, long lda, int m, int n, C* out, long ldo) {
+    const size_t tot = (size_t)m * n;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e % m), c = (int)(e / m);
+        out[(size_t)r * ldo + c] = A[(size_t)c * lda + r];
+    }
+}
+
 dim3 grid1(size_t n) {
     size_t g = (n + 255) / 256;
     if (g > 65536) g = 65536;
@@ -455,6 +465,12 @@ hipError_t dense_axpby2d(int prec, int m, int n, double2 alpha, const void* X, l
     else
         hipLaunchKernelGGL(axpby2d_kernel<float2>, grid1((size_t)m * n), dim3(256), 0, s, m, n, alpha,
                            (const float2*)X, ldx, beta, (const float2*)Y, ldy, (float2*)out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t dense_transpose(const double2* A, long lda, int m, int n, double2* out, long ldo, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(transpose_kernel<double2>, grid1((size_t)m * n), dim3(256), 0, s, A, lda, m, n, out, ldo);
     return hipGetLastError();
 }
 

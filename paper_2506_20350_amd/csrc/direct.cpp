@@ -88,10 +88,10 @@ mlfft_status Ctx::row_precond_setup(Array& a) {
 // done pairwise in place with one copy.  Every inverse is formed explicitly (LU with
 // partial pivoting) and its 1-norm condition checked: a leading block section with
 // rcond < 1e-14 stops the recursion (MLFFT_E_SINGULAR).
-static mlfft_status rybicki(Ctx* c, Array& a, int W, const double2* V, double2* I, double* min_rcond, double* flops) {
+static mlfft_status rybicki(Ctx* c, Array& a, int W, const double2* V, long ldv, double2* I, long ldi,
+                            double* min_rcond, double* flops) {
     hipStream_t s = c->stream;
     const int Ny = a.Ny, n = a.Nx * a.b;
-    const long N = (long)Ny * n;
     const size_t nn = (size_t)n * n;
     double fl = 0.0, rmin = 1.0;
     auto gemm = [&](int M, int Nc, int K, double2 al, const double2* A, long lda, const double2* B, long ldb, double2 be,
@@ -135,7 +135,7 @@ static mlfft_status rybicki(Ctx* c, Array& a, int W, const double2* V, double2* 
     };
     // order 1: x_1 = R_0^{-1} y_1, G_1 = R_0^{-1} R_{-1}, H_1 = R_0^{-1} R_1
     STCHK(inv(R(0), Dinv, "R_0", 0));
-    STCHK(gemm(n, W, n, kOne, Dinv, n, yb(0), N, kZero, xb(0), N));
+    STCHK(gemm(n, W, n, kOne, Dinv, n, yb(0), ldv, kZero, xb(0), ldi));
     if (Ny > 1) {
         STCHK(gemm(n, n, n, kOne, Dinv, n, R(-1), n, kZero, G(1), n));
         STCHK(gemm(n, n, n, kOne, Dinv, n, R(1), n, kZero, H(1), n));
@@ -145,11 +145,12 @@ static mlfft_status rybicki(Ctx* c, Array& a, int W, const double2* V, double2* 
         HIPCHK(dense_axpby2d(0, n, n, kMinus, R(0), n, kZero, nullptr, 0, S, n, s), "copy");
         for (int j = 1; j <= M; ++j) STCHK(gemm(n, n, n, kOne, R(M + 1 - j), n, G(M + 1 - j), n, kOne, S, n));
         STCHK(inv(S, Dinv, "D", M));
-        HIPCHK(dense_axpby2d(0, n, W, kMinus, yb(M), N, kZero, nullptr, 0, Rt.p, n, s), "copy");
-        for (int j = 1; j <= M; ++j) STCHK(gemm(n, W, n, kOne, R(M + 1 - j), n, xb(j - 1), N, kOne, (double2*)Rt.p, n));
-        STCHK(gemm(n, W, n, kOne, Dinv, n, (double2*)Rt.p, n, kZero, xb(M), N));
+        HIPCHK(dense_axpby2d(0, n, W, kMinus, yb(M), ldv, kZero, nullptr, 0, Rt.p, n, s), "copy");
+        for (int j = 1; j <= M; ++j)
+            STCHK(gemm(n, W, n, kOne, R(M + 1 - j), n, xb(j - 1), ldi, kOne, (double2*)Rt.p, n));
+        STCHK(gemm(n, W, n, kOne, Dinv, n, (double2*)Rt.p, n, kZero, xb(M), ldi));
         // eq. xi
-        for (int j = 1; j <= M; ++j) STCHK(gemm(n, W, n, kMinus, G(M + 1 - j), n, xb(M), N, kOne, xb(j - 1), N));
+        for (int j = 1; j <= M; ++j) STCHK(gemm(n, W, n, kMinus, G(M + 1 - j), n, xb(M), ldi, kOne, xb(j - 1), ldi));
         if (M + 1 == Ny) break;
         // eq. GM1
         HIPCHK(dense_axpby2d(0, n, n, kMinus, R(0), n, kZero, nullptr, 0, S, n, s), "copy");
@@ -175,6 +176,111 @@ static mlfft_status rybicki(Ctx* c, Array& a, int W, const double2* V, double2* 
     return MLFFT_OK;
 }
 
+// Z I = V with the border moved to the right-hand side (Sec. III-E): Z_A [U F] = [V_A Z_B^T]
+// by the block Rybicki recursion (W + Nc right-hand sides), then the Schur complement
+// S = Z_C - Z_B F, I_C = S^{-1}(V_C - Z_B U) and I_A = U - F I_C.
+static mlfft_status schur_direct(Ctx* c, Array& a, int W, const double2* V, double2* I, double* min_rcond,
+                                 double* flops) {
+    hipStream_t s = c->stream;
+    const long N = (long)a.NA(), Nt = (long)a.Nt();
+    const int Nc = a.Nc;
+    const int Wr = W + Nc;
+    Buf Rb(&c->alloc), Xb(&c->alloc), Sb(&c->alloc), Si(&c->alloc), Rc(&c->alloc), dws(&c->alloc), iws(&c->alloc);
+    HIPCHK(Rb.ensure((size_t)N * Wr * sizeof(double2)), "border right-hand sides");
+    HIPCHK(Xb.ensure((size_t)N * Wr * sizeof(double2)), "border right-hand sides");
+    HIPCHK(Sb.ensure((size_t)Nc * Nc * sizeof(double2)), "Schur complement");
+    HIPCHK(Si.ensure((size_t)Nc * Nc * sizeof(double2)), "Schur complement");
+    HIPCHK(Rc.ensure((size_t)Nc * W * sizeof(double2)), "Schur complement");
+    HIPCHK(dws.ensure((Nc + 2) * sizeof(double)), "Schur complement");
+    HIPCHK(iws.ensure((Nc + 1) * sizeof(int)), "Schur complement");
+    double2* R = (double2*)Rb.p;
+    double2* X = (double2*)Xb.p;
+    HIPCHK(dense_axpby2d(0, (int)N, W, kOne, V, Nt, kZero, nullptr, 0, R, N, s), "gather V_A");
+    HIPCHK(hipMemcpyAsync(R + (size_t)N * W, a.Bt64.p, (size_t)N * Nc * sizeof(double2), hipMemcpyDeviceToDevice, s),
+           "gather Z_B^T");
+    double rc = 1.0, fl = 0.0;
+    STCHK(rybicki(c, a, Wr, R, N, X, N, &rc, &fl));
+    const double2* U = X;
+    const double2* F = X + (size_t)N * W;
+    double2* S = (double2*)Sb.p;
+    HIPCHK(hipMemcpyAsync(S, a.C64.p, (size_t)Nc * Nc * sizeof(double2), hipMemcpyDeviceToDevice, s), "Schur");
+    HIPCHK(dense_gemm(0, Nc, Nc, (int)N, kMinus, a.B64.p, Nc, 0, F, N, 0, kOne, S, Nc, 0, 1, s), "Schur");
+    HIPCHK(dense_axpby2d(0, Nc, W, kOne, V + N, Nt, kZero, nullptr, 0, Rc.p, Nc, s), "gather V_C");
+    HIPCHK(dense_gemm(0, Nc, W, (int)N, kMinus, a.B64.p, Nc, 0, U, N, 0, kOne, Rc.p, Nc, 0, 1, s), "Schur");
+    double src = 0.0;
+    int info = 0;
+    STCHK(invert(c, S, (double2*)Si.p, Nc, (double*)dws.p, (int*)iws.p, &src, &info));
+    if (info != 0 || !(src >= 1e-14))
+        return c->fail(MLFFT_E_SINGULAR, "Schur complement Z_C - Z_B Z_A^{-1} Z_B^T is singular (rcond %.3e)", src);
+    HIPCHK(dense_gemm(0, Nc, W, Nc, kOne, Si.p, Nc, 0, Rc.p, Nc, 0, kZero, I + N, Nt, 0, 1, s), "I_C");
+    HIPCHK(dense_axpby2d(0, (int)N, W, kOne, U, N, kZero, nullptr, 0, I, Nt, s), "I_A");
+    HIPCHK(dense_gemm(0, (int)N, W, Nc, kMinus, F, N, 0, I + N, Nt, 0, kOne, I, Nt, 0, 1, s), "I_A");
+    HIPCHK(hipStreamSynchronize(s), "direct solve");
+    fl += 8.0 * ((double)Nc * Nc * N + (double)Nc * W * N + (double)Nc * W * Nc + (double)N * W * Nc) +
+          8.0 * (double)Nc * Nc * Nc * (1.0 / 3.0 + 1.0);
+    if (min_rcond) *min_rcond = std::min(rc, src);
+    if (flops) *flops = fl;
+    return MLFFT_OK;
+}
+
+mlfft_status Ctx::border_matvec(const std::vector<MatvecItem>& items, int prec) {
+    Ctx* c = this;
+    const int p = prec == P64 ? 0 : 1;
+    const int eb = prec_elem_bytes(prec);
+    for (const MatvecItem& it : items) {
+        const Array* a = it.arr;
+        if (a->Nc == 0) continue;
+        const long N = (long)a->NA(), ld = (long)a->Nt();
+        const int Nc = a->Nc, W = it.W;
+        const char* xa = (const char*)it.x;
+        const char* xc = xa + N * eb;
+        char* ya = (char*)it.y;
+        char* yc = ya + N * eb;
+        const double2 al = make_double2(it.alpha, 0.0);
+        const int pr = prof_begin(PK_BORDER, prec, (double)eb * W * (2.0 * Nc + 3.0 * N) +
+                                  (p ? 8.0 : 16.0) * ((double)2 * N * Nc + (double)Nc * Nc),
+                                  8.0 * W * ((double)2 * N * Nc + (double)Nc * Nc));
+        // y_A += alpha Z_B^T x_C
+        HIPCHK(dense_gemm(p, (int)N, W, Nc, al, p ? a->Bt32.p : a->Bt64.p, N, 0, xc, ld, 0, kOne, ya, ld, 0, 1, stream),
+               "border product");
+        // y_C = alpha (Z_B x_A + Z_C x_C) + beta v_C
+        double2 be = kZero;
+        if (it.addend) {
+            HIPCHK(dense_axpby2d(p, Nc, W, make_double2(it.beta, 0.0), (const char*)it.addend + N * eb, ld, kZero,
+                                 nullptr, 0, yc, ld, stream), "border addend");
+            be = kOne;
+        }
+        HIPCHK(dense_gemm(p, Nc, W, (int)N, al, p ? a->B32.p : a->B64.p, Nc, 0, xa, ld, 0, be, yc, ld, 0, 1, stream),
+               "border product");
+        HIPCHK(dense_gemm(p, Nc, W, Nc, al, p ? a->C32.p : a->C64.p, Nc, 0, xc, ld, 0, kOne, yc, ld, 0, 1, stream),
+               "border product");
+        prof_end(pr);
+    }
+    return MLFFT_OK;
+}
+
+mlfft_status Ctx::border_precond(const std::vector<MatvecItem>& items, int prec) {
+    Ctx* c = this;
+    const int p = prec == P64 ? 0 : 1;
+    const int eb = prec_elem_bytes(prec);
+    for (const MatvecItem& it : items) {
+        const Array* a = it.arr;
+        if (a->Nc == 0) continue;
+        const long N = (long)a->NA(), ld = (long)a->Nt();
+        const int Nc = a->Nc, W = it.W;
+        char* zc = (char*)it.y + N * eb;
+        double2 be = kZero;
+        if (it.addend) {
+            HIPCHK(dense_axpby2d(p, Nc, W, make_double2(it.beta, 0.0), (const char*)it.addend + N * eb, ld, kZero,
+                                 nullptr, 0, zc, ld, stream), "border addend");
+            be = kOne;
+        }
+        HIPCHK(dense_gemm(p, Nc, W, Nc, make_double2(it.alpha, 0.0), p ? a->Ci32.p : a->Ci64.p, Nc, 0,
+                          (const char*)it.x + N * eb, ld, 0, be, zc, ld, 0, 1, stream), "border preconditioner");
+    }
+    return MLFFT_OK;
+}
+
 extern "C" {
 
 mlfft_status mlfft_direct_solve(mlfft_ctx ctx, int array_id, int W, const void* V, void* I, double* min_rcond,
@@ -190,7 +296,87 @@ mlfft_status mlfft_direct_solve(mlfft_ctx ctx, int array_id, int W, const void* 
     if ((const char*)V < (const char*)I + vb && (const char*)I < (const char*)V + vb)
         return c->fail(MLFFT_E_ARG, "V and I overlap");
     HIPCHK(hipSetDevice(c->device), "set device");
-    return rybicki(c, *a, W, (const double2*)V, (double2*)I, min_rcond, flops);
+    if (a->Nc > 0) return schur_direct(c, *a, W, (const double2*)V, (double2*)I, min_rcond, flops);
+    const long N = (long)a->NA();
+    return rybicki(c, *a, W, (const double2*)V, N, (double2*)I, N, min_rcond, flops);
+}
+
+mlfft_status mlfft_set_border(mlfft_ctx ctx, int array_id, int Nc, const void* ZB, const void* ZC, int on_device) {
+    if (!ctx) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    Array* a = c->find(array_id);
+    if (!a) return c->fail(MLFFT_E_STATE, "unknown array id %d", array_id);
+    if (Nc < 0 || Nc > 65536) return c->fail(MLFFT_E_ARG, "Nc must be in [0, 65536]");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    HIPCHK(hipStreamSynchronize(c->stream), "set border");
+    for (Buf* x : {&a->B64, &a->B32, &a->Bt64, &a->Bt32, &a->C64, &a->C32, &a->Ci64, &a->Ci32, &a->Kc64, &a->Kc32})
+        x->release();
+    a->Nc = 0;
+    if (Nc == 0) return MLFFT_OK;
+    if (!ZB || !ZC) return c->fail(MLFFT_E_ARG, "ZB or ZC is NULL");
+    const long N = (long)a->NA();
+    const size_t nb = (size_t)N * Nc, nc = (size_t)Nc * Nc, bb = (size_t)a->b * a->b;
+    if (!on_device) {
+        const double* h = (const double*)ZB;
+        for (size_t i = 0; i < 2 * nb; ++i)
+            if (!std::isfinite(h[i])) return c->fail(MLFFT_E_ARG, "ZB contains a non-finite value");
+        h = (const double*)ZC;
+        for (size_t i = 0; i < 2 * nc; ++i)
+            if (!std::isfinite(h[i])) return c->fail(MLFFT_E_ARG, "ZC contains a non-finite value");
+    }
+    hipStream_t s = c->stream;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    Buf Ct(&c->alloc), dws(&c->alloc), iws(&c->alloc);
+    HIPCHK(a->Bt64.ensure(nb * sizeof(double2)), "border");
+    HIPCHK(a->B64.ensure(nb * sizeof(double2)), "border");
+    HIPCHK(a->C64.ensure(nc * sizeof(double2)), "border");
+    HIPCHK(a->Ci64.ensure(nc * sizeof(double2)), "border");
+    HIPCHK(a->Kc64.ensure(bb * sizeof(double2)), "border");
+    for (Buf* x : {&a->Bt32, &a->B32}) HIPCHK(x->ensure(nb * sizeof(float2)), "border");
+    for (Buf* x : {&a->C32, &a->Ci32}) HIPCHK(x->ensure(nc * sizeof(float2)), "border");
+    HIPCHK(a->Kc32.ensure(bb * sizeof(float2)), "border");
+    HIPCHK(Ct.ensure(nc * sizeof(double2)), "border");
+    HIPCHK(dws.ensure((Nc + 2) * sizeof(double)), "border");
+    HIPCHK(iws.ensure((Nc + 1) * sizeof(int)), "border");
+    // row-major Z_B (Nc x N) is the column-major N x Nc matrix Z_B^T; row-major Z_C is Z_C^T column-major
+    HIPCHK(hipMemcpyAsync(a->Bt64.p, ZB, nb * sizeof(double2), kind, s), "border upload");
+    HIPCHK(hipMemcpyAsync(Ct.p, ZC, nc * sizeof(double2), kind, s), "border upload");
+    HIPCHK(dense_transpose((const double2*)a->Bt64.p, N, (int)N, Nc, (double2*)a->B64.p, Nc, s), "border");
+    HIPCHK(dense_transpose((const double2*)Ct.p, Nc, Nc, Nc, (double2*)a->C64.p, Nc, s), "border");
+    HIPCHK(dense_transpose((const double2*)a->K64.p, a->b, a->b, a->b, (double2*)a->Kc64.p, a->b, s), "border");
+    if (on_device) {
+        Buf flag(&c->alloc);
+        HIPCHK(flag.ensure(sizeof(int)), "flag");
+        HIPCHK(hipMemsetAsync(flag.p, 0, sizeof(int), s), "flag");
+        HIPCHK(launch_nonfinite((const double*)a->Bt64.p, 2 * nb, (int*)flag.p, s), "finite check");
+        HIPCHK(launch_nonfinite((const double*)a->C64.p, 2 * nc, (int*)flag.p, s), "finite check");
+        int hflag = 0;
+        HIPCHK(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, s), "flag");
+        HIPCHK(hipStreamSynchronize(s), "finite check");
+        if (hflag) {
+            for (Buf* x : {&a->B64, &a->B32, &a->Bt64, &a->Bt32, &a->C64, &a->C32, &a->Ci64, &a->Ci32, &a->Kc64, &a->Kc32})
+                x->release();
+            return c->fail(MLFFT_E_ARG, "ZB or ZC contains a non-finite value");
+        }
+    }
+    // Z_C^{-1} for the border part of P_X (Sec. III-B: the LU of Z_C)
+    HIPCHK(hipMemcpyAsync(Ct.p, a->C64.p, nc * sizeof(double2), hipMemcpyDeviceToDevice, s), "border");
+    double rc = 0.0;
+    int info = 0;
+    STCHK(invert(c, (double2*)Ct.p, (double2*)a->Ci64.p, Nc, (double*)dws.p, (int*)iws.p, &rc, &info));
+    if (info != 0 || !(rc >= 1e-14)) {
+        for (Buf* x : {&a->B64, &a->B32, &a->Bt64, &a->Bt32, &a->C64, &a->C32, &a->Ci64, &a->Ci32, &a->Kc64, &a->Kc32})
+            x->release();
+        return c->fail(MLFFT_E_SINGULAR, "border self block Z_C is singular (rcond %.3e)", rc);
+    }
+    HIPCHK(launch_cast_c64_to_c32((const double2*)a->Bt64.p, (float2*)a->Bt32.p, nb, s), "cast");
+    HIPCHK(launch_cast_c64_to_c32((const double2*)a->B64.p, (float2*)a->B32.p, nb, s), "cast");
+    HIPCHK(launch_cast_c64_to_c32((const double2*)a->C64.p, (float2*)a->C32.p, nc, s), "cast");
+    HIPCHK(launch_cast_c64_to_c32((const double2*)a->Ci64.p, (float2*)a->Ci32.p, nc, s), "cast");
+    HIPCHK(launch_cast_c64_to_c32((const double2*)a->Kc64.p, (float2*)a->Kc32.p, bb, s), "cast");
+    HIPCHK(hipStreamSynchronize(s), "set border");
+    a->Nc = Nc;
+    return MLFFT_OK;
 }
 
 mlfft_status mlfft_dense_gemm(mlfft_ctx ctx, int prec, int M, int N, int K, double alpha_re, double alpha_im,

@@ -105,7 +105,7 @@ struct FwdY {
         const int ix = tid / cm, mi = tid - ix * cm;
         if (mi >= wk.mlen) return;
         const C* __restrict__ src = static_cast<const C*>(t->in)
-            + ((size_t)wk.w * NY * Nx + ix) * b + wk.m0 + mi;
+            + (size_t)wk.w * ((size_t)NY * Nx * b + t->colpad) + (size_t)ix * b + wk.m0 + mi;
         const size_t ys = (size_t)Nx * b;
         C* col = tile + ix * cm + mi;
         const int rs = t->rs;
@@ -246,7 +246,7 @@ struct InvY {
 #pragma unroll
             for (int iy = 0; iy < NY; ++iy) v[iy] = cadd(v[iy], col[2 * iy * rs]);
         }
-        const size_t off = ((size_t)wk.w * NY * Nx + ix) * b + wk.m0 + mi;
+        const size_t off = (size_t)wk.w * ((size_t)NY * Nx * b + t->colpad) + (size_t)ix * b + wk.m0 + mi;
         const size_t ys = (size_t)Nx * b;
         C* __restrict__ dst = static_cast<C*>(t->out) + off;
         const R alpha = (R)t->alpha;
@@ -345,7 +345,7 @@ struct InvYHalf {
         Fft<C, NY, 1>::tw2(v);
 #pragma unroll
         for (int iy = 0; iy < NY; ++iy) v[iy] = cadd(v[iy], e[iy]);
-        const size_t off = ((size_t)wk.w * NY * Nx + ix) * b + wk.m0 + mi;
+        const size_t off = (size_t)wk.w * ((size_t)NY * Nx * b + t->colpad) + (size_t)ix * b + wk.m0 + mi;
         const size_t ys = (size_t)Nx * b;
         C* __restrict__ dst = static_cast<C*>(t->out) + off;
         const R alpha = (R)t->alpha;

@@ -27,7 +27,9 @@ struct FftTask {
     int nmc;                // number of m chunks
     int block_begin;        // first workgroup of this task in the grouped grid
     int pad;
-    int reserved = 0;       // fills the tail: a task's bytes are all defined (tables are cached by content)
+    int colpad = 0;         // elements after each spatial column of in (forward) / out and addend (inverse):
+                            // spatial columns start every Ny Nx b + colpad elements (the border unknowns of
+                            // the full system follow the array's in every column); 0: back to back
 };
 
 // One array's share of a grouped per-frequency block product
@@ -40,7 +42,7 @@ struct GemmTask {
     int K, b, W;
     int mgroups;            // workgroups per frequency (row groups)
     int block_begin;
-    int reserved = 0;       // fills the tail, as in FftTask
+    int reserved = 0;       // fills the tail: a task's bytes are all defined (tables are cached by content)
 };
 
 // no padding bytes: the members add up to the size

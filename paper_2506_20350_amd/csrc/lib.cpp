@@ -99,7 +99,11 @@ Array* Ctx::find(int id) {
 }
 
 size_t Array::bytes() const {
-    return G64.n + G32.n + G16.n + S64.n + S32.n + S16.n + K64.n + K32.n + K16.n + R64.n + Z64.n + Z32.n;
+    size_t t = 0;
+    for (const Buf* x : {&G64, &G32, &G16, &S64, &S32, &S16, &K64, &K32, &K16, &R64, &Z64, &Z32, &B64, &B32, &Bt64,
+                         &Bt32, &C64, &C32, &Ci64, &Ci32, &Kc64, &Kc32})
+        t += x->n;
+    return t;
 }
 
 void Array::release() {
@@ -107,7 +111,9 @@ void Array::release() {
     S64.release(); S32.release(); S16.release();
     K64.release(); K32.release(); K16.release();
     R64.release(); Z64.release(); Z32.release();
+    for (Buf* x : {&B64, &B32, &Bt64, &Bt32, &C64, &C32, &Ci64, &Ci32, &Kc64, &Kc32}) x->release();
     row_rcond = 0.0;
+    Nc = 0;
 }
 
 #define HIPCHK(call, what)                                   \
@@ -253,7 +259,7 @@ mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec, v
         const Array* a = it.arr;
         FftTask t{};
         t.in = it.x; t.out = sa + off[i]; t.addend = nullptr; t.alpha = 1.0; t.beta = 0.0;
-        t.Nx = a->Nx; t.Ny = a->Ny; t.b = a->b; t.W = it.W; t.pad = 1;
+        t.Nx = a->Nx; t.Ny = a->Ny; t.b = a->b; t.W = it.W; t.pad = 1; t.colpad = a->Nc;
         fw[i] = t;
         GemmTask g{};
         g.G = prec == P64 ? a->G64.p : prec == P32 ? a->G32.p : a->G16.p;
@@ -263,7 +269,7 @@ mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec, v
         FftTask u{};
         u.in = sb + off[i]; u.out = it.y; u.addend = it.addend;
         u.alpha = it.alpha / (double)a->K; u.beta = it.beta;
-        u.Nx = a->Nx; u.Ny = a->Ny; u.b = a->b; u.W = it.W; u.pad = 1;
+        u.Nx = a->Nx; u.Ny = a->Ny; u.b = a->b; u.W = it.W; u.pad = 1; u.colpad = a->Nc;
         iv[i] = u;
     }
     // algorithmic bytes / flops of the three launches (s: bytes per complex of the data, sg: of the spectra)
@@ -286,7 +292,7 @@ mlfft_status Ctx::matvec_group(const std::vector<MatvecItem>& items, int prec, v
     pr = prof_begin(PK_FFT_INV, prec, bi, 0);
     STCHK(fft_grouped(prec, iv, true, "inverse MLFFT launch"));
     prof_end(pr);
-    return MLFFT_OK;
+    return border_matvec(items, prec);
 }
 
 // z = alpha * P^{-1} r (+ beta * addend) with the block-circulant or self-block preconditioner
@@ -298,6 +304,7 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
     if (kind == 4) {
         // row preconditioner P'_Z: every row of cells of every column is one vector of
         // length Nx b, so the apply is one dense product (T^[1]_0)^{-1} [n x (Ny W)]
+        // (batched over the columns when border unknowns sit between them)
         for (const MatvecItem& it : items) {
             Array* a = const_cast<Array*>(it.arr);
             if (it.addend || it.alpha != 1.0) return fail(MLFFT_E_ARG, "row preconditioner apply has no epilogue");
@@ -307,25 +314,41 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
             const double bytes = (double)eb * 2 * n * a->Ny * it.W + (p ? 8.0 : 16.0) * n * n;
             const double flops = 8.0 * n * (double)n * a->Ny * it.W;
             const int pr = prof_begin(PK_PC_GEMM, prec, bytes, flops);
-            HIPCHK(dense_gemm(p, n, a->Ny * it.W, n, make_double2(1.0, 0.0), p ? a->Z32.p : a->Z64.p, n, 0, it.x, n, 0,
-                              make_double2(0.0, 0.0), it.y, n, 0, 1, stream), "row preconditioner apply");
+            const void* Zi = p ? a->Z32.p : a->Z64.p;
+            if (a->Nc == 0)
+                HIPCHK(dense_gemm(p, n, a->Ny * it.W, n, make_double2(1.0, 0.0), Zi, n, 0, it.x, n, 0,
+                                  make_double2(0.0, 0.0), it.y, n, 0, 1, stream), "row preconditioner apply");
+            else
+                HIPCHK(dense_gemm(p, n, a->Ny, n, make_double2(1.0, 0.0), Zi, n, 0, it.x, n, (long)a->Nt(),
+                                  make_double2(0.0, 0.0), it.y, n, (long)a->Nt(), it.W, stream),
+                       "row preconditioner apply");
             prof_end(pr);
         }
-        return MLFFT_OK;
+        return border_precond(items, prec);
     }
     if (kind == 2) {
-        // self block: one b x b product per cell, the whole vector as one frequency
-        std::vector<GemmTask> gm(nt);
-        for (int i = 0; i < nt; ++i) {
-            const MatvecItem& it = items[i];
+        // self block: one b x b product per cell.  Arrays without a border run the block
+        // product with the whole vector as one frequency; with border unknowns between the
+        // columns it is a dense product R_{0,0}^{-1} [b x (Nx Ny)] batched over the columns.
+        std::vector<GemmTask> gm;
+        for (const MatvecItem& it : items) {
             const Array* a = it.arr;
             if (it.addend || it.alpha != 1.0) return fail(MLFFT_E_ARG, "self-block apply has no epilogue");
+            if (a->Nc > 0) {
+                const int p = prec == P64 ? 0 : 1;
+                const long ld = (long)a->Nt();
+                HIPCHK(dense_gemm(p, a->b, a->Nx * a->Ny, a->b, make_double2(1.0, 0.0), p ? a->Kc32.p : a->Kc64.p, a->b,
+                                  0, it.x, a->b, ld, make_double2(0.0, 0.0), it.y, a->b, ld, it.W, stream),
+                       "self-block apply");
+                continue;
+            }
             GemmTask g{};
             g.G = prec == P64 ? a->K64.p : prec == P32 ? a->K32.p : a->K16.p;
             g.X = it.x; g.Y = it.y; g.K = it.W; g.b = a->b; g.W = a->Nx * a->Ny; g.gstride = 0;
-            gm[i] = g;
+            gm.push_back(g);
         }
-        return gemm_grouped(prec, gm, 1, "self-block apply launch");
+        if (!gm.empty()) STCHK(gemm_grouped(prec, gm, 1, "self-block apply launch"));
+        return border_precond(items, prec);
     }
     size_t need = 0;
     std::vector<size_t> off(nt);
@@ -344,7 +367,7 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
         const Array* a = it.arr;
         FftTask t{};
         t.in = it.x; t.out = (char*)spec_a.p + off[i]; t.alpha = 1.0;
-        t.Nx = a->Nx; t.Ny = a->Ny; t.b = a->b; t.W = it.W; t.pad = 0;
+        t.Nx = a->Nx; t.Ny = a->Ny; t.b = a->b; t.W = it.W; t.pad = 0; t.colpad = a->Nc;
         fw[i] = t;
         GemmTask g{};
         g.G = prec == P64 ? a->S64.p : prec == P32 ? a->S32.p : a->S16.p;
@@ -354,7 +377,7 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
         FftTask u{};
         u.in = (char*)spec_b.p + off[i]; u.out = it.y; u.addend = it.addend;
         u.alpha = it.alpha / (double)(a->Nx * a->Ny); u.beta = it.beta;
-        u.Nx = a->Nx; u.Ny = a->Ny; u.b = a->b; u.W = it.W; u.pad = 0;
+        u.Nx = a->Nx; u.Ny = a->Ny; u.b = a->b; u.W = it.W; u.pad = 0; u.colpad = a->Nc;
         iv[i] = u;
     }
     double bf = 0, bg = 0, fl = 0;
@@ -375,7 +398,7 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
     pr = prof_begin(PK_PC_FFT_INV, prec, bf, 0);
     STCHK(fft_grouped(prec, iv, true, "preconditioner IFFT launch"));
     prof_end(pr);
-    return MLFFT_OK;
+    return border_precond(items, prec);
 }
 
 // ------------------------------------------------------------------ setup
@@ -584,12 +607,13 @@ mlfft_status mlfft_array_info(mlfft_ctx ctx, int array_id, mlfft_array_info_t* o
     out->pc_fallbacks = a->pc_fallbacks;
     out->pc_min_rcond = a->pc_min_rcond;
     out->device_bytes = a->bytes();
+    out->Nc = a->Nc;
     return MLFFT_OK;
 }
 
 static const char* kProfNames[PK_COUNT] = {"mlfft_fwd_fft", "block_gemm", "mlfft_inv_fft", "precond_fwd_fft",
                                            "precond_gemm", "precond_inv_fft", "arnoldi", "net_forward",
-                                           "net_backward"};
+                                           "net_backward", "border_gemm"};
 
 mlfft_status mlfft_profile_enable(mlfft_ctx ctx, int enable) {
     if (!ctx) return MLFFT_E_ARG;
@@ -638,7 +662,7 @@ mlfft_status mlfft_matvec(mlfft_ctx ctx, int array_id, int W, const void* x, voi
     if (prec < MLFFT_FP64 || prec > MLFFT_FP32_BF16GEMM) return c->fail(MLFFT_E_ARG, "invalid precision");
     if (W == 0) return MLFFT_OK;
     if (!x || !y) return c->fail(MLFFT_E_ARG, "x or y is NULL");
-    const size_t vb = (size_t)a->Nx * a->Ny * a->b * W * prec_elem_bytes(prec);
+    const size_t vb = a->Nt() * W * prec_elem_bytes(prec);
     if ((const char*)x < (const char*)y + vb && (const char*)y < (const char*)x + vb)
         return c->fail(MLFFT_E_ARG, "x and y overlap");
     HIPCHK(hipSetDevice(c->device), "set device");
@@ -662,7 +686,7 @@ mlfft_status mlfft_matvec_axpby(mlfft_ctx ctx, int array_id, int W, double alpha
     if (!std::isfinite(alpha) || !std::isfinite(beta)) return c->fail(MLFFT_E_ARG, "alpha and beta must be finite");
     if (W == 0) return MLFFT_OK;
     if (!x || !y) return c->fail(MLFFT_E_ARG, "x or y is NULL");
-    const size_t vb = (size_t)a->Nx * a->Ny * a->b * W * prec_elem_bytes(prec);
+    const size_t vb = a->Nt() * W * prec_elem_bytes(prec);
     if (overlap(x, vb, y, vb)) return c->fail(MLFFT_E_ARG, "x and y overlap");
     if (v && overlap(v, vb, y, vb)) return c->fail(MLFFT_E_ARG, "v and y overlap");
     HIPCHK(hipSetDevice(c->device), "set device");
@@ -701,7 +725,7 @@ mlfft_status mlfft_precond_apply(mlfft_ctx ctx, int array_id, int kind, int W, c
     if (prec < MLFFT_FP64 || prec > MLFFT_FP32_BF16GEMM) return c->fail(MLFFT_E_ARG, "invalid precision");
     if (W == 0) return MLFFT_OK;
     if (!r || !z) return c->fail(MLFFT_E_ARG, "r or z is NULL");
-    const size_t vb = (size_t)a->Nx * a->Ny * a->b * W * prec_elem_bytes(prec);
+    const size_t vb = a->Nt() * W * prec_elem_bytes(prec);
     if ((const char*)r < (const char*)z + vb && (const char*)z < (const char*)r + vb)
         return c->fail(MLFFT_E_ARG, "r and z overlap");
     HIPCHK(hipSetDevice(c->device), "set device");

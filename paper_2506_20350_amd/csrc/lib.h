@@ -51,12 +51,20 @@ struct Array {
     Buf R64;                // the unique blocks R_{p,q} as given, [p+Ny-1][q+Nx-1][m][n] (direct solver, P'_Z)
     Buf Z64, Z32;           // row preconditioner P'_Z: (T^[1]_0)^{-1}, (Nx b) x (Nx b) column-major (built on first use)
     double row_rcond = 0.0; // 1-norm reciprocal condition number of T^[1]_0 (0 until built)
+    // border of the full matrix Z = [[Z_A, Z_B^T], [Z_B, Z_C]] (eq. Zblock), all column-major:
+    // B (Nc x N) = Z_B, Bt (N x Nc) = Z_B^T, C (Nc x Nc) = Z_C, Ci = Z_C^{-1}, Kc = R_{0,0}^{-1}
+    int Nc = 0;
+    Buf B64, B32, Bt64, Bt32, C64, C32, Ci64, Ci32, Kc64, Kc32;
+    size_t NA() const { return (size_t)Nx * Ny * b; }
+    size_t Nt() const { return NA() + (size_t)Nc; }      // unknowns per column of the full system
     int pc_fallbacks = 0;
     double pc_min_rcond = 1.0;
     size_t bytes() const;
     void release();
     void bind(const Alloc* a) {
-        for (Buf* b : {&G64, &G32, &G16, &S64, &S32, &S16, &K64, &K32, &K16, &R64, &Z64, &Z32}) b->bind(a);
+        for (Buf* b : {&G64, &G32, &G16, &S64, &S32, &S16, &K64, &K32, &K16, &R64, &Z64, &Z32, &B64, &B32, &Bt64,
+                       &Bt32, &C64, &C32, &Ci64, &Ci32, &Kc64, &Kc32})
+            b->bind(a);
     }
 };
 
@@ -83,7 +91,7 @@ struct ProfRec {
     double bytes, flops;
 };
 enum ProfKind { PK_FFT_FWD = 0, PK_GEMM, PK_FFT_INV, PK_PC_FFT_FWD, PK_PC_GEMM, PK_PC_FFT_INV, PK_ARNOLDI,
-                PK_NET_FWD, PK_NET_BWD, PK_COUNT };
+                PK_NET_FWD, PK_NET_BWD, PK_BORDER, PK_COUNT };
 }  // namespace mlfft
 
 struct mlfft_ctx_s {
@@ -147,6 +155,11 @@ struct mlfft_ctx_s {
     mlfft_status precond_group(const std::vector<mlfft::MatvecItem>& items, int kind, int prec);
     // P'_Z of Sec. III-B: (T^[1]_0)^{-1} of array a, built once (dense.cpp)
     mlfft_status row_precond_setup(mlfft::Array& a);
+    // border terms of y = alpha Z x + beta v for the arrays with a border (dense.cpp): runs after the
+    // Z_A part has written alpha Z_A x_A + beta v_A into y_A
+    mlfft_status border_matvec(const std::vector<mlfft::MatvecItem>& items, int prec);
+    // border part of P_X^{-1}: z_C = Z_C^{-1} r_C
+    mlfft_status border_precond(const std::vector<mlfft::MatvecItem>& items, int prec);
     void release_workspaces() {
         graphs_release();
         spec_a.release(); spec_b.release(); solve_ws.release(); solve_ws2.release();

@@ -276,6 +276,7 @@ mlfft_status mlfft_net_apply(mlfft_ctx ctx, int array_id, int W, const void* y, 
     Array* a = c->find(array_id);
     if (!a) return c->fail(MLFFT_E_STATE, "unknown array id %d", array_id);
     if (W < 1 || !y || !z) return c->fail(MLFFT_E_ARG, "bad apply arguments");
+    if (a->Nc > 0) return c->fail(MLFFT_E_ARG, "the learned correction is not defined for arrays with border unknowns");
     return c->net_correct(a, W, y, z, MLFFT_FP32, nullptr);
 }
 

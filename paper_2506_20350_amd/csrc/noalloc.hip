@@ -52,7 +52,7 @@ extern "C" mlfft_status mlfft_matvec_noalloc(mlfft_ctx ctx, int array_id, int W,
     if (prec < MLFFT_FP64 || prec > MLFFT_FP32_BF16GEMM) return c->fail(MLFFT_E_ARG, "invalid precision");
     if (W == 0) return MLFFT_OK;
     if (!x || !y) return c->fail(MLFFT_E_ARG, "x or y is NULL");
-    const size_t vb = (size_t)a->Nx * a->Ny * a->b * W * prec_elem_bytes(prec);
+    const size_t vb = a->Nt() * W * prec_elem_bytes(prec);
     if ((const char*)x < (const char*)y + vb && (const char*)y < (const char*)x + vb)
         return c->fail(MLFFT_E_ARG, "x and y overlap");
     const size_t need = ((size_t)a->K * a->b * W * prec_elem_bytes(prec) + 255) / 256 * 256;

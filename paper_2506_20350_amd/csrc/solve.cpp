@@ -367,7 +367,7 @@ mlfft_status solve_impl(Ctx* c, std::vector<Seg>& segs, const mlfft_solve_opts& 
     size_t S = 0;
     for (size_t i = 0; i < segs.size(); ++i) {
         Seg& sg = segs[i];
-        sg.N = (size_t)sg.arr->Nx * sg.arr->Ny * sg.arr->b;
+        sg.N = sg.arr->Nt();
         sg.off = S;
         for (int q = 0; q < sg.W; ++q) {
             hoff.push_back(S + (size_t)q * sg.N);
@@ -711,6 +711,9 @@ mlfft_status mlfft_solve_batch(mlfft_ctx ctx, int n_arrays, const int* array_ids
         for (int j = 0; j < i; ++j)
             if (array_ids[j] == array_ids[i]) return c->fail(MLFFT_E_ARG, "array id %d appears twice", array_ids[i]);
         if (Ws[i] < 0) return c->fail(MLFFT_E_ARG, "W must be >= 0");
+        if (o.precond == 3 && a->Nc > 0)
+            return c->fail(MLFFT_E_ARG, "the learned correction is not defined for array %d with border unknowns",
+                           array_ids[i]);
         if (Ws[i] == 0) continue;
         if (!V[i] || !I[i]) return c->fail(MLFFT_E_ARG, "V or I is NULL for array %d", array_ids[i]);
         segs.push_back(Seg{a, Ws[i], 0, 0, V[i], I[i]});
