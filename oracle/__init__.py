@@ -25,6 +25,8 @@ paper's definitions directly, with no blocking or fusion:
              blockwise product (eq. ZIVblock), the Schur-complement direct
              solve around the block Rybicki recursion (Sec. III-E) and the
              block-diagonal preconditioner P_X (Sec. III-B).
+  spectrum   singular values of P^{-1} Z by a randomized range finder with a
+             given test matrix (Sec. V; Halko, Martinsson and Tropp).
   net        FP64 3x3 convolution network used as a learned correction of the
              block-circulant preconditioner: forward, backward, loss, Adam and
              bfloat16 round-to-nearest-even emulation.
