@@ -457,19 +457,57 @@ def bench_pcmodes(a, torch):
     ctx.close()
 
 
+def bench_spectrum(a, torch):
+    """Spectrum diagnostics of Sec. V: the l largest singular values of P^{-1} Z for P = I, P'_K,
+    P'_Z and the block circulant (randomized range finder, one power step, every product
+    through the FP64 MLFFT matvec), at the generator's loading 10x and at 1x."""
+    from paper_2506_20350_amd import abi, synth
+    from paper_2506_20350_amd.api import Context
+    Nx, Ny, b = a.spectrum_shape
+    l = a.spectrum_l
+    N = Nx * Ny * b
+    ctx = Context(0)
+    Om = torch.from_numpy(synth.random_vectors(N, l, seed=11)).cuda()
+    rows = []
+    for alpha in (10.0, 1.0):
+        ctx.set_blocks(0, synth.green_blocks(Nx, Ny, b, math.pi, seed=0, alpha=alpha))
+        for name, kind in (("I", 0), ("P'_K", 2), ("P'_Z", 4), ("block circulant", 1)):
+            ctx.sync_stream()
+            abi.mlfft_spectrum(ctx.h, 0, kind, l, Om.data_ptr(), 1)      # warm-up (builds P'_Z once)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sv = abi.mlfft_spectrum(ctx.h, 0, kind, l, Om.data_ptr(), 1)
+            dt = time.perf_counter() - t0
+            rows.append(dict(loading=alpha, P=name, ms=round(dt * 1e3, 2), sigma_first=[round(float(x), 5) for x in sv[:8]],
+                             sigma_at=[round(float(sv[i]), 5) for i in (15, 31, 63, 127, l - 1) if i < l],
+                             above_1_1=int(np.sum(sv > 1.1))))
+            log(f"[bench] spectrum loading {alpha:g}, P = {name}: sigma_1 {sv[0]:.4f}, sigma_{l} {sv[-1]:.4f}, "
+                f"{rows[-1]['above_1_1']} above 1.1 ({dt * 1e3:.1f} ms)")
+    out = dict(metric=f"largest {l} singular values of P^-1 Z ({Nx}x{Ny} array, b={b}, N={N})", value=None,
+               unit="table", n_gpus=1, steps=1, warmup=1, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64", data="synthetic",
+               config=dict(workload=f"{Nx}x{Ny} array, b={b}, kd=pi, randomized range finder l={l}, one power step",
+                           Nx=Nx, Ny=Ny, b=b, l=l),
+               rows=rows)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4", "direct", "pcmodes"] + sorted(SMALL),
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["c4", "direct", "pcmodes", "spectrum"] + sorted(SMALL),
                     default="c5",
                     help="c5: 30x30 b=200; c3: 30x30 b=120; c4: 64 uneven arrays in one batched solve; "
                          "c1, c2: latency of the small cases, eager and with graph-captured Krylov steps; "
                          "direct: the block Rybicki direct solver; pcmodes: P'_K / P'_Z / block circulant, "
-                         "global / split / one port at a time")
+                         "global / split / one port at a time; spectrum: singular values of P^-1 Z")
     ap.add_argument("--direct-shape", type=int, nargs=3, default=[30, 30, 120], metavar=("NX", "NY", "B"))
     ap.add_argument("--pcmodes-shape", type=int, nargs=3, default=[16, 16, 48], metavar=("NX", "NY", "B"))
+    ap.add_argument("--spectrum-shape", type=int, nargs=3, default=[10, 10, 48], metavar=("NX", "NY", "B"))
+    ap.add_argument("--spectrum-l", type=int, default=256)
     ap.add_argument("--form", choices=sorted(FORMS), default="learned")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--pc-prec", choices=["fp32", "bf16"], default="bf16",
@@ -514,6 +552,8 @@ def main():
         return bench_direct(a, torch)
     if a.workload == "pcmodes":
         return bench_pcmodes(a, torch)
+    if a.workload == "spectrum":
+        return bench_spectrum(a, torch)
     if a.workload in SMALL:
         return bench_small(a, torch)
     cfg = WORKLOADS[a.workload]

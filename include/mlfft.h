@@ -332,11 +332,45 @@ mlfft_status mlfft_dense_gemm(mlfft_ctx ctx, int prec, int M, int N, int K, doub
                               const void* A, long lda, const void* B, long ldb, double beta_re, double beta_im, void* C,
                               long ldc);
 
+/* C = alpha A^H B + beta C (complex128, FP64 MFMA) with A stored K x M (lda >= K),
+ * B K x N (ldb >= K), C M x N (ldc >= M), column-major on the device; the Gram
+ * products of mlfft_spectrum.  Asynchronous. */
+mlfft_status mlfft_dense_gemm_ah(mlfft_ctx ctx, int M, int N, int K, double alpha_re, double alpha_im, const void* A,
+                                 long lda, const void* B, long ldb, double beta_re, double beta_im, void* C, long ldc);
+
+/* sigma (host, l values, descending) = square roots of the eigenvalues of the pencil
+ * M v = lambda G v for Hermitian l x l G (positive definite) and M (device complex128,
+ * column-major, both overwritten): Cholesky G = L L^H, T = L^{-1} M L^{-H}, cyclic
+ * Jacobi on T in one workgroup (the last step of mlfft_spectrum).  1 <= l <= 1024.
+ * G not positive definite: MLFFT_E_SINGULAR.  Blocking. */
+mlfft_status mlfft_dense_gen_eig(mlfft_ctx ctx, int l, void* G, void* M, double* sigma);
+
 /* B <- A^{-1} B for the n x n complex128 matrix A (device, column-major, overwritten
  * by its LU factors: blocked right-looking LU with partial pivoting, as LAPACK's
  * zgetrf / zgetrs) and ncols columns of B.  An exactly zero pivot gives
  * MLFFT_E_SINGULAR.  Blocking. */
 mlfft_status mlfft_dense_solve(mlfft_ctx ctx, int n, void* A, long lda, void* B, long ldb, int ncols);
+
+/* ------------------------------------------------------------------ spectrum diagnostics */
+
+/* Approximate largest singular values of the preconditioned operator A = P^{-1} Z
+ * (Sec. V, the spectra of P^{-1} Z for P = I, P_K and P_Z) by the randomized range
+ * finder of Halko, Martinsson and Tropp with every product through the FP64 MLFFT
+ * matvec and preconditioner: Y = A Omega, `power_iters` steps Y = A (A^H Y), then
+ * with Y = Q R and C = A^H Y the matrix B = Q^H A has B B^H = R^{-H} C^H C R^{-1},
+ * whose eigenvalues (Cholesky of Y^H Y and Jacobi on the device) are the squared
+ * singular values returned.  kind: 0 (P = I, the spectrum of Z), 1 block circulant,
+ * 2 P'_K, 4 P'_Z (with a border: P_X).  Omega: device complex128, l test vectors in
+ * the vector layout (the caller draws them; 1 <= l <= 1024, l <= unknowns).
+ * sigma: host, l doubles, descending.  The adjoint is applied as
+ * A^H y = conj(Z P^{-1} conj(y)), which holds for complex-symmetric Z and P, i.e.
+ * reciprocal blocks (R_{-p,-q} = R_{p,q}^T, the symmetric MoM form); for other
+ * blocks the result is not the spectrum of A.  Without power steps the leading
+ * values are accurate only when the spectrum decays; 1 or 2 steps sharpen them
+ * (power_iters <= 8).  A rank-deficient sketch: MLFFT_E_SINGULAR.  Device memory:
+ * 4 l N x 16 bytes.  Blocking. */
+mlfft_status mlfft_spectrum(mlfft_ctx ctx, int array_id, int kind, int l, const void* Omega, int power_iters,
+                            double* sigma);
 
 /* ------------------------------------------------------------------ learned correction */
 /*

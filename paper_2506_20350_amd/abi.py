@@ -283,9 +283,37 @@ def mlfft_set_border(ctx, array_id: int, Nc: int, ZB_ptr, ZC_ptr, on_device: boo
     return check(ctx, lib().mlfft_set_border(ctx, array_id, Nc, ZB_ptr or None, ZC_ptr or None, int(on_device)))
 
 
+_SIGNATURES["mlfft_spectrum"] = (_ST, [_P, _I, _I, _I, _P, _I, ctypes.POINTER(ctypes.c_double)])
+
+
+def mlfft_spectrum(ctx, array_id: int, kind: int, l: int, Omega_ptr: int, power_iters: int = 0):
+    """Largest singular values (descending numpy array of l values) of P^{-1} Z."""
+    import numpy as np
+    out = np.zeros(l, dtype=np.float64)
+    check(ctx, lib().mlfft_spectrum(ctx, array_id, kind, l, Omega_ptr, power_iters,
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
 _SIGNATURES["mlfft_direct_solve"] = (_ST, [_P, _I, _I, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)])
 _SIGNATURES["mlfft_dense_gemm"] = (_ST, [_P, _I, _I, _I, _I, _D, _D, _P, _L, _P, _L, _D, _D, _P, _L])
 _SIGNATURES["mlfft_dense_solve"] = (_ST, [_P, _I, _P, _L, _P, _L, _I])
+_SIGNATURES["mlfft_dense_gemm_ah"] = (_ST, [_P, _I, _I, _I, _D, _D, _P, _L, _P, _L, _D, _D, _P, _L])
+_SIGNATURES["mlfft_dense_gen_eig"] = (_ST, [_P, _I, _P, _P, ctypes.POINTER(_D)])
+
+
+def mlfft_dense_gemm_ah(ctx, M: int, N: int, K: int, alpha: complex, A_ptr: int, lda: int, B_ptr: int, ldb: int,
+                        beta: complex, C_ptr: int, ldc: int):
+    alpha, beta = complex(alpha), complex(beta)
+    return check(ctx, lib().mlfft_dense_gemm_ah(ctx, M, N, K, alpha.real, alpha.imag, A_ptr, lda, B_ptr, ldb,
+                                                beta.real, beta.imag, C_ptr, ldc))
+
+
+def mlfft_dense_gen_eig(ctx, l: int, G_ptr: int, M_ptr: int):
+    import numpy as np
+    out = np.zeros(l, dtype=np.float64)
+    check(ctx, lib().mlfft_dense_gen_eig(ctx, l, G_ptr, M_ptr, out.ctypes.data_as(ctypes.POINTER(_D))))
+    return out
 
 
 def mlfft_direct_solve(ctx, array_id: int, W: int, V_ptr: int, I_ptr: int):

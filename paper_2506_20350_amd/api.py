@@ -170,6 +170,21 @@ class Context:
         abi.mlfft_precond_apply(self.h, array_id, kind, W, r.data_ptr(), z.data_ptr(), p)
         return z
 
+    def spectrum(self, array_id: int, Omega: torch.Tensor, kind: int = 1, power_iters: int = 1) -> np.ndarray:
+        """Largest singular values of P^{-1} Z from the l test vectors Omega (complex128 (l, N))."""
+        l = self._check_vec(array_id, Omega, abi.MLFFT_FP64, "Omega")
+        self.sync_stream()
+        return abi.mlfft_spectrum(self.h, array_id, kind, l, Omega.data_ptr(), power_iters)
+
+    def direct_solve(self, array_id: int, V: torch.Tensor, I: torch.Tensor = None):
+        """Z I = V by block Rybicki (with a border: the Schur complement); returns (I, (rcond, flops))."""
+        W = self._check_vec(array_id, V, abi.MLFFT_FP64, "V")
+        if I is None:
+            I = torch.empty_like(V)
+        self._check_vec(array_id, I, abi.MLFFT_FP64, "I")
+        self.sync_stream()
+        return I, abi.mlfft_direct_solve(self.h, array_id, W, V.data_ptr(), I.data_ptr())
+
     # ---------------------------------------------------------------- solve
     @staticmethod
     def make_opts(**kw) -> abi.SolveOpts:

@@ -21,7 +21,7 @@ BUILD = os.path.join(PKG, "_build")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libmlfft.so")
 
-SOURCES = ["fft2d.hip", "bgemm.hip", "bgemm_f32.hip", "bgemm_f64.hip", "bgemm_bf16.hip", "setup.hip", "krylov.hip", "net.hip", "lib.cpp", "solve.cpp", "netapi.cpp", "tune.cpp", "noalloc.hip", "dense.hip", "direct.cpp"]
+SOURCES = ["fft2d.hip", "bgemm.hip", "bgemm_f32.hip", "bgemm_f64.hip", "bgemm_bf16.hip", "setup.hip", "krylov.hip", "net.hip", "lib.cpp", "solve.cpp", "netapi.cpp", "tune.cpp", "noalloc.hip", "dense.hip", "direct.cpp", "spectrum.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

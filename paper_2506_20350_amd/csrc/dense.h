@@ -14,6 +14,20 @@ namespace mlfft {
 hipError_t dense_gemm(int prec, int M, int N, int K, double2 alpha, const void* A, long lda, long sA, const void* B,
                       long ldb, long sB, double2 beta, void* C, long ldc, long sC, int batch, hipStream_t s);
 
+// C = alpha A^H B + beta C (complex128) with A stored K x M (lda >= K): the Gram products of
+// the randomized range finder
+hipError_t dense_gemm_ah(int M, int N, int K, double2 alpha, const double2* A, long lda, const double2* B, long ldb,
+                         double2 beta, double2* C, long ldc, hipStream_t s);
+
+// out = conj(x) over n complex128 values
+hipError_t dense_conj(const double2* x, double2* out, size_t n, hipStream_t s);
+
+// out[0 .. l) = square roots of the eigenvalues of L^{-1} M L^{-H} (descending) for l x l Hermitian
+// G = L L^H and M, one workgroup (Cholesky, forward substitutions, `sweeps` round-robin Jacobi
+// sweeps); G, M overwritten, X l x l scratch; *info = 1 if G is not positive definite.  l <= 1024.
+hipError_t dense_herm_sqrt_eig(double2* G, double2* M, double2* X, int l, int sweeps, double* out, int* info,
+                               hipStream_t s);
+
 // LU with partial pivoting of the n x n matrix A in place (L unit lower, U upper,
 // ipiv[k] = row interchanged with row k, absolute).  *info (device, cleared by
 // the caller) receives the 1-based index of the first exactly zero pivot.

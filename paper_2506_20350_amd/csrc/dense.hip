@@ -48,7 +48,7 @@ template<> struct DMfma<float> {
 // the next step's operands prefetched into registers.  Complex products take four
 // real MFMAs (the real part subtracts Im A Im B through a negated operand).
 // blockIdx.z selects the batch entry (strides sA, sB, sC in elements).
-template<typename T>
+template<typename T, bool CONJA>
 __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, double2 alpha, const typename DMfma<T>::c_t* A,
                                                    long lda, long sA, const typename DMfma<T>::c_t* B, long ldb, long sB,
                                                    double2 beta, typename DMfma<T>::c_t* Cm, long ldc, long sC) {
@@ -77,9 +77,18 @@ __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, double2
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = tid + 256 * i;
-            const int ar = e & 63, ak = e >> 6;           // A: 64 consecutive rows of one column
-            const int gr = row0 + ar, gk = k0 + ak;
-            pa[i] = (gr < M && gk < K) ? A[(size_t)gk * lda + gr] : czero<C>();
+            if (!CONJA) {
+                const int ar = e & 63, ak = e >> 6;       // A: 64 consecutive rows of one column
+                const int gr = row0 + ar, gk = k0 + ak;
+                pa[i] = (gr < M && gk < K) ? A[(size_t)gk * lda + gr] : czero<C>();
+            } else {
+                // op(A) = A^H with A stored K x M: 16 consecutive rows of one stored column
+                const int ak = e & 15, ar = e >> 4;
+                const int gr = row0 + ar, gk = k0 + ak;
+                C v = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : czero<C>();
+                v.y = -v.y;
+                pa[i] = v;
+            }
             const int bk = e & 15, bc = e >> 4;           // B: 16 consecutive rows of one column
             const int hk = k0 + bk, hc = col0 + bc;
             pb[i] = (hk < K && hc < N) ? B[(size_t)hc * ldb + hk] : czero<C>();
@@ -91,8 +100,9 @@ __global__ void __launch_bounds__(256) zgemm_kernel(int M, int N, int K, double2
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int e = tid + 256 * i;
-            sAr[e >> 6][e & 63] = pa[i].x;
-            sAi[e >> 6][e & 63] = pa[i].y;
+            const int ak = CONJA ? (e & 15) : (e >> 6), ar = CONJA ? (e >> 4) : (e & 63);
+            sAr[ak][ar] = pa[i].x;
+            sAi[ak][ar] = pa[i].y;
             sBr[e & 15][e >> 4] = pb[i].x;
             sBi[e & 15][e >> 4] = pb[i].y;
         }
@@ -365,6 +375,161 @@ __global__ void transpose_kernel(const C* A, long lda, int m, int n, C* out, lon
     }
 }
 
+// out = conj(x) over n complex128 values (out may be x)
+__global__ void conj_kernel(const double2* x, double2* out, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double2 v = x[i];
+        out[i] = make_double2(v.x, -v.y);
+    }
+}
+
+// Eigenvalues of T = L^{-1} M L^{-H} for l x l Hermitian G = L L^H (positive definite)
+// and M (column-major, overwritten), one workgroup: Cholesky of G in place, two
+// forward substitutions (X = L^{-1} M, T = L^{-1} X^H, since M = M^H), then cyclic
+// two-sided Jacobi on T with the round-robin pairing (l/2 disjoint rotations at a
+// time; each rotation's angle, the inner one, from its 2 x 2 block before the round,
+// columns then rows updated).  out[i] = sqrt(max(lambda_i, 0)) in descending order.
+// X: l x l scratch; info: 1 if G is not positive definite.
+__global__ void __launch_bounds__(1024) herm_sqrt_eig_kernel(double2* G, double2* M, double2* X, int l, int sweeps,
+                                                             double* out, int* info) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ double s_d;
+    __shared__ int s_bad;
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    auto at = [l](double2* A, int r, int c) -> double2& { return A[(size_t)c * l + r]; };
+    // Cholesky, lower triangle of G
+    for (int j = 0; j < l; ++j) {
+        if (tid == 0) {
+            const double d = at(G, j, j).x;
+            if (!(d > 0.0)) s_bad = 1;
+            s_d = d > 0.0 ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double dj = s_d;
+        for (int i = j + tid; i < l; i += nt) {
+            double2& g = at(G, i, j);
+            g = i == j ? make_double2(dj, 0.0) : make_double2(g.x / dj, g.y / dj);
+        }
+        __syncthreads();
+        // trailing update G[i][k] -= L[i][j] conj(L[k][j]) for j < k <= i
+        const int rem = l - j - 1;
+        for (int e = tid; e < rem * rem; e += nt) {
+            const int i = j + 1 + e % rem, k = j + 1 + e / rem;
+            if (k > i) continue;
+            const double2 li = at(G, i, j), lk = at(G, k, j);
+            double2& g = at(G, i, k);
+            g = csub(g, cconjmul(lk, li));        // li * conj(lk)
+        }
+        __syncthreads();
+    }
+    // X = L^{-1} M, one column per thread
+    for (int c = tid; c < l; c += nt)
+        for (int i = 0; i < l; ++i) {
+            double2 v = at(M, i, c);
+            for (int k = 0; k < i; ++k) v = csub(v, cmul(at(G, i, k), at(X, k, c)));
+            const double d = at(G, i, i).x;
+            at(X, i, c) = make_double2(v.x / d, v.y / d);
+        }
+    __syncthreads();
+    // T = L^{-1} X^H into M
+    for (int c = tid; c < l; c += nt)
+        for (int i = 0; i < l; ++i) {
+            const double2 xh = at(X, c, i);
+            double2 v = make_double2(xh.x, -xh.y);
+            for (int k = 0; k < i; ++k) v = csub(v, cmul(at(G, i, k), at(M, k, c)));
+            const double d = at(G, i, i).x;
+            at(M, i, c) = make_double2(v.x / d, v.y / d);
+        }
+    __syncthreads();
+    // symmetrise (T is Hermitian up to rounding): keep the average of T and T^H
+    for (int e = tid; e < l * l; e += nt) {
+        const int i = e % l, k = e / l;
+        if (k < i) {
+            const double2 a = at(M, i, k), b = at(M, k, i);
+            const double2 m = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+            at(M, i, k) = m;
+            at(M, k, i) = make_double2(m.x, -m.y);
+        } else if (k == i) {
+            at(M, i, i).y = 0.0;
+        }
+    }
+    __syncthreads();
+    // round-robin Jacobi; n even (a dummy index n - 1 = l when l is odd is skipped)
+    const int n = (l + 1) & ~1;
+    __shared__ int pp[512], qq[512];
+    __shared__ double cs[512], sn[512];
+    __shared__ double2 ph[512];
+    for (int sw = 0; sw < sweeps; ++sw) {
+        for (int r = 0; r < n - 1; ++r) {
+            // pairs of round r: position 0 fixed, the others rotated by r
+            for (int k = tid; k < n / 2; k += nt) {
+                auto player = [n, r](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % (n - 1); };
+                int p = player(k), q = player(n - 1 - k);
+                if (p > q) { const int t = p; p = q; q = t; }
+                pp[k] = p;
+                qq[k] = q;
+                double c = 1.0, sv = 0.0;
+                double2 u = make_double2(1.0, 0.0);
+                if (q < l) {
+                    const double2 t = at(M, p, q);
+                    const double rr = hypot(t.x, t.y);
+                    if (rr > 0.0) {
+                        u = make_double2(t.x / rr, t.y / rr);
+                        // the inner rotation, |theta| <= pi/4 (the outer one swaps p and q and slows
+                        // the convergence of the sweeps)
+                        double th = 0.5 * atan2(2.0 * rr, at(M, p, p).x - at(M, q, q).x);
+                        if (th > 0.7853981633974483) th -= 1.5707963267948966;
+                        c = cos(th);
+                        sv = sin(th);
+                    }
+                }
+                cs[k] = c;
+                sn[k] = sv;
+                ph[k] = u;
+            }
+            __syncthreads();
+            // columns: T <- T U
+            for (int e = tid; e < (n / 2) * l; e += nt) {
+                const int k = e / l, row = e - k * l;
+                const int p = pp[k], q = qq[k];
+                if (q >= l || sn[k] == 0.0) continue;
+                const double c = cs[k], sv = sn[k];
+                const double2 u = ph[k];
+                const double2 a = at(M, row, p), b = at(M, row, q);
+                // col p: a c + b s conj(u);  col q: -a s u + b c
+                at(M, row, p) = cadd(cscale(a, c), cscale(cconjmul(u, b), sv));
+                at(M, row, q) = csub(cscale(b, c), cscale(cmul(a, u), sv));
+            }
+            __syncthreads();
+            // rows: T <- U^H T
+            for (int e = tid; e < (n / 2) * l; e += nt) {
+                const int k = e / l, col = e - k * l;
+                const int p = pp[k], q = qq[k];
+                if (q >= l || sn[k] == 0.0) continue;
+                const double c = cs[k], sv = sn[k];
+                const double2 u = ph[k];
+                const double2 a = at(M, p, col), b = at(M, q, col);
+                // row p: c a + s u b;  row q: -s conj(u) a + c b
+                at(M, p, col) = cadd(cscale(a, c), cscale(cmul(u, b), sv));
+                at(M, q, col) = csub(cscale(b, c), cscale(cconjmul(u, a), sv));
+            }
+            __syncthreads();
+        }
+    }
+    // sqrt of the diagonal, ranked in descending order (ties by index)
+    for (int i = tid; i < l; i += nt) {
+        const double v = at(M, i, i).x;
+        int rank = 0;
+        for (int j = 0; j < l; ++j) {
+            const double w = at(M, j, j).x;
+            rank += (w > v) || (w == v && j < i);
+        }
+        out[rank] = sqrt(fmax(v, 0.0));
+    }
+    if (tid == 0) *info = s_bad;
+}
+
 dim3 grid1(size_t n) {
     size_t g = (n + 255) / 256;
     if (g > 65536) g = 65536;
@@ -384,11 +549,20 @@ hipError_t dense_gemm(int prec, int M, int N, int K, double2 alpha, const void* 
         K = 0;
     }
     if (prec == 0)
-        hipLaunchKernelGGL(zgemm_kernel<double>, grid, dim3(256), 0, s, M, N, K, alpha, (const double2*)A, lda, sA,
-                           (const double2*)B, ldb, sB, beta, (double2*)C, ldc, sC);
+        hipLaunchKernelGGL((zgemm_kernel<double, false>), grid, dim3(256), 0, s, M, N, K, alpha, (const double2*)A, lda,
+                           sA, (const double2*)B, ldb, sB, beta, (double2*)C, ldc, sC);
     else
-        hipLaunchKernelGGL(zgemm_kernel<float>, grid, dim3(256), 0, s, M, N, K, alpha, (const float2*)A, lda, sA,
-                           (const float2*)B, ldb, sB, beta, (float2*)C, ldc, sC);
+        hipLaunchKernelGGL((zgemm_kernel<float, false>), grid, dim3(256), 0, s, M, N, K, alpha, (const float2*)A, lda,
+                           sA, (const float2*)B, ldb, sB, beta, (float2*)C, ldc, sC);
+    return hipGetLastError();
+}
+
+hipError_t dense_gemm_ah(int M, int N, int K, double2 alpha, const double2* A, long lda, const double2* B, long ldb,
+                         double2 beta, double2* C, long ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int tiles = ((M + kTile - 1) / kTile) * ((N + kTile - 1) / kTile);
+    hipLaunchKernelGGL((zgemm_kernel<double, true>), dim3(tiles, 1, 1), dim3(256), 0, s, M, N, K, alpha, A, lda, 0L,
+                       B, ldb, 0L, beta, C, ldc, 0L);
     return hipGetLastError();
 }
 
@@ -471,6 +645,18 @@ hipError_t dense_axpby2d(int prec, int m, int n, double2 alpha, const void* X, l
 hipError_t dense_transpose(const double2* A, long lda, int m, int n, double2* out, long ldo, hipStream_t s) {
     if (m <= 0 || n <= 0) return hipSuccess;
     hipLaunchKernelGGL(transpose_kernel<double2>, grid1((size_t)m * n), dim3(256), 0, s, A, lda, m, n, out, ldo);
+    return hipGetLastError();
+}
+
+hipError_t dense_conj(const double2* x, double2* out, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(conj_kernel, grid1(n), dim3(256), 0, s, x, out, n);
+    return hipGetLastError();
+}
+
+hipError_t dense_herm_sqrt_eig(double2* G, double2* M, double2* X, int l, int sweeps, double* out, int* info,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(herm_sqrt_eig_kernel, dim3(1), dim3(1024), 0, s, G, M, X, l, sweeps, out, info);
     return hipGetLastError();
 }
 

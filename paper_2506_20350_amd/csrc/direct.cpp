@@ -395,6 +395,39 @@ mlfft_status mlfft_dense_gemm(mlfft_ctx ctx, int prec, int M, int N, int K, doub
     return MLFFT_OK;
 }
 
+mlfft_status mlfft_dense_gemm_ah(mlfft_ctx ctx, int M, int N, int K, double alpha_re, double alpha_im, const void* A,
+                                 long lda, const void* B, long ldb, double beta_re, double beta_im, void* C, long ldc) {
+    if (!ctx) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    if (M < 0 || N < 0 || K < 0) return c->fail(MLFFT_E_ARG, "negative dimension");
+    if (M == 0 || N == 0) return MLFFT_OK;
+    if (!C || (K > 0 && (!A || !B))) return c->fail(MLFFT_E_ARG, "NULL matrix");
+    if (lda < std::max(K, 1) || ldb < std::max(K, 1) || ldc < M) return c->fail(MLFFT_E_ARG, "leading dimension too small");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    HIPCHK(dense_gemm_ah(M, N, K, make_double2(alpha_re, alpha_im), (const double2*)A, lda, (const double2*)B, ldb,
+                         make_double2(beta_re, beta_im), (double2*)C, ldc, c->stream), "dense product");
+    return MLFFT_OK;
+}
+
+mlfft_status mlfft_dense_gen_eig(mlfft_ctx ctx, int l, void* G, void* M, double* sigma) {
+    if (!ctx) return MLFFT_E_ARG;
+    Ctx* c = ctx;
+    if (l < 1 || l > 1024) return c->fail(MLFFT_E_ARG, "l must be in [1, 1024]");
+    if (!G || !M || !sigma) return c->fail(MLFFT_E_ARG, "NULL argument");
+    HIPCHK(hipSetDevice(c->device), "set device");
+    Buf Xb(&c->alloc);
+    HIPCHK(Xb.ensure((size_t)l * l * sizeof(double2) + l * sizeof(double) + 256), "eigenvalue workspace");
+    double* sv = (double*)((double2*)Xb.p + (size_t)l * l);
+    int* info = (int*)(sv + l);
+    HIPCHK(dense_herm_sqrt_eig((double2*)G, (double2*)M, (double2*)Xb.p, l, 16, sv, info, c->stream), "eigenvalues");
+    int hinfo = 0;
+    HIPCHK(hipMemcpyAsync(sigma, sv, l * sizeof(double), hipMemcpyDeviceToHost, c->stream), "eigenvalues");
+    HIPCHK(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, c->stream), "eigenvalues");
+    HIPCHK(hipStreamSynchronize(c->stream), "eigenvalues");
+    if (hinfo) return c->fail(MLFFT_E_SINGULAR, "G is not positive definite");
+    return MLFFT_OK;
+}
+
 mlfft_status mlfft_dense_solve(mlfft_ctx ctx, int n, void* A, long lda, void* B, long ldb, int ncols) {
     if (!ctx) return MLFFT_E_ARG;
     Ctx* c = ctx;

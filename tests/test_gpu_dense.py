@@ -70,6 +70,37 @@ def test_dense_gemm_beta_zero_ignores_nan_output(ctx):
     assert relerr(from_colmajor(Cd, 40).T, (A @ B).T) <= 1e-13
 
 
+@pytest.mark.parametrize("M,N,K,pad", [(1, 1, 1, 0), (48, 48, 48, 0), (40, 40, 180000, 0), (70, 33, 129, 3),
+                                       (130, 65, 17, 1)])
+def test_dense_gemm_conj_transposed_matches_numpy(ctx, M, N, K, pad):
+    rng = np.random.default_rng(M + 3 * N + K)
+    A, B, C = crand(rng, K, M), crand(rng, K, N), crand(rng, M, N)
+    alpha, beta = 1.1 + 0.2j, 0.5 - 0.5j
+    Ad, Bd, Cd = (colmajor(A, K + pad, torch.complex128), colmajor(B, K + pad, torch.complex128),
+                  colmajor(C, M + pad, torch.complex128))
+    ctx.sync_stream()
+    abi.mlfft_dense_gemm_ah(ctx.h, M, N, K, alpha, Ad.data_ptr(), K + pad, Bd.data_ptr(), K + pad, beta, Cd.data_ptr(),
+                            M + pad)
+    ref = alpha * (A.conj().T @ B) + beta * C
+    assert relerr(from_colmajor(Cd, M).T, ref.T) <= 1e-13
+
+
+@pytest.mark.parametrize("l", [1, 2, 7, 48, 64, 129, 256])
+def test_generalised_hermitian_eigenvalues_match_numpy(ctx, l):
+    """sqrt of the eigenvalues of M v = lambda G v (Cholesky + round-robin Jacobi in one workgroup)."""
+    import scipy.linalg as sla
+    rng = np.random.default_rng(l)
+    Y = crand(rng, l + 5, l)
+    G = Y.conj().T @ Y
+    Cm = crand(rng, 2 * l, l)
+    Mm = Cm.conj().T @ Cm
+    Gd, Md = colmajor(G, l, torch.complex128), colmajor(Mm, l, torch.complex128)
+    ctx.sync_stream()
+    sv = abi.mlfft_dense_gen_eig(ctx.h, l, Gd.data_ptr(), Md.data_ptr())
+    ref = np.sqrt(np.clip(np.sort(sla.eigh(Mm, G, eigvals_only=True))[::-1], 0, None))
+    assert np.max(np.abs(sv - ref)) <= 1e-10 * ref[0]
+
+
 @pytest.mark.parametrize("n,ncols", [(1, 1), (5, 3), (33, 7), (100, 40), (257, 9), (64, 1)])
 def test_dense_solve_matches_numpy(ctx, n, ncols):
     rng = np.random.default_rng(n + ncols)
