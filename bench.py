@@ -600,7 +600,7 @@ def main():
             GATED["learned"] = dict(precond=1)
             FORMS["learned"]["label"] = ("FP32 inner GMRES(30) + FP64 refinement, block-circulant preconditioner "
                                          "(the learned correction was trained and then gated off: it did not lower "
-                                         "the held-out loss below the gate)")
+                                         "the held-out GMRES iterations below the gate)")
     I, infos, dt, stats = timed_solves(ctx, 0, Vd, a.steps, a.warmup, a.form, a.tol, torch, a.inner_tol, a.orth)
     conv = [int(np.sum(inf["relres"] <= a.tol)) for inf in infos]
     value = sum(conv) / dt

@@ -15,6 +15,10 @@ int gemm_bp(int prec, int b) {
 }
 
 static GemmShape g_shape_override[3][33];      // [prec][bp/8]; waves == 0: not tuned
+static GemmShape g_shape_pc16[33];             // bf16 preconditioner product [bp/8]; waves == 0: default
+static int g_pc_wg_target = 512;               // workgroups a launch of the frequency kernel aims at
+
+void gemm_set_pc_wg_target(int n) { if (n >= 1 && n <= (1 << 20)) g_pc_wg_target = n; }
 
 static GemmShape default_shape(int prec, int bp) {
     if (prec == P64) return GemmShape{8, bp > 128 ? 16 : 32, 0};
@@ -31,8 +35,13 @@ GemmShape gemm_shape(int prec, int bp, int tag) {
         // product of the same b when that is an eight-wave flat shape
         const GemmShape& o = g_shape_override[prec][bp / 8];
         if (prec == P32 && o.m3 == 2 && o.waves == 8) return o;
-        // the bf16 preconditioner product takes a tuned or imported flat shape
-        if (prec == PBF16 && o.m3 == 2) return o;
+        // the bf16 preconditioner product: one frequency per workgroup (each X tile staged
+        // once for all row slices of its frequency) for padded b in 112..208, unless a shape
+        // was imported for it (below 112 the flat kernels are faster, beyond 208 the
+        // frequency kernel's stationary fragments spill)
+        if (prec == PBF16)
+            return g_shape_pc16[bp / 8].waves ? g_shape_pc16[bp / 8]
+                                              : (bp >= 112 && bp <= 208) ? GemmShape{8, 32, 3} : GemmShape{8, 32, 2};
         return GemmShape{8, 32, 2};
     }
     const GemmShape& o = g_shape_override[prec][bp / 8];
@@ -43,8 +52,15 @@ void gemm_set_shape(int prec, int bp, int waves, int nt, int m3) {
     if (prec < 0 || prec > 2 || bp < 8 || bp > 256 || bp % 8) return;
     // BF16 has the eight-row kernel (m3 = 0) and the flat kernel with eight waves and
     // 32-column tiles or four waves and 16-column tiles
-    if (prec == PBF16 && (m3 == 1 || (m3 == 2 && !((waves == 8 && nt == 32) || (waves == 4 && nt == 16))))) return;
+    if (prec == PBF16 && (m3 == 1 || (m3 == 2 && !((waves == 8 && nt == 32) || (waves == 4 && nt == 16))) ||
+                          (m3 == 3 && !(waves == 8 && nt == 32)) || m3 > 3)) return;
+    if (prec != PBF16 && m3 > 2) return;
     g_shape_override[prec][bp / 8] = GemmShape{waves, nt, m3};
+}
+
+void gemm_set_pc_shape(int bp, int waves, int nt, int m3) {
+    if (bp < 16 || bp > 256 || bp % 16) return;
+    g_shape_pc16[bp / 8] = waves ? GemmShape{waves, nt, m3} : GemmShape{0, 0, 0};
 }
 
 void gemm_get_shape(int prec, int bp, int* waves, int* nt, int* m3) {
@@ -64,6 +80,7 @@ static int bp_max_of(int prec, const GemmTask* tasks, int ntasks) {
 // multiple of the XCD count; the flat three-product kernel (m3 == 2) deals the
 // K * ceil(b/16) (frequency, slice) items to eight waves per workgroup
 static int task_blocks(const GemmTask& t, const GemmShape& sh) {
+    if (sh.m3 == 3) return t.K * t.mgroups;
     if (sh.m3 == 2) return (t.K * ((t.b + 15) / 16) + sh.waves - 1) / sh.waves;
     return ((t.K + kXcd - 1) / kXcd) * kXcd * t.mgroups;
 }
@@ -98,6 +115,12 @@ void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int tag, int* grid, 
         GemmTask& t = tasks[i];
         const int nslices = (t.b + rows - 1) / rows;
         t.mgroups = (nslices + sh.waves - 1) / sh.waves;
+        if (sh.m3 == 3) {
+            // one frequency per workgroup; its columns split so that the launch has at
+            // least g_pc_wg_target workgroups, each split reading G once more
+            const int tiles = (t.W + sh.nt - 1) / sh.nt;
+            t.mgroups = std::max(1, std::min(tiles, (g_pc_wg_target + t.K - 1) / std::max(t.K, 1)));
+        }
         t.block_begin = g;
         g += task_blocks(t, sh);
     }

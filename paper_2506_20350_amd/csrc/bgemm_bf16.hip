@@ -23,6 +23,16 @@ static hipError_t launch_b16_flat_cfg(const GemmTask& t0, const GemmTask* td, in
 }
 
 template<int BP, int TAG>
+static hipError_t launch_b16_freq(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
+    constexpr int BP32 = (BP + 31) / 32 * 32;
+    const size_t lds = (size_t)4 * 32 * (BP32 + 8) * sizeof(unsigned short);
+    auto k = bgemm_bf16_freq_kernel<BP, 32, TAG>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(512), lds, s, t0, td, n);
+    return hipGetLastError();
+}
+
+template<int BP, int TAG>
 static hipError_t launch_b16_flat(GemmShape sh, const GemmTask& t0, const GemmTask* td, int n, int grid,
                                   hipStream_t s) {
     if (sh.waves == 8 && sh.nt == 32) return launch_b16_flat_cfg<BP, TAG, 32, 8>(t0, td, n, grid, s);
@@ -37,6 +47,14 @@ static hipError_t launch_b16_flat(GemmShape sh, const GemmTask& t0, const GemmTa
 
 hipError_t launch_bgemm_bf16(int bp, GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
                              hipStream_t s) {
+    if (sh.m3 == 3) {
+        switch (bp) {
+#define Q16(B) case B: return tag ? launch_b16_freq<B, 1>(t0, td, n, grid, s) : launch_b16_freq<B, 0>(t0, td, n, grid, s);
+            MLFFT_BP16(Q16)
+#undef Q16
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (sh.m3 == 2) {
         switch (bp) {
 #define F16(B) case B: return tag ? launch_b16_flat<B, 1>(sh, t0, td, n, grid, s) \

@@ -821,4 +821,157 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_bf16_flat_kernel(GemmTask t0
     }
 }
 
+// BF16 inputs, FP32 accumulation, one frequency per workgroup: the product of the
+// preconditioner, which is bound by HBM (a bf16 ridge of 315 flop/B), so each X tile
+// of a frequency is staged into LDS once and serves all ceil(b/16) row slices of
+// that frequency.  The eight waves take slices w and w + 8; each keeps the two slices'
+// A fragments in registers as separate real and imaginary planes (Re G, Im G: half the
+// registers of the real-expanded form, which is what lets a wave hold two slices), and
+// the tile is staged as Re X and -Im X planes (bf16 rounding is symmetric, so -Im X
+// rounds to minus the rounded Im X).  A complex product is four MFMAs into two
+// accumulators: Re Y = Re G Re X + Im G (-Im X), Im Y = Im G Re X + (-Re G)(-Im X),
+// with -Re G formed by flipping sign bits.  The reduction runs over b padded to 32.  The columns
+// of a frequency may be split over a few workgroups (mgroups of them) so that a launch
+// has enough workgroups; each reads G once more.  X tiles are double-buffered with the
+// next tile prefetched into registers; a lane's four output rows leave as two 16-byte
+// stores.
+template<int BP, int NT, int TAG>
+__global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
+    constexpr int NTH = 512;
+    constexpr int BP32 = (BP + 31) / 32 * 32;
+    constexpr int S = BP32 / 32;                      // reduction steps of 32
+    constexpr int LDX = BP32 + 8;                     // bf16 elements per LDS row (16-byte skew)
+    constexpr int PF = (NT * BP + NTH - 1) / NTH;      // prefetched complex values per thread
+    extern __shared__ unsigned char smem_raw[];
+    unsigned short* xs = reinterpret_cast<unsigned short*>(smem_raw);   // [buffer][plane][NT][LDX]
+    const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
+    const int b = t.b, W = t.W, K = t.K, ncs = t.mgroups;
+    const int nwg = K * ncs;
+    const int local = blockIdx.x - t.block_begin;
+    const int per = nwg >> 3;
+    const int grp = local < per * 8 ? (local & 7) * per + (local >> 3) : local;
+    const int k = grp / ncs, chunk = grp - k * ncs;
+    const int ntile = (W + NT - 1) / NT;
+    const int tpc = (ntile + ncs - 1) / ncs;          // tiles per column chunk
+    const int wbeg = chunk * tpc * NT, wend = min(W, (chunk + 1) * tpc * NT);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = lane & 15, q = lane >> 4;
+    const int ns = (b + 15) >> 4;
+    bool act[2];
+    int mb[2];
+    ushortx8 gr[2][S], gi[2][S];
+    const uint32_t* __restrict__ Gk = static_cast<const uint32_t*>(t.G) + (size_t)k * t.gstride;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int sl = wave + 8 * h;
+        act[h] = sl < ns;
+        mb[h] = sl * 16;
+        const int m = mb[h] + j;
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            ushortx8 vr, vi;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int n = 32 * st + 8 * q + e;
+                uint32_t g = 0;
+                if (act[h] && m < b && n < b) g = gload(Gk + (size_t)m * b + n);
+                vr[e] = (unsigned short)(g & 0xffffu);
+                vi[e] = (unsigned short)(g >> 16);
+            }
+            gr[h][st] = vr;
+            gi[h][st] = vi;
+        }
+    }
+    // reduction padding n in [b, BP32) of every row, both planes, both buffers
+    const int padn = BP32 - b;
+    for (int e = threadIdx.x; e < 4 * NT * padn; e += NTH) {
+        const int row = e / padn, n = b + (e - row * padn);
+        xs[row * LDX + n] = 0;
+    }
+    const float2* __restrict__ Xk = static_cast<const float2*>(t.X) + (size_t)k * W * b;
+    float2* __restrict__ Yk = static_cast<float2*>(t.Y) + (size_t)k * W * b;
+    const int plane = NT * LDX, bufsz = 2 * plane;
+    float2 pre[PF];
+    auto fetch = [&](int w0) {
+        const int have = min(NT, wend - w0) * b;
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int e = threadIdx.x + i * NTH;
+            pre[i] = e < have ? gload(Xk + (size_t)w0 * b + e) : make_float2(0.f, 0.f);
+        }
+    };
+    auto stage = [&](unsigned short* buf) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+            const int e = threadIdx.x + i * NTH;
+            if (e < NT * b) {
+                const int w = e / b, n = e - w * b;
+                buf[w * LDX + n] = f32_to_bf16_bits(pre[i].x);
+                buf[plane + w * LDX + n] = f32_to_bf16_bits(-pre[i].y);
+            }
+        }
+    };
+    const bool even_b = (b & 1) == 0;
+    fetch(wbeg);                          // zeros when the chunk is empty
+    __syncthreads();                      // padding zeroed
+    stage(xs);
+    if (wbeg + NT < wend) fetch(wbeg + NT);
+    __syncthreads();
+    for (int w0 = wbeg, it = 0; w0 < wend; w0 += NT, ++it) {
+        const unsigned short* xr = xs + (it & 1) * bufsz;
+        const unsigned short* xn = xr + plane;            // -Im X
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (!act[h]) continue;
+            floatx4 cr[NT / 16], ci[NT / 16];
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) {
+                cr[cg] = floatx4{0, 0, 0, 0};
+                ci[cg] = floatx4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int st = 0; st < S; ++st) {
+                const bf16x8 ar = __builtin_bit_cast(bf16x8, gr[h][st]);
+                const bf16x8 ai = __builtin_bit_cast(bf16x8, gi[h][st]);
+                const bf16x8 an = __builtin_bit_cast(bf16x8, gr[h][st] ^ (unsigned short)0x8000u);   // -Re G
+#pragma unroll
+                for (int cg = 0; cg < NT / 16; ++cg) {
+                    const int off = (cg * 16 + j) * LDX + 32 * st + 8 * q;
+                    const bf16x8 br = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushortx8*>(&xr[off]));
+                    const bf16x8 bn = __builtin_bit_cast(bf16x8, *reinterpret_cast<const ushortx8*>(&xn[off]));
+                    // Re Y = Re G Re X + Im G (-Im X),  Im Y = Im G Re X + (-Re G)(-Im X)
+                    cr[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, cr[cg], 0, 0, 0);
+                    cr[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bn, cr[cg], 0, 0, 0);
+                    ci[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, ci[cg], 0, 0, 0);
+                    ci[cg] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(an, bn, ci[cg], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int cg = 0; cg < NT / 16; ++cg) {
+                const int w = w0 + cg * 16 + j;
+                if (w < wend) {
+                    float2 o[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) o[r] = make_float2(cr[cg][r], ci[cg][r]);
+                    const int m0 = mb[h] + 4 * q;
+                    float2* dst = Yk + (size_t)w * b + m0;
+                    if (even_b && m0 + 4 <= b) {
+                        gstore2(dst, o[0], o[1]);
+                        gstore2(dst + 2, o[2], o[3]);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (m0 + r < b) gstore(dst + r, o[r]);
+                    }
+                }
+            }
+        }
+        if (w0 + NT < wend) {
+            stage(xs + ((it + 1) & 1) * bufsz);
+            if (w0 + 2 * NT < wend) fetch(w0 + 2 * NT);
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace mlfft

@@ -74,6 +74,10 @@ void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int tag, int* grid, 
 // tuned launch shape of the MLFFT block product (waves per workgroup 4 or 8; columns per tile:
 // FP64 16 or 32, FP32 / BF16 32 or 64; FP32 three-product form m3 = 1)
 void gemm_set_shape(int prec, int bp, int waves, int nt, int m3);
+// launch shape of the bf16 preconditioner product (waves 0: the default, one frequency per workgroup)
+void gemm_set_pc_shape(int bp, int waves, int nt, int m3);
+// workgroups a launch of the bf16 preconditioner's frequency kernel aims at (columns split to reach it)
+void gemm_set_pc_wg_target(int n);
 void gemm_get_shape(int prec, int bp, int* waves, int* nt, int* m3);
 int gemm_bp(int prec, int b);
 

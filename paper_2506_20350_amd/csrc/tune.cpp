@@ -179,6 +179,17 @@ mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text) {
                              (a5 == 2 && a1 == 2 && a3 == 4 && a4 == 16));
             if (!ok) return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
             gemm_set_shape(a1, a2, a3, a4, a5);
+        } else if (sscanf(ln.c_str(), "gemmpc %d %d %d %d %d", &a1, &a2, &a3, &a4, &a5) == 5) {
+            // the bf16 preconditioner product: form 3 (one frequency per workgroup, padded b up
+            // to 208) or form 2 (the flat kernel, eight waves, 32-column tiles); waves 0 restores
+            // the default
+            const bool ok = a1 == 2 && a2 >= 16 && a2 <= 256 && a2 % 16 == 0 &&
+                            ((a3 == 8 && a4 == 32 && (a5 == 2 || (a5 == 3 && a2 <= 208))) || a3 == 0);
+            if (!ok) return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
+            gemm_set_pc_shape(a2, a3, a4, a5);
+        } else if (sscanf(ln.c_str(), "gemmpcwg %d", &a1) == 1) {
+            if (a1 < 1 || a1 > (1 << 20)) return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
+            gemm_set_pc_wg_target(a1);
         } else if (sscanf(ln.c_str(), "fftcm %d %d %d %d %d %d", &a1, &a2, &a3, &a4, &a5, &a6) == 6) {
             if (a1 < 0 || a1 > 1 || a2 < 0 || a2 > 1 || a6 < 0 || a6 > 64)
                 return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
