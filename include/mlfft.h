@@ -445,13 +445,16 @@ mlfft_status mlfft_tune_report(mlfft_ctx ctx, int array_id, char* buf, size_t n)
  * "gemm prec bp waves nt form" (form 0 four products, 1 three products, 2 three
  * products with the flat assignment, which takes prec 1 with waves 8 and nt 32
  * or 16, prec 1 with waves 4 and nt 16, or prec 0 with waves 4 and nt 16) and
- * "fftcm prec pad Nx Ny b cm", and "gemmpc 2 bp waves nt form" for the bf16
+ * "fftshape prec pad dir Nx Ny b cm half" (dir 0 forward, 1 inverse; cm the
+ * m-chunk, 0 for the default rule; half 1 for the half-height tile of a padded
+ * transform, 0 for the one-pass tile, -1 for the default), the older
+ * "fftcm prec pad Nx Ny b cm" (both directions), and "gemmpc 2 bp waves nt form" for the bf16
  * preconditioner product with bp a multiple of 16 (form 3, bp <= 208: one
  * frequency per workgroup, the default for bp in 112..208; form 2 with 8 waves
  * and 32-column tiles: the flat kernel, the default elsewhere; waves 0 restores
  * the default), "gemmpcwg n" for the number of workgroups a launch of the form-3 kernel
  * aims at (the columns of a frequency are split to reach it; default 512); other
- * lines are ignored.  MLFFT_E_ARG for a malformed gemm, gemmpc, gemmpcwg or fftcm line. */
+ * lines are ignored.  MLFFT_E_ARG for a malformed gemm, gemmpc, gemmpcwg, fftshape or fftcm line. */
 mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text);
 
 /* ------------------------------------------------------------------ profiling */

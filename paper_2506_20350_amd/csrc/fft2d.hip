@@ -179,6 +179,94 @@ __global__ void __launch_bounds__(512) fft_fwd_kernel(FftTask t0, const FftTask*
     dispatch_n<FwdX, C, CLS>(t->Nx, tl, wk, (const C*)tile);
 }
 
+// ---------------------------------------------------------------- forward, half-height tile
+
+// The padded forward in two halves: the even-ky rows (the length-Ny DFT of each
+// column) are written to a tile of Ny rows and transformed along x; then the
+// odd-ky rows (the DFT of the twiddled column) go through the same tile.  Each
+// thread keeps its input column in registers between the halves, so the column
+// is read from HBM once.  The tile is half as tall as the one-pass kernel's,
+// which admits twice the m-chunk (longer contiguous runs in the spectrum) or two
+// workgroups per CU.
+template<typename C, int NY>
+struct FwdYHalf {
+    static __device__ __forceinline__ void run(const FftTask& tt, Work wk, C* tile, C* xin, int par) {
+        const FftTask* t = &tt;
+        const int Nx = t->Nx, cm = t->cm, b = t->b;
+        const int tid = threadIdx.x;
+        if (tid >= Nx * cm) return;
+        const int ix = tid / cm, mi = tid - ix * cm;
+        if (mi >= wk.mlen) return;
+        C v[NY];
+        if (par == 0) {
+            const C* __restrict__ src = static_cast<const C*>(t->in)
+                + (size_t)wk.w * ((size_t)NY * Nx * b + t->colpad) + (size_t)ix * b + wk.m0 + mi;
+            const size_t ys = (size_t)Nx * b;
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy) v[iy] = src[iy * ys];
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy) xin[iy] = v[iy];
+        } else {
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy) v[iy] = xin[iy];
+            Fft<C, NY, -1>::tw2(v);
+        }
+        Fft<C, NY, -1>::run(v);
+        C* col = tile + ix * cm + mi;
+#pragma unroll
+        for (int j = 0; j < NY; ++j) col[j * t->rs] = v[j];
+    }
+};
+
+template<typename C, int NX>
+struct FwdXHalf {
+    static __device__ __forceinline__ void run(const FftTask& tt, Work wk, const C* tile, int par) {
+        const FftTask* t = &tt;
+        const int cm = t->cm, b = t->b, W = t->W;
+        const int Px = 2 * NX;
+        const int tid = threadIdx.x;
+        if (tid >= t->Ny * cm) return;
+        const int a = tid / cm, mi = tid - a * cm;
+        if (mi >= wk.mlen) return;
+        const int ky = 2 * a + par;
+        C* __restrict__ dst = static_cast<C*>(t->out) + (size_t)wk.w * b + wk.m0 + mi;
+        const size_t ks = (size_t)W * b;
+        for (int g = 0; g < 2; ++g) {
+            C v[NX];
+#pragma unroll
+            for (int ix = 0; ix < NX; ++ix) v[ix] = tile[a * t->rs + ix * cm + mi];
+            if (g) Fft<C, NX, -1>::tw2(v);
+            Fft<C, NX, -1>::run(v);
+#pragma unroll
+            for (int i = 0; i < NX; ++i) dst[(size_t)(ky * Px + 2 * i + g) * ks] = v[i];
+        }
+    }
+};
+
+template<typename C, int CLS, int LB>
+__global__ void __launch_bounds__(LB) fft_fwd_half_kernel(FftTask t0, const FftTask* tasks, int ntasks) {
+    extern __shared__ unsigned char smem_raw[];
+    C* tile = reinterpret_cast<C*>(smem_raw);
+    const int bid = work_index();
+    FftTask tl = ntasks > 0 ? *find_task(tasks, ntasks, bid) : t0;
+    tl.pad = 1;
+    const FftTask* t = &tl;
+    const int local = bid - t->block_begin;
+    Work wk;
+    wk.w = local / t->nmc;
+    const int mc = local - wk.w * t->nmc;
+    wk.m0 = mc * t->cm;
+    wk.mlen = min(t->cm, t->b - wk.m0);
+    C xin[32];
+    dispatch_n<FwdYHalf, C, CLS>(t->Ny, tl, wk, tile, xin, 0);
+    __syncthreads();
+    dispatch_n<FwdXHalf, C, CLS>(t->Nx, tl, wk, (const C*)tile, 0);
+    __syncthreads();
+    dispatch_n<FwdYHalf, C, CLS>(t->Ny, tl, wk, tile, xin, 1);
+    __syncthreads();
+    dispatch_n<FwdXHalf, C, CLS>(t->Nx, tl, wk, (const C*)tile, 1);
+}
+
 // ---------------------------------------------------------------- inverse
 
 template<typename C, int NX>
@@ -286,11 +374,11 @@ __global__ void __launch_bounds__(512) fft_inv_kernel(FftTask t0, const FftTask*
 
 // ---------------------------------------------------------------- inverse, half-height tile
 
-// The padded inverse (FP32) in two halves: the even-ky rows are transformed
-// along x into a tile of Ny rows and then along y into registers; the odd-ky
-// rows follow through the same tile and are added.  The tile is half as tall
-// as the one-pass kernel's, so two workgroups share a CU and one's loads overlap
-// the other's arithmetic.
+// The padded inverse in two halves: the even-ky rows are transformed along x
+// into a tile of Ny rows and then along y into registers; the odd-ky rows
+// follow through the same tile and are added.  The tile is half as tall as the
+// one-pass kernel's, so two workgroups share a CU and one's loads overlap the
+// other's arithmetic (or one workgroup takes twice the m-chunk).
 template<typename C, int NX>
 struct InvXHalf {
     static __device__ __forceinline__ void run(const FftTask& tt, Work wk, C* tile, int par) {
@@ -304,6 +392,23 @@ struct InvXHalf {
         const int ky = 2 * a + par;
         const C* __restrict__ src = static_cast<const C*>(t->in) + (size_t)wk.w * b + wk.m0 + mi;
         const size_t ks = (size_t)W * b;
+        C* row = tile + a * t->rs + mi;
+        if (sizeof(C) == 16) {
+            // FP64: one half-length vector live at a time, the odd-kx half added in LDS
+            C v[NX];
+#pragma unroll
+            for (int i = 0; i < NX; ++i) v[i] = src[(size_t)(ky * Px + 2 * i) * ks];
+            Fft<C, NX, 1>::run(v);
+#pragma unroll
+            for (int ix = 0; ix < NX; ++ix) row[ix * cm] = v[ix];
+#pragma unroll
+            for (int i = 0; i < NX; ++i) v[i] = src[(size_t)(ky * Px + 2 * i + 1) * ks];
+            Fft<C, NX, 1>::run(v);
+            Fft<C, NX, 1>::tw2(v);
+#pragma unroll
+            for (int ix = 0; ix < NX; ++ix) row[ix * cm] = cadd(row[ix * cm], v[ix]);
+            return;
+        }
         C v[NX], o[NX];
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
@@ -313,7 +418,6 @@ struct InvXHalf {
         Fft<C, NX, 1>::run(v);
         Fft<C, NX, 1>::run(o);
         Fft<C, NX, 1>::tw2(o);
-        C* row = tile + a * t->rs + mi;
 #pragma unroll
         for (int ix = 0; ix < NX; ++ix) row[ix * cm] = cadd(v[ix], o[ix]);
     }
@@ -333,6 +437,15 @@ struct InvYHalf {
         if (mi >= wk.mlen) return;
         const C* col = tile + ix * cm + mi;
         const int rs = t->rs;
+        const size_t off = (size_t)wk.w * ((size_t)NY * Nx * b + t->colpad) + (size_t)ix * b + wk.m0 + mi;
+        const size_t ys = (size_t)Nx * b;
+        // the addend is requested before the odd half's transform, which hides its latency
+        C av[NY];
+        if (par == 1 && t->addend) {
+            const C* __restrict__ add = static_cast<const C*>(t->addend) + off;
+#pragma unroll
+            for (int iy = 0; iy < NY; ++iy) av[iy] = add[iy * ys];
+        }
         C v[NY];
 #pragma unroll
         for (int j = 0; j < NY; ++j) v[j] = col[j * rs];
@@ -345,18 +458,13 @@ struct InvYHalf {
         Fft<C, NY, 1>::tw2(v);
 #pragma unroll
         for (int iy = 0; iy < NY; ++iy) v[iy] = cadd(v[iy], e[iy]);
-        const size_t off = (size_t)wk.w * ((size_t)NY * Nx * b + t->colpad) + (size_t)ix * b + wk.m0 + mi;
-        const size_t ys = (size_t)Nx * b;
         C* __restrict__ dst = static_cast<C*>(t->out) + off;
         const R alpha = (R)t->alpha;
         if (t->addend) {
-            const C* __restrict__ add = static_cast<const C*>(t->addend) + off;
             const R beta = (R)t->beta;
 #pragma unroll
-            for (int iy = 0; iy < NY; ++iy) {
-                const C a = add[iy * ys];
-                dst[iy * ys] = cmake<C>(v[iy].x * alpha + a.x * beta, v[iy].y * alpha + a.y * beta);
-            }
+            for (int iy = 0; iy < NY; ++iy)
+                dst[iy * ys] = cmake<C>(v[iy].x * alpha + av[iy].x * beta, v[iy].y * alpha + av[iy].y * beta);
         } else {
 #pragma unroll
             for (int iy = 0; iy < NY; ++iy) dst[iy * ys] = cscale(v[iy], alpha);
@@ -364,8 +472,8 @@ struct InvYHalf {
     }
 };
 
-template<typename C, int CLS>
-__global__ void __launch_bounds__(512) fft_inv_half_kernel(FftTask t0, const FftTask* tasks, int ntasks) {
+template<typename C, int CLS, int LB>
+__global__ void __launch_bounds__(LB) fft_inv_half_kernel(FftTask t0, const FftTask* tasks, int ntasks) {
     extern __shared__ unsigned char smem_raw[];
     C* tile = reinterpret_cast<C*>(smem_raw);
     const int bid = work_index();
@@ -392,22 +500,42 @@ __global__ void __launch_bounds__(512) fft_inv_half_kernel(FftTask t0, const Fft
 
 static const size_t kLdsBudget = 160 * 1024;
 
-// tuned m-chunk per (prec, pad, Nx, Ny, b); absent: the default rule
-static std::map<std::tuple<int, int, int, int, int>, int> g_cm_override;
+// tuned m-chunk and tile choice per (prec, pad, dir, Nx, Ny, b); cm 0: the default
+// rule, half -1: the default choice
+struct FftChoice {
+    int cm = 0;
+    int half = -1;
+};
+static std::map<std::tuple<int, int, int, int, int, int>, FftChoice> g_fft_override;
 
-void fft_set_cm(int prec, int pad, int Nx, int Ny, int b, int cm) {
-    if (cm <= 0) g_cm_override.erase(std::make_tuple(prec, pad, Nx, Ny, b));
-    else g_cm_override[std::make_tuple(prec, pad, Nx, Ny, b)] = cm;
+void fft_set_choice(int prec, int pad, int dir, int Nx, int Ny, int b, int cm, int half) {
+    const auto key = std::make_tuple(prec, pad, dir, Nx, Ny, b);
+    if (cm <= 0 && half < 0) { g_fft_override.erase(key); return; }
+    g_fft_override[key] = FftChoice{cm > 0 ? cm : 0, half};
 }
 
-int fft_get_cm(int prec, int pad, int Nx, int Ny, int b) {
-    auto it = g_cm_override.find(std::make_tuple(prec, pad, Nx, Ny, b));
-    return it == g_cm_override.end() ? 0 : it->second;
+static FftChoice choice_of(int prec, int pad, int dir, int Nx, int Ny, int b) {
+    auto it = g_fft_override.find(std::make_tuple(prec, pad, dir, Nx, Ny, b));
+    return it == g_fft_override.end() ? FftChoice{} : it->second;
 }
 
-// largest m-chunk the launch limits allow (LDS tile and 512 threads)
+// Half-height tile: padded transforms whose lengths are not the primes 17..31
+// (their direct DFTs would spill with a parked half-length vector), by default
+// in both directions and precisions.
+bool fft_use_half(int prec, int pad, int dir, int Nx, int Ny, int b) {
+    if (!pad || std::max(len_class(Nx), len_class(Ny)) > 1) return false;
+    const FftChoice c = choice_of(prec, pad, dir, Nx, Ny, b);
+    if (c.half >= 0) return c.half != 0;
+    return true;
+}
+
+// threads a workgroup may have: the FP64 half-height kernels are bounded at 256
+// so that a wave may hold the parked half-length vector (and the codelet) in up
+// to 512 registers without spilling
+static int thread_limit(int prec, bool half) { return prec == P64 && half ? 256 : 512; }
+
 // LDS rows of a tile
-static int tile_rows(int prec, int pad, int Ny) { (void)prec; return (pad ? 2 : 1) * Ny; }
+static int tile_rows(int pad, bool half, int Ny) { return pad && !half ? 2 * Ny : Ny; }
 
 // Row stride of a tile in elements.  A wave reads 64 / cm rows of cm consecutive
 // elements each (the x-transforms); with the stride a multiple of the segment
@@ -420,31 +548,43 @@ static int tile_stride(int eb, int Nx, int cm) {
     return rs;
 }
 
-int fft_max_cm(int prec, int pad, int Nx, int Ny, int b) {
-    const int eb = prec == P64 ? 16 : 8;
-    const int Py = tile_rows(prec, pad, Ny);
+static int elem_bytes(int prec) { return prec == P64 ? 16 : 8; }
+
+static bool cm_fits(int prec, int pad, bool half, int Nx, int Ny, int cm) {
+    const int eb = elem_bytes(prec);
+    const int Py = tile_rows(pad, half, Ny);
+    return (size_t)Py * tile_stride(eb, Nx, cm) * eb <= kLdsBudget &&
+           (Py > Nx ? Py : Nx) * cm <= thread_limit(prec, half);
+}
+
+// largest power-of-two m-chunk (up to 64 and b) the launch limits allow for a tile choice
+int fft_max_cm(int prec, int pad, int half, int Nx, int Ny, int b) {
     int cm = 64;
     if (cm > b) cm = b;
-    while (cm > 1 && ((size_t)Py * tile_stride(eb, Nx, cm) * eb > kLdsBudget || (Py > Nx ? Py : Nx) * cm > 512))
-        cm >>= 1;
+    while (cm > 1 && !cm_fits(prec, pad, half != 0, Nx, Ny, cm)) cm >>= 1;
     return cm;
 }
 
-static int elem_bytes(int prec) { return prec == P64 ? 16 : 8; }
+void fft_get_choice(int prec, int pad, int dir, int Nx, int Ny, int b, int* cm, int* half) {
+    *cm = choice_of(prec, pad, dir, Nx, Ny, b).cm;
+    *half = fft_use_half(prec, pad, dir, Nx, Ny, b) ? 1 : 0;
+}
 
-void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block, size_t* lds) {
+void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int dir, int* grid, int* block, size_t* lds) {
     const int eb = elem_bytes(prec);
     int g = 0, blk = 64;
     size_t l = 0;
     for (int i = 0; i < ntasks; ++i) {
         FftTask& t = tasks[i];
-        const int Py = tile_rows(prec, t.pad, t.Ny);
-        // default: 64-byte contiguous runs per series group; shrink when LDS would overflow
-        int cm = fft_get_cm(prec, t.pad, t.Nx, t.Ny, t.b);
-        if (cm <= 0) cm = 64 / eb;
+        const bool half = fft_use_half(prec, t.pad, dir, t.Nx, t.Ny, t.b);
+        const int Py = tile_rows(t.pad, half, t.Ny);
+        // default: 128-byte contiguous runs per series group (whole 128-byte lines of
+        // the spectrum), 64-byte runs when that would leave fewer than 2048
+        // workgroups; shrink when LDS or the thread limit would overflow
+        int cm = choice_of(prec, t.pad, dir, t.Nx, t.Ny, t.b).cm;
+        if (cm <= 0) cm = (size_t)t.W * ((t.b + 128 / eb - 1) / (128 / eb)) >= 2048 ? 128 / eb : 64 / eb;
         if (cm > t.b) cm = t.b;
-        while (cm > 1 && (size_t)Py * tile_stride(eb, t.Nx, cm) * eb > kLdsBudget) cm >>= 1;
-        while (cm > 1 && (Py > t.Nx ? Py : t.Nx) * cm > 512) cm >>= 1;
+        while (cm > 1 && !cm_fits(prec, t.pad, half, t.Nx, t.Ny, cm)) cm >>= 1;
         t.cm = cm;
         t.nmc = (t.b + cm - 1) / cm;
         t.block_begin = g;
@@ -461,33 +601,39 @@ void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block,
     *lds = l;
 }
 
-int fft_group_key(int prec, const FftTask& t) {
+int fft_group_key(int prec, const FftTask& t, int dir) {
     FftTask one = t;
     int grid, block;
     size_t lds;
-    plan_fft_tasks(prec, &one, 1, &grid, &block, &lds);
+    plan_fft_tasks(prec, &one, 1, dir, &grid, &block, &lds);
     int bucket = 0;
     while (((size_t)1 << bucket) < lds) ++bucket;
-    return std::max(len_class(t.Nx), len_class(t.Ny)) * 64 + bucket;
+    const int half = fft_use_half(prec, t.pad, dir, t.Nx, t.Ny, t.b) ? 1 : 0;
+    return (half * 4 + std::max(len_class(t.Nx), len_class(t.Ny))) * 64 + bucket;
 }
 
 typedef void (*FftKernel)(FftTask, const FftTask*, int);
 
+static FftKernel with_lds(FftKernel k) {
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
+    return k;
+}
+
 template<typename C, int INV>
 static FftKernel pick_kernel(int cls, int pad) {
-#define PICK(CL, PD) if (cls == CL && pad == PD) { \
-        FftKernel k = INV ? (FftKernel)fft_inv_kernel<C, CL, PD> : (FftKernel)fft_fwd_kernel<C, CL, PD>; \
-        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget); \
-        return k; }
+#define PICK(CL, PD) if (cls == CL && pad == PD) \
+        return with_lds(INV ? (FftKernel)fft_inv_kernel<C, CL, PD> : (FftKernel)fft_fwd_kernel<C, CL, PD>);
     PICK(0, 0) PICK(0, 1) PICK(1, 0) PICK(1, 1) PICK(2, 0) PICK(2, 1)
 #undef PICK
     return nullptr;
 }
 
-static FftKernel pick_inv_half(int cls) {
-    FftKernel k = cls == 0 ? (FftKernel)fft_inv_half_kernel<float2, 0> : (FftKernel)fft_inv_half_kernel<float2, 1>;
-    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
-    return k;
+template<typename C, int INV>
+static FftKernel pick_half(int cls) {
+    constexpr int LB = sizeof(C) == 16 ? 256 : 512;
+    if (cls > 1) return nullptr;
+    if (INV) return with_lds(cls == 0 ? (FftKernel)fft_inv_half_kernel<C, 0, LB> : (FftKernel)fft_inv_half_kernel<C, 1, LB>);
+    return with_lds(cls == 0 ? (FftKernel)fft_fwd_half_kernel<C, 0, LB> : (FftKernel)fft_fwd_half_kernel<C, 1, LB>);
 }
 
 template<typename C, int INV>
@@ -497,16 +643,12 @@ static hipError_t launch_t(const FftTask* th, const FftTask* td, int ntasks, hip
     size_t lds = 0;
     const int eb = sizeof(C);
     const int prec = sizeof(C) == 16 ? P64 : P32;
-    // the padded FP32 inverse runs with the half-height tile, except for the prime
-    // lengths 17..31, whose direct DFTs would then spill registers (the forward,
-    // bound by its scattered spectrum stores, gained nothing from it)
-    bool half = INV && prec == P32 && ntasks > 0 && th[0].pad;
-    for (int i = 0; i < ntasks && half; ++i)
-        half = std::max(len_class(th[i].Nx), len_class(th[i].Ny)) <= 1;
+    if (ntasks <= 0) return hipSuccess;
+    const bool half = fft_use_half(prec, th[0].pad, INV, th[0].Nx, th[0].Ny, th[0].b);
     for (int i = 0; i < ntasks; ++i) {
         const FftTask& t = th[i];
-        if (t.pad != th[0].pad) return hipErrorInvalidValue;
-        const int Py = half ? t.Ny : tile_rows(prec, t.pad, t.Ny);
+        if (t.pad != th[0].pad || fft_use_half(prec, t.pad, INV, t.Nx, t.Ny, t.b) != half) return hipErrorInvalidValue;
+        const int Py = tile_rows(t.pad, half, t.Ny);
         grid = t.block_begin + t.nmc * t.W > grid ? t.block_begin + t.nmc * t.W : grid;
         int thr = ((Py > t.Nx ? Py : t.Nx) * t.cm + 63) / 64 * 64;
         if (thr > block) block = thr;
@@ -515,7 +657,8 @@ static hipError_t launch_t(const FftTask* th, const FftTask* td, int ntasks, hip
         cls = std::max(cls, std::max(len_class(t.Nx), len_class(t.Ny)));
     }
     if (grid == 0) return hipSuccess;
-    FftKernel k = half ? pick_inv_half(cls) : pick_kernel<C, INV>(cls, th[0].pad);
+    if (block > thread_limit(prec, half) || lds > kLdsBudget) return hipErrorInvalidValue;
+    FftKernel k = half ? pick_half<C, INV>(cls) : pick_kernel<C, INV>(cls, th[0].pad);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, s, th[0], ntasks > 1 ? td : nullptr, ntasks > 1 ? ntasks : 0);
     return hipGetLastError();

@@ -56,18 +56,23 @@ hipError_t launch_fft_fwd(int prec, const FftTask* tasks_host, const FftTask* ta
                           hipStream_t s);
 hipError_t launch_fft_inv(int prec, const FftTask* tasks_host, const FftTask* tasks_dev, int ntasks,
                           hipStream_t s);
-// fills cm / nmc / block_begin for a list of tasks; returns the total grid size and the
-// block size / dynamic LDS bytes the grouped launch needs
-void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int* grid, int* block, size_t* lds);
-// key of the launch a task joins: its length class and its LDS tile size rounded up to a power of two
-int fft_group_key(int prec, const FftTask& t);
+// fills cm / nmc / block_begin for a list of tasks of one direction (dir 0 forward,
+// 1 inverse); returns the total grid size and the block size / dynamic LDS bytes the
+// grouped launch needs
+void plan_fft_tasks(int prec, FftTask* tasks, int ntasks, int dir, int* grid, int* block, size_t* lds);
+// key of the launch a task joins: its tile kind (one-pass or half-height), its length
+// class and its LDS tile size rounded up to a power of two
+int fft_group_key(int prec, const FftTask& t, int dir);
+
+// tuned FFT m-chunk (basis functions per workgroup) and tile kind per (prec, pad, dir,
+// shape); cm <= 0 keeps the default rule, half < 0 the default tile
+void fft_set_choice(int prec, int pad, int dir, int Nx, int Ny, int b, int cm, int half);
+// the tuned m-chunk (0: default rule) and the tile kind in force (1: half-height)
+void fft_get_choice(int prec, int pad, int dir, int Nx, int Ny, int b, int* cm, int* half);
+bool fft_use_half(int prec, int pad, int dir, int Nx, int Ny, int b);
+int fft_max_cm(int prec, int pad, int half, int Nx, int Ny, int b);
 
 // tag 0: MLFFT spectra, 1: preconditioner (separate kernel symbols for profilers)
-// tuned FFT m-chunk (basis functions per workgroup); cm <= 0 restores the default rule
-void fft_set_cm(int prec, int pad, int Nx, int Ny, int b, int cm);
-int fft_get_cm(int prec, int pad, int Nx, int Ny, int b);
-int fft_max_cm(int prec, int pad, int Nx, int Ny, int b);
-
 hipError_t launch_bgemm(int prec, const GemmTask* tasks_host, const GemmTask* tasks_dev, int ntasks, int tag,
                         hipStream_t s);
 void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int tag, int* grid, int* bp_max);

@@ -205,13 +205,13 @@ mlfft_status Ctx::fft_grouped(int prec, std::vector<FftTask>& tasks, bool invers
     // the transforms of the bf16-product forms are FP32 (and tuned as such)
     if (prec == PBF16) prec = P32;
     std::map<int, std::vector<FftTask>> groups;
-    for (const FftTask& t : tasks) groups[fft_group_key(prec, t)].push_back(t);
+    for (const FftTask& t : tasks) groups[fft_group_key(prec, t, inverse ? 1 : 0)].push_back(t);
     for (auto& kv : groups) {
         std::vector<FftTask>& sub = kv.second;
         const int n = (int)sub.size();
         int grid, block;
         size_t lds;
-        plan_fft_tasks(prec, sub.data(), n, &grid, &block, &lds);
+        plan_fft_tasks(prec, sub.data(), n, inverse ? 1 : 0, &grid, &block, &lds);
         void* d = nullptr;
         if (n > 1) {
             mlfft_status st = upload_tasks(sub.data(), sizeof(FftTask) * n, &d);

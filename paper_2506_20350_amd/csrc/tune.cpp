@@ -103,33 +103,41 @@ mlfft_status mlfft_autotune(mlfft_ctx ctx, int array_id, int W, int prec, int re
         }
         if (bw) gemm_set_shape(prec, bp, bw, bn, bm);
     }
-    // ---- forward / inverse 2-D FFT (MLFFT grid and preconditioner torus)
+    // ---- forward / inverse 2-D FFT (MLFFT grid and preconditioner torus), each
+    // direction on its own: tile kind (one-pass or half-height, padded grids) x m-chunk
     const int fprec = prec == P64 ? P64 : P32;
     for (int pad : {1, 0}) {
-        const int cmax = fft_max_cm(fprec, pad, a->Nx, a->Ny, a->b);
-        int bestcm = 0;
-        double bestms = 1e30;
-        for (int cm = 1; cm <= cmax; cm *= 2) {
-            fft_set_cm(fprec, pad, a->Nx, a->Ny, a->b, cm);
-            FftTask f{}, v{};
-            f.in = c->spec_b.p; f.out = c->spec_a.p; f.alpha = 1.0;
-            f.Nx = a->Nx; f.Ny = a->Ny; f.b = a->b; f.W = W; f.pad = pad;
-            v = f;
-            v.in = c->spec_a.p; v.out = c->spec_b.p;
-            int grid, block;
-            size_t lds;
-            plan_fft_tasks(fprec, &f, 1, &grid, &block, &lds);
-            plan_fft_tasks(fprec, &v, 1, &grid, &block, &lds);
-            const double ms = time_it(c, reps, [&]() {
-                hipError_t e = launch_fft_fwd(fprec, &f, nullptr, 1, c->stream);
-                return e != hipSuccess ? e : launch_fft_inv(fprec, &v, nullptr, 1, c->stream);
-            });
-            snprintf(line, sizeof line, "fft pair prec=%d pad=%d Nx=%d Ny=%d b=%d W=%d cm=%d: %.4f ms\n", fprec, pad,
-                     a->Nx, a->Ny, a->b, W, cm, ms);
-            rep += line;
-            if (ms > 0 && ms < kTuneMargin * bestms) { bestms = ms; bestcm = cm; }
+        for (int dir : {0, 1}) {
+            int bestcm = 0, besthalf = -1;
+            double bestms = 1e30;
+            for (int half : {0, 1}) {
+                if (half && !pad) continue;
+                fft_set_choice(fprec, pad, dir, a->Nx, a->Ny, a->b, 0, half);
+                if (fft_use_half(fprec, pad, dir, a->Nx, a->Ny, a->b) != (half != 0)) continue;   // prime lengths
+                const int cmax = fft_max_cm(fprec, pad, half, a->Nx, a->Ny, a->b);
+                for (int cm = 1; cm <= cmax; cm *= 2) {
+                    fft_set_choice(fprec, pad, dir, a->Nx, a->Ny, a->b, cm, half);
+                    FftTask f{};
+                    f.in = dir ? c->spec_a.p : c->spec_b.p;
+                    f.out = dir ? c->spec_b.p : c->spec_a.p;
+                    f.alpha = 1.0;
+                    f.Nx = a->Nx; f.Ny = a->Ny; f.b = a->b; f.W = W; f.pad = pad;
+                    int grid, block;
+                    size_t lds;
+                    plan_fft_tasks(fprec, &f, 1, dir, &grid, &block, &lds);
+                    if (f.cm != cm) continue;
+                    const double ms = time_it(c, reps, [&]() {
+                        return dir ? launch_fft_inv(fprec, &f, nullptr, 1, c->stream)
+                                   : launch_fft_fwd(fprec, &f, nullptr, 1, c->stream);
+                    });
+                    snprintf(line, sizeof line, "fft %s prec=%d pad=%d Nx=%d Ny=%d b=%d W=%d half=%d cm=%d: %.4f ms\n",
+                             dir ? "inv" : "fwd", fprec, pad, a->Nx, a->Ny, a->b, W, half, cm, ms);
+                    rep += line;
+                    if (ms > 0 && ms < kTuneMargin * bestms) { bestms = ms; bestcm = cm; besthalf = half; }
+                }
+            }
+            fft_set_choice(fprec, pad, dir, a->Nx, a->Ny, a->b, bestcm, besthalf);
         }
-        fft_set_cm(fprec, pad, a->Nx, a->Ny, a->b, bestcm);
     }
     g_report = rep;
     return MLFFT_OK;
@@ -149,19 +157,22 @@ mlfft_status mlfft_tune_report(mlfft_ctx ctx, int array_id, char* buf, size_t n)
         gemm_get_shape(prec, gemm_bp(prec, a->b), &w, &nt, &m3);
         snprintf(line, sizeof line, "gemm %d %d %d %d %d\n", prec, gemm_bp(prec, a->b), w, nt, m3);
         s += line;
-        for (int pad : {1, 0}) {
-            snprintf(line, sizeof line, "fftcm %d %d %d %d %d %d\n", prec, pad, a->Nx, a->Ny, a->b,
-                     fft_get_cm(prec, pad, a->Nx, a->Ny, a->b));
-            s += line;
-        }
+        for (int pad : {1, 0})
+            for (int dir : {0, 1}) {
+                int cm, half;
+                fft_get_choice(prec, pad, dir, a->Nx, a->Ny, a->b, &cm, &half);
+                snprintf(line, sizeof line, "fftshape %d %d %d %d %d %d %d %d\n", prec, pad, dir, a->Nx, a->Ny, a->b,
+                         cm, half);
+                s += line;
+            }
     }
     s += g_report;
     snprintf(buf, n, "%s", s.c_str());
     return MLFFT_OK;
 }
 
-// Apply choices in the format of mlfft_tune_report ("gemm prec bp waves nt" and
-// "fftcm prec pad Nx Ny b cm" lines; other lines are ignored).
+// Apply choices in the format of mlfft_tune_report ("gemm", "gemmpc", "gemmpcwg",
+// "fftshape" and the older "fftcm" lines; other lines are ignored).
 mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text) {
     if (!ctx || !text) return MLFFT_E_ARG;
     Ctx* c = ctx;
@@ -169,7 +180,7 @@ mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text) {
     while (*p) {
         const char* e = strchr(p, '\n');
         std::string ln(p, e ? (size_t)(e - p) : strlen(p));
-        int a1, a2, a3, a4, a5, a6;
+        int a1, a2, a3, a4, a5, a6, a7, a8;
         if (sscanf(ln.c_str(), "gemm %d %d %d %d %d", &a1, &a2, &a3, &a4, &a5) == 5) {
             const bool ok = a1 >= 0 && a1 <= 2 && a2 >= 8 && a2 <= 256 && a2 % 8 == 0 && (a3 == 4 || a3 == 8) &&
                             (a4 == 16 || a4 == 32 || a4 == 64) &&
@@ -190,10 +201,16 @@ mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text) {
         } else if (sscanf(ln.c_str(), "gemmpcwg %d", &a1) == 1) {
             if (a1 < 1 || a1 > (1 << 20)) return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
             gemm_set_pc_wg_target(a1);
+        } else if (sscanf(ln.c_str(), "fftshape %d %d %d %d %d %d %d %d", &a1, &a2, &a3, &a4, &a5, &a6, &a7, &a8) == 8) {
+            if (a1 < 0 || a1 > 1 || a2 < 0 || a2 > 1 || a3 < 0 || a3 > 1 || a4 < 1 || a5 < 1 || a6 < 1 ||
+                a7 < 0 || a7 > 64 || a8 < -1 || a8 > 1 || (a8 == 1 && !a2))
+                return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
+            fft_set_choice(a1, a2, a3, a4, a5, a6, a7, a8);
         } else if (sscanf(ln.c_str(), "fftcm %d %d %d %d %d %d", &a1, &a2, &a3, &a4, &a5, &a6) == 6) {
+            // both directions, default tile kind
             if (a1 < 0 || a1 > 1 || a2 < 0 || a2 > 1 || a6 < 0 || a6 > 64)
                 return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
-            fft_set_cm(a1, a2, a3, a4, a5, a6);
+            for (int dir : {0, 1}) fft_set_choice(a1, a2, dir, a3, a4, a5, a6, -1);
         }
         if (!e) break;
         p = e + 1;

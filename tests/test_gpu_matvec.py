@@ -186,7 +186,7 @@ def test_autotuned_shapes_keep_parity(ctx):
     for prec in (0, 1):
         abi.mlfft_autotune(ctx.h, 51, W, prec, 1)
     rep = abi.mlfft_tune_report(ctx.h, 51)
-    assert "gemm 1 64" in rep and "fftcm 1 1 10 10 64" in rep
+    assert "gemm 1 64" in rep and "fftshape 1 1 0 10 10 64" in rep and "fftshape 1 1 1 10 10 64" in rep
     X = synth.random_vectors(Nx * Ny * b, W, seed=8)
     ref = tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)
     for prec in ("fp64", "fp32"):
@@ -195,6 +195,41 @@ def test_autotuned_shapes_keep_parity(ctx):
     R = synth.random_vectors(Nx * Ny * b, W, seed=9)
     z = ctx.precond_apply(51, to_dev(R, DT["fp32"]), kind=1, prec="fp32")
     assert relerr(to_host(z), opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)) <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("Nx,Ny,b,W", [(30, 30, 13, 3), (7, 5, 24, 5), (1, 9, 40, 4), (16, 12, 8, 6), (17, 4, 6, 3)])
+def test_fft_tile_kinds_and_chunks_keep_parity(ctx, prec, Nx, Ny, b, W):
+    """Every tile kind (one-pass, half-height) and m-chunk of the padded transforms, forced per
+    direction through tuning lines, against the oracle: the product and its fused epilogue
+    (alpha Z x + beta v, the true residual's form).  Ragged b leaves a partial last m-chunk;
+    Nx = 1 and the prime 17 (one-pass only) are included."""
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=5)
+    ctx.set_blocks(52, blocks)
+    X = synth.random_vectors(Nx * Ny * b, W, seed=6)
+    Vv = synth.random_vectors(Nx * Ny * b, W, seed=7)
+    ref = tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)
+    p = 0 if prec == "fp64" else 1
+    Xd, Vd = to_dev(X, DT[prec]), to_dev(Vv, DT[prec])
+    try:
+        for half in (0, 1):
+            for cm in (1, 2, 4, 8, 16, 32):
+                abi.mlfft_tune_import(ctx.h, "".join(f"fftshape {p} 1 {d} {Nx} {Ny} {b} {cm} {half}\n" for d in (0, 1)))
+                assert relerr(to_host(ctx.matvec(52, Xd, prec=prec)), ref) <= TOL[prec], (half, cm)
+                y = torch.empty_like(Xd)
+                ctx.sync_stream()
+                abi.mlfft_matvec_axpby(ctx.h, 52, W, -1.0, Xd.data_ptr(), 1.0, Vd.data_ptr(), y.data_ptr(), p)
+                assert relerr(to_host(y), Vv - ref) <= TOL[prec], (half, cm)
+    finally:
+        abi.mlfft_tune_import(ctx.h, "".join(f"fftshape {p} 1 {d} {Nx} {Ny} {b} 0 -1\n" for d in (0, 1)))
+
+
+def test_fft_shape_lines_are_validated(ctx):
+    for bad in ("fftshape 2 1 0 4 4 8 4 0", "fftshape 0 0 0 4 4 8 4 1", "fftshape 0 1 2 4 4 8 4 0",
+                "fftshape 0 1 0 4 4 8 65 0", "fftshape 0 1 0 4 4 8 4 2"):
+        with pytest.raises(abi.MlfftError) as e:
+            abi.mlfft_tune_import(ctx.h, bad + "\n")
+        assert e.value.status == abi.MLFFT_E_ARG
 
 
 @pytest.mark.parametrize("b", [24, 120, 200, 13, 40])
