@@ -167,12 +167,12 @@ def traffic_record(group, prec, workload, tune_text):
 
 
 def gemm_form_three_products(tune_text, prec, b):
-    """True if the tuned block-product shape for (prec, padded b) is a three-product form (m3 = 1 or 2)."""
+    """True if the tuned block-product shape for (prec, padded b) is a three-product form (m3 = 1, 2 or 4)."""
     for line in (tune_text or "").splitlines():
         f = line.split()
         if len(f) == 6 and f[0] == "gemm" and int(f[1]) == prec and int(f[2]) >= b:
-            return int(f[5]) in (1, 2)
-    return prec in (0, 1)          # untuned: the default shapes of FP64 / FP32 are three-product forms
+            return int(f[5]) in (1, 2, 4)
+    return prec == 1 and b >= 97   # untuned: the FP32 default from b = 97 is form 4
 
 
 def cpu_baseline(blocks, V, cfg, tol, n_cols):

@@ -22,7 +22,9 @@ void gemm_set_pc_wg_target(int n) { if (n >= 1 && n <= (1 << 20)) g_pc_wg_target
 
 static GemmShape default_shape(int prec, int bp) {
     if (prec == P64) return GemmShape{8, bp > 128 ? 16 : 32, 0};
-    if (prec == P32) return GemmShape{8, bp > 160 ? 32 : 64, 0};
+    // FP32 from b = 97 (seven 16-row slices): the flat three-product kernel with
+    // direct-to-LDS tiles (odd b falls back to the register-staged flat kernel)
+    if (prec == P32) return bp >= 104 ? GemmShape{8, 16, 4} : GemmShape{8, bp > 160 ? 32 : 64, 0};
     // BF16: the eight-wave flat kernel (32-column tiles) for b >= 97, the four-wave one
     // (16-column tiles) for b >= 33, see launch_shape
     return GemmShape{8, 32, 2};
@@ -34,7 +36,7 @@ GemmShape gemm_shape(int prec, int bp, int tag) {
         // the FP32 preconditioner product takes the tile shape tuned for the MLFFT
         // product of the same b when that is an eight-wave flat shape
         const GemmShape& o = g_shape_override[prec][bp / 8];
-        if (prec == P32 && o.m3 == 2 && o.waves == 8) return o;
+        if (prec == P32 && (o.m3 == 2 || o.m3 == 4) && o.waves == 8) return o;
         // the bf16 preconditioner product: one frequency per workgroup (each X tile staged
         // once for all row slices of its frequency) for padded b in 112..208, unless a shape
         // was imported for it (below 112 the flat kernels are faster, beyond 208 the
@@ -50,11 +52,13 @@ GemmShape gemm_shape(int prec, int bp, int tag) {
 
 void gemm_set_shape(int prec, int bp, int waves, int nt, int m3) {
     if (prec < 0 || prec > 2 || bp < 8 || bp > 256 || bp % 8) return;
+    if (waves == 0) { g_shape_override[prec][bp / 8] = GemmShape{0, 0, 0}; return; }    // back to the default
     // BF16 has the eight-row kernel (m3 = 0) and the flat kernel with eight waves and
     // 32-column tiles or four waves and 16-column tiles
     if (prec == PBF16 && (m3 == 1 || (m3 == 2 && !((waves == 8 && nt == 32) || (waves == 4 && nt == 16))) ||
                           (m3 == 3 && !(waves == 8 && nt == 32)) || m3 > 3)) return;
-    if (prec != PBF16 && m3 > 2) return;
+    // FP32 form 4: the flat kernel with direct-to-LDS tiles, eight waves, 16-column tiles
+    if (prec != PBF16 && m3 > 2 && !(prec == P32 && m3 == 4 && waves == 8 && nt == 16)) return;
     g_shape_override[prec][bp / 8] = GemmShape{waves, nt, m3};
 }
 
@@ -81,7 +85,7 @@ static int bp_max_of(int prec, const GemmTask* tasks, int ntasks) {
 // K * ceil(b/16) (frequency, slice) items to eight waves per workgroup
 static int task_blocks(const GemmTask& t, const GemmShape& sh) {
     if (sh.m3 == 3) return t.K * t.mgroups;
-    if (sh.m3 == 2) return (t.K * ((t.b + 15) / 16) + sh.waves - 1) / sh.waves;
+    if (sh.m3 == 2 || sh.m3 == 4) return (t.K * ((t.b + 15) / 16) + sh.waves - 1) / sh.waves;
     return ((t.K + kXcd - 1) / kXcd) * kXcd * t.mgroups;
 }
 
@@ -91,7 +95,13 @@ static int task_blocks(const GemmTask& t, const GemmShape& sh) {
 // workgroup per row group is used.
 static GemmShape launch_shape(int prec, const GemmTask* tasks, int ntasks, int tag, int bpm) {
     GemmShape sh = gemm_shape(prec, bpm, tag);
-    if (sh.m3 == 2) {
+    if (sh.m3 == 4) {
+        // direct-to-LDS tiles move two complex values per lane: every b even
+        bool even = true;
+        for (int i = 0; i < ntasks; ++i) even = even && (tasks[i].b & 1) == 0;
+        if (!even) sh = GemmShape{8, 16, 2};
+    }
+    if (sh.m3 == 2 || sh.m3 == 4) {
         int bmin = 1 << 30;
         for (int i = 0; i < ntasks; ++i) bmin = std::min(bmin, tasks[i].b);
         // waves - 1 consecutive slices must not reach a third frequency

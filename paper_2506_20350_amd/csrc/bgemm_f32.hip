@@ -46,10 +46,25 @@ static hipError_t launch_3m_flat_cfg(const GemmTask& t0, const GemmTask* td, int
     return hipGetLastError();
 }
 
+template<int BP, int TAG>
+static hipError_t launch_direct_cfg(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
+    if constexpr (BP >= 104) {
+        const size_t lds = (size_t)4 * 16 * f32_direct_rs(BP) * sizeof(float2);
+        auto k = bgemm_f32_3m_direct_kernel<BP, TAG>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(512), lds, s, t0, td, n);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;     // the flat kernels need ceil(b / 16) >= 7
+    }
+}
+
 template<int BP>
 static hipError_t launch_f32(GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
                              hipStream_t s) {
     constexpr int B16 = (BP + 15) / 16 * 16;
+    if (sh.m3 == 4)       // flat, direct-to-LDS tiles (even b)
+        return tag ? launch_direct_cfg<BP, 1>(t0, td, n, grid, s) : launch_direct_cfg<BP, 0>(t0, td, n, grid, s);
     // the flat kernels slice rows at run time and only need the reduction
     // length padded to a multiple of 8 (b = 200: 50 reduction steps, not 52)
     if (tag)      // preconditioner: fixed shape (flat unless some b is below 97)

@@ -445,6 +445,155 @@ __global__ void __launch_bounds__(64 * WAVES, 2) bgemm_f32_3m_flat_kernel(GemmTa
     }
 }
 
+// The FP32 three-product flat kernel with the X tiles loaded straight into LDS
+// (global_load_lds_dwordx4, gfx950): no staging registers and no LDS stores, so
+// the next tile's loads run under the current tile's products with one barrier per
+// tile.  Eight waves, 16-column tiles, double-buffered, even b only (a lane moves
+// two consecutive complex values, which must not cross a column).
+//  - LDS rows hold RS = BP + 2 complex values; RS / 2 is odd, so the 16-byte B
+//    fragment reads of eight consecutive lanes fall on distinct banks.
+//  - The reduction runs in pair steps: sub-step e of pair step s2 takes n = 8 s2 +
+//    2 q + e in lane group q, so one 16-byte read feeds two sub-steps (six MFMAs).
+//  - A lane's 16-byte slots in a tile are fixed, so their source offsets are
+//    computed once; pairs past b / 2 of a row are never loaded and stay zero.
+//  - The products of a tile leave after the barrier that ends the tile, and the
+//    wait before that barrier (one counter covers loads and stores) then covers
+//    stores issued a whole tile earlier.
+// LDS row length (complex values) of the direct-tile kernel
+__host__ __device__ constexpr int f32_direct_rs(int bp) { return bp + 2; }
+
+template<int BP, int TAG>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) bgemm_f32_3m_direct_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
+    constexpr int WAVES = 8, NTH = 512, NT = 16;
+    constexpr int RS = f32_direct_rs(BP);               // complex values per LDS row
+    constexpr int HP = RS / 2;                          // 16-byte pairs per row
+    constexpr int TILE = NT * RS;                       // complex values per (buffer, panel)
+    constexpr int CHUNKS = (NT * HP + 63) / 64;         // 64-pair chunks per tile
+    constexpr int CPW = (CHUNKS + WAVES - 1) / WAVES;   // chunks per wave and tile
+    static_assert(HP % 2 == 1, "row pairs must be odd");
+    extern __shared__ unsigned char smem_raw[];
+    float2* xs = reinterpret_cast<float2*>(smem_raw);   // [buffer][panel][NT][RS]
+    const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
+    const int b = t.b, W = t.W, K = t.K;
+    const int ns = (b + 15) >> 4;
+    const int total = K * ns;
+    const int nwg = (total + WAVES - 1) / WAVES;
+    const int local = blockIdx.x - t.block_begin;
+    const int per = nwg >> 3;
+    const int grp = local < per * 8 ? (local & 7) * per + (local >> 3) : local;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gs0 = grp * WAVES;
+    const int kA = gs0 / ns;
+    const int kB = min((gs0 + WAVES - 1) / ns, K - 1);
+    const int npan = kB != kA ? 2 : 1;
+    const int gs = gs0 + wave;
+    const bool active = gs < total;
+    const int kw = active ? gs / ns : kA;
+    const int m_base = (gs - kw * ns) * 16;
+    const int pan = kw - kA;
+    const bool full16 = m_base + 16 <= b;
+    const int j = lane & 15, q = lane >> 4;
+    // stationary fragments: Re G, Im G and Re G + Im G (the third product's operand)
+    float ar[BP / 4], ai[BP / 4], as[BP / 4];
+    {
+        const float2* __restrict__ Gk = static_cast<const float2*>(t.G) + (size_t)kw * t.gstride;
+        const int m = m_base + j;
+#pragma unroll
+        for (int s2 = 0; s2 < BP / 8; ++s2) {
+            const int n = 8 * s2 + 2 * q;
+            mlfft_f4v g = mlfft_f4v{0.f, 0.f, 0.f, 0.f};
+            if (active && m < b && n < b) g = *(const MLFFT_GLOBAL mlfft_f4v*)(Gk + (size_t)m * b + n);
+            ar[2 * s2] = g[0];
+            ai[2 * s2] = g[1];
+            ar[2 * s2 + 1] = g[2];
+            ai[2 * s2 + 1] = g[3];
+        }
+#pragma unroll
+        for (int s = 0; s < BP / 4; ++s) as[s] = ar[s] + ai[s];
+    }
+    // both buffers and panels zeroed once: the pairs past b / 2 of every row are padding
+    {
+        mlfft_f4v* z = reinterpret_cast<mlfft_f4v*>(xs);
+        for (int e = threadIdx.x; e < 2 * TILE; e += NTH) z[e] = mlfft_f4v{0.f, 0.f, 0.f, 0.f};
+    }
+    // source offsets (complex values from the tile's first column) of this lane's slots
+    int soff[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const int ch = wave + WAVES * c;
+        const int slot = ch * 64 + lane;
+        const int row = slot / HP, p = slot - row * HP;
+        soff[c] = (ch < CHUNKS && row < NT && 2 * p < b) ? row * b + 2 * p : -1;
+    }
+    const float2* __restrict__ Xa = static_cast<const float2*>(t.X) + (size_t)kA * W * b;
+    const float2* __restrict__ Xb = static_cast<const float2*>(t.X) + (size_t)kB * W * b;
+    float2* __restrict__ Yk = static_cast<float2*>(t.Y) + (size_t)kw * W * b;
+    auto load_tile = [&](int w0, int buf) {
+        const int lim = min(NT, W - w0) * b;             // the columns of a last, partial tile
+#pragma unroll
+        for (int pn = 0; pn < 2; ++pn) {
+            if (pn >= npan) break;
+            const float2* __restrict__ src = (pn ? Xb : Xa) + (size_t)w0 * b;
+            float2* dst = xs + (buf * 2 + pn) * TILE;
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+                const int ch = wave + WAVES * c;
+                if (ch < CHUNKS && soff[c] >= 0 && soff[c] < lim)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void*)(src + soff[c]),
+                        (__attribute__((address_space(3))) void*)(dst + ch * 128), 16, 0, 0);
+            }
+        }
+    };
+    float2 o[4];
+    auto store = [&](int w0) {
+        const int w = w0 + j;
+        if (w < W) {
+            const int m0 = m_base + 4 * q;
+            float2* dst = Yk + (size_t)w * b + m0;
+            if (full16) {
+                gstore2(dst, o[0], o[1]);
+                gstore2(dst + 2, o[2], o[3]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (m0 + r < b) gstore(dst + r, o[r]);
+            }
+        }
+    };
+    __syncthreads();                                     // zeroing done before any tile lands
+    load_tile(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int w0 = 0, it = 0; w0 < W; w0 += NT, ++it) {
+        if (w0 + NT < W) load_tile(w0 + NT, (it + 1) & 1);
+        if (active) {
+            const float2* __restrict__ xp = xs + ((it & 1) * 2 + pan) * TILE + j * RS + 2 * q;
+            floatx4 t1 = floatx4{0, 0, 0, 0}, t2 = floatx4{0, 0, 0, 0}, t3 = floatx4{0, 0, 0, 0};
+            // B fragments read two pair steps ahead of their products
+            mlfft_f4v u0 = *reinterpret_cast<const mlfft_f4v*>(xp);
+            mlfft_f4v u1 = *reinterpret_cast<const mlfft_f4v*>(xp + 8);
+#pragma unroll
+            for (int s2 = 0; s2 < BP / 8; ++s2) {
+                const mlfft_f4v u = u0;
+                u0 = u1;
+                if (s2 + 2 < BP / 8) u1 = *reinterpret_cast<const mlfft_f4v*>(xp + 8 * (s2 + 2));
+                t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[2 * s2], u[0], t1, 0, 0, 0);
+                t2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[2 * s2], u[1], t2, 0, 0, 0);
+                t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(as[2 * s2], u[0] + u[1], t3, 0, 0, 0);
+                t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[2 * s2 + 1], u[2], t1, 0, 0, 0);
+                t2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[2 * s2 + 1], u[3], t2, 0, 0, 0);
+                t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(as[2 * s2 + 1], u[2] + u[3], t3, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[r] = make_float2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]);
+        }
+        __builtin_amdgcn_s_waitcnt(0);                   // the next tile has landed
+        __syncthreads();
+        if (active) store(w0);
+    }
+}
+
 // FP64 three-product form with the flat assignment, four waves per workgroup.
 // Same scheme as the FP32 kernel above with v_mfma_f64_16x16x4f64, whose
 // accumulator holds row 4r + l/16 of column l%16 in register r.  Four waves of

@@ -160,10 +160,12 @@ def test_full_size_30x30_b120_sampled_columns(ctx, prec):
     assert np.all(np.isfinite(y))
 
 
-@pytest.mark.parametrize("b", [8, 24, 120, 200, 13])
-@pytest.mark.parametrize("shape", ["4 32 1", "8 64 1", "4 64 0", "8 32 0", "8 32 2", "8 16 2", "4 16 2"])
+@pytest.mark.parametrize("b", [8, 24, 120, 200, 13, 97, 112, 250])
+@pytest.mark.parametrize("shape", ["4 32 1", "8 64 1", "4 64 0", "8 32 0", "8 32 2", "8 16 2", "4 16 2", "8 16 4"])
 def test_block_product_shapes_match_oracle(ctx, b, shape):
-    """Every launch shape the autotuner can pick, including the three-product FP32 form."""
+    """Every launch shape the autotuner can pick, including the three-product FP32 forms (form 4,
+    the flat kernel with direct-to-LDS tiles, runs for even b with at least seven 16-row slices:
+    112, 120, 200, 250; the others fall back).  W = 70 leaves a partial last tile."""
     Nx, Ny, W = 3, 4, 70
     blocks = synth.random_blocks(Nx, Ny, b, seed=b)
     ctx.set_blocks(50, blocks)
@@ -175,8 +177,55 @@ def test_block_product_shapes_match_oracle(ctx, b, shape):
         y = ctx.matvec(50, to_dev(X, torch.complex64), prec="fp32")
         assert relerr(to_host(y), tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)) <= TOL["fp32"]
     finally:
-        default_nt = 32 if bp > 160 else 64
-        abi.mlfft_tune_import(ctx.h, f"gemm 1 {bp} 8 {default_nt} 0\n")
+        abi.mlfft_tune_import(ctx.h, f"gemm 1 {bp} 0 0 0\n")
+
+
+@pytest.mark.parametrize("b", [112, 200, 250])
+def test_direct_tile_product_serves_the_fp32_preconditioner(ctx, b):
+    """With form 4 tuned for the MLFFT product, the FP32 preconditioner product (900 frequencies
+    of a 30x30 torus here, a few columns) runs the same kernel; it matches the oracle, and the
+    flat kernel with register-staged tiles to FP32 rounding (the two sum in different orders)."""
+    Nx, Ny, W = 30, 30, 19
+    blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=b)
+    ctx.set_blocks(55, blocks)
+    bp = (b + 7) // 8 * 8
+    R = synth.random_vectors(Nx * Ny * b, W, seed=5)
+    Rd = to_dev(R, torch.complex64)
+    z = {}
+    try:
+        for form in ("8 16 2", "8 16 4"):
+            abi.mlfft_tune_import(ctx.h, f"gemm 1 {bp} {form}\n")
+            z[form] = to_host(ctx.precond_apply(55, Rd, kind=1, prec="fp32"))
+    finally:
+        abi.mlfft_tune_import(ctx.h, f"gemm 1 {bp} 0 0 0\n")
+    assert relerr(z["8 16 4"], opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)) <= 1e-4
+    assert relerr(z["8 16 4"], z["8 16 2"]) <= 1e-5
+
+
+def test_direct_tile_product_in_a_batch_with_an_odd_b(ctx):
+    """Arrays with b = 114 and b = 119 pad to the same reduction length (120) and share a launch:
+    form 4 needs every b even, so the launch falls back to the flat kernel; alone, the b = 114
+    array runs form 4.  Both products match the oracle."""
+    specs = [(3, 3, 114, 0), (2, 4, 119, 1)]
+    abi.mlfft_tune_import(ctx.h, "gemm 1 120 8 16 4\n")
+    try:
+        ids, Vs, refs = [], [], []
+        for i, (Nx, Ny, b, seed) in enumerate(specs):
+            blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=seed)
+            ctx.set_blocks(62 + i, blocks)
+            V = synth.port_rhs(Nx, Ny, b)
+            ids.append(62 + i)
+            Vs.append(to_dev(V))
+            refs.append(direct.lu_solve(tp.dense_Z(blocks), V))
+            X = synth.random_vectors(Nx * Ny * b, 20, seed=3)
+            y = ctx.matvec(62 + i, to_dev(X, torch.complex64), prec="fp32")
+            assert relerr(to_host(y), tp.matvec_fft(blocks, X, 2 * Ny, 2 * Nx)) <= TOL["fp32"]
+        Is, info = ctx.solve_batch(ids, Vs, tol=1e-10, inner_prec="fp32", precond=1)
+        assert info["status"] == abi.MLFFT_OK and np.all(info["relres"] <= 1e-10)
+        for I, ref in zip(Is, refs):
+            assert relerr(to_host(I), ref) <= 1e-8
+    finally:
+        abi.mlfft_tune_import(ctx.h, "gemm 1 120 0 0 0\n")
 
 
 def test_autotuned_shapes_keep_parity(ctx):
