@@ -172,7 +172,7 @@ def gemm_form_three_products(tune_text, prec, b):
         f = line.split()
         if len(f) == 6 and f[0] == "gemm" and int(f[1]) == prec and int(f[2]) >= b:
             return int(f[5]) in (1, 2, 4)
-    return prec == 1 and b >= 97   # untuned: the FP32 default from b = 97 is form 4
+    return (prec == 1 and b >= 97) or (prec == 0 and b >= 33)   # untuned defaults: form 4
 
 
 def cpu_baseline(blocks, V, cfg, tol, n_cols):

@@ -445,9 +445,10 @@ mlfft_status mlfft_tune_report(mlfft_ctx ctx, int array_id, char* buf, size_t n)
  * "gemm prec bp waves nt form" (form 0 four products, 1 three products, 2 three
  * products with the flat assignment, which takes prec 1 with waves 8 and nt 32
  * or 16, prec 1 with waves 4 and nt 16, or prec 0 with waves 4 and nt 16; form 4,
- * prec 1 with waves 8 and nt 16 only: the flat assignment with X tiles loaded
- * straight into LDS, for even b, else the launch falls back to form 2; "gemm prec
- * bp 0 0 0" restores the default shape) and
+ * prec 1 with waves 8 and nt 16 or prec 0 with waves 4 and nt 16: the flat
+ * assignment with X tiles loaded straight into LDS, in FP32 for even b only, else
+ * the launch falls back to form 2; "gemm prec bp 0 0 0" restores the default
+ * shape) and
  * "fftshape prec pad dir Nx Ny b cm half" (dir 0 forward, 1 inverse; cm the
  * m-chunk, 0 for the default rule; half 1 for the half-height tile of a padded
  * transform, 0 for the one-pass tile, -1 for the default), the older

@@ -21,7 +21,9 @@ static int g_pc_wg_target = 512;               // workgroups a launch of the fre
 void gemm_set_pc_wg_target(int n) { if (n >= 1 && n <= (1 << 20)) g_pc_wg_target = n; }
 
 static GemmShape default_shape(int prec, int bp) {
-    if (prec == P64) return GemmShape{8, bp > 128 ? 16 : 32, 0};
+    // FP64 from b = 33 (three 16-row slices): the flat three-product kernel with
+    // direct-to-LDS half-reduction tiles
+    if (prec == P64) return bp >= 40 ? GemmShape{4, 16, 4} : GemmShape{8, bp > 128 ? 16 : 32, 0};
     // FP32 from b = 97 (seven 16-row slices): the flat three-product kernel with
     // direct-to-LDS tiles (odd b falls back to the register-staged flat kernel)
     if (prec == P32) return bp >= 104 ? GemmShape{8, 16, 4} : GemmShape{8, bp > 160 ? 32 : 64, 0};
@@ -57,8 +59,9 @@ void gemm_set_shape(int prec, int bp, int waves, int nt, int m3) {
     // 32-column tiles or four waves and 16-column tiles
     if (prec == PBF16 && (m3 == 1 || (m3 == 2 && !((waves == 8 && nt == 32) || (waves == 4 && nt == 16))) ||
                           (m3 == 3 && !(waves == 8 && nt == 32)) || m3 > 3)) return;
-    // FP32 form 4: the flat kernel with direct-to-LDS tiles, eight waves, 16-column tiles
-    if (prec != PBF16 && m3 > 2 && !(prec == P32 && m3 == 4 && waves == 8 && nt == 16)) return;
+    // form 4: the flat kernel with direct-to-LDS tiles, 16-column tiles, eight waves (FP32)
+    // or four (FP64)
+    if (prec != PBF16 && m3 > 2 && !(m3 == 4 && nt == 16 && waves == (prec == P32 ? 8 : 4))) return;
     g_shape_override[prec][bp / 8] = GemmShape{waves, nt, m3};
 }
 
@@ -96,10 +99,13 @@ static int task_blocks(const GemmTask& t, const GemmShape& sh) {
 static GemmShape launch_shape(int prec, const GemmTask* tasks, int ntasks, int tag, int bpm) {
     GemmShape sh = gemm_shape(prec, bpm, tag);
     if (sh.m3 == 4) {
-        // direct-to-LDS tiles move two complex values per lane: every b even
-        bool even = true;
-        for (int i = 0; i < ntasks; ++i) even = even && (tasks[i].b & 1) == 0;
-        if (!even) sh = GemmShape{8, 16, 2};
+        // the waves' consecutive slices span at most two frequencies (see below); FP32
+        // direct-to-LDS tiles move two complex values per lane: every b even.  Otherwise
+        // the flat kernel with register-staged tiles.
+        bool ok = true;
+        for (int i = 0; i < ntasks; ++i)
+            ok = ok && (tasks[i].b + 15) / 16 >= sh.waves - 1 && (prec != P32 || (tasks[i].b & 1) == 0);
+        if (!ok) sh = prec == P32 ? GemmShape{8, 16, 2} : GemmShape{4, 16, 2};
     }
     if (sh.m3 == 2 || sh.m3 == 4) {
         int bmin = 1 << 30;

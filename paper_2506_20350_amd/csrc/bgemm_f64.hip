@@ -37,9 +37,24 @@ static hipError_t launch_real(GemmShape sh, int tag, const GemmTask& t0, const G
                : launch_real_cfg<T, BP, NS, 8, 0>(t0, td, n, grid, s);
 }
 
+template<int BP, int TAG>
+static hipError_t launch_direct_cfg(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
+    if constexpr (BP >= 40) {
+        const size_t lds = (size_t)4 * 16 * f64_direct_rs(BP) * sizeof(double2);
+        auto k = bgemm_f64_3m_direct_kernel<BP, TAG>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, s, t0, td, n);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;     // four waves of one slice each need ceil(b / 16) >= 3
+    }
+}
+
 template<int BP>
 static hipError_t launch_f64(GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
                              hipStream_t s) {
+    if (sh.m3 == 4)       // flat, direct-to-LDS half-reduction tiles
+        return tag ? launch_direct_cfg<BP, 1>(t0, td, n, grid, s) : launch_direct_cfg<BP, 0>(t0, td, n, grid, s);
     // the flat kernel slices rows at run time and only needs the reduction length
     // padded to a multiple of 8
     if (sh.m3 == 2)

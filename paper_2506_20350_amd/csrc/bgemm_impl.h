@@ -566,7 +566,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     for (int w0 = 0, it = 0; w0 < W; w0 += NT, ++it) {
-        if (w0 + NT < W) load_tile(w0 + NT, (it + 1) & 1);
+        // the next tile's loads are issued after the first pair step, so the MFMA pipes
+        // already have work while the wave issues them
+        auto next = [&]() { if (w0 + NT < W) load_tile(w0 + NT, (it + 1) & 1); };
+        if (!active) next();
         if (active) {
             const float2* __restrict__ xp = xs + ((it & 1) * 2 + pan) * TILE + j * RS + 2 * q;
             floatx4 t1 = floatx4{0, 0, 0, 0}, t2 = floatx4{0, 0, 0, 0}, t3 = floatx4{0, 0, 0, 0};
@@ -578,6 +581,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
                 const mlfft_f4v u = u0;
                 u0 = u1;
                 if (s2 + 2 < BP / 8) u1 = *reinterpret_cast<const mlfft_f4v*>(xp + 8 * (s2 + 2));
+                if (s2 == 1) next();
                 t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[2 * s2], u[0], t1, 0, 0, 0);
                 t2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[2 * s2], u[1], t2, 0, 0, 0);
                 t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(as[2 * s2], u[0] + u[1], t3, 0, 0, 0);
@@ -727,6 +731,158 @@ __global__ void __launch_bounds__(256) bgemm_f64_3m_flat_kernel(GemmTask t0, con
         }
     }
     if (active && wdone >= 0) store();
+}
+
+// LDS row length (complex values) of a half-reduction tile of the FP64 direct-tile
+// kernel: odd, so the 16-byte B-fragment reads of eight lanes fall on distinct banks
+__host__ __device__ constexpr int f64_direct_rs(int bp) { return bp / 2 + 1; }
+
+// The FP64 three-product flat kernel with X tiles loaded straight into LDS
+// (global_load_lds_dwordx4, one complex value per lane), four waves (one per SIMD,
+// so that Gr and Gi of a 16-row slice, 2 b' doubles per lane, stay in registers)
+// of one 16-row slice each.  A 16-column tile of two panels would not fit in LDS
+// twice, so each tile is split into the two halves of the reduction, which take
+// turns in the two buffers: the loads of one half run under the products of the
+// other, with one wait and one barrier per half.  The products of a tile leave
+// after the barrier that ends it (covered by the next wait, a half-tile later).
+template<int BP, int TAG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) bgemm_f64_3m_direct_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
+    constexpr int WAVES = 4, NT = 16;
+    constexpr int HB = BP / 2;                          // reduction length of a half
+    constexpr int RS = f64_direct_rs(BP);               // complex values per LDS row
+    constexpr int TILE = NT * RS;                       // complex values per (buffer, panel)
+    constexpr int CHUNKS = (TILE + 63) / 64;            // 64-value chunks per half tile
+    constexpr int CPW = (CHUNKS + WAVES - 1) / WAVES;   // chunks per wave
+    constexpr int SH = HB / 4;                          // reduction steps per half
+    static_assert(HB % 4 == 0 && RS % 2 == 1, "half tiles of whole steps, odd rows");
+    extern __shared__ unsigned char smem_raw[];
+    double2* xs = reinterpret_cast<double2*>(smem_raw);  // [buffer = half][panel][NT][RS]
+    const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
+    const int b = t.b, W = t.W, K = t.K;
+    const int ns = (b + 15) >> 4;
+    const int total = K * ns;
+    const int nwg = (total + WAVES - 1) / WAVES;
+    const int local = blockIdx.x - t.block_begin;
+    const int per = nwg >> 3;
+    const int grp = local < per * 8 ? (local & 7) * per + (local >> 3) : local;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gs0 = grp * WAVES;
+    const int kA = gs0 / ns;
+    const int kB = min((gs0 + WAVES - 1) / ns, K - 1);
+    const int npan = kB != kA ? 2 : 1;
+    const int gs = gs0 + wave;
+    const bool active = gs < total;
+    const int kw = active ? gs / ns : kA;
+    const int m_base = (gs - kw * ns) * 16;
+    const int pan = kw - kA;
+    const int j = lane & 15, q = lane >> 4;
+    double ar[BP / 4], ai[BP / 4];
+    {
+        const double2* __restrict__ Gk = static_cast<const double2*>(t.G) + (size_t)kw * t.gstride;
+        const int m = m_base + j;
+#pragma unroll
+        for (int s = 0; s < BP / 4; ++s) {
+            const int n = 4 * s + q;
+            double2 g = make_double2(0.0, 0.0);
+            if (active && m < b && n < b) g = gload(Gk + (size_t)m * b + n);
+            ar[s] = g.x;
+            ai[s] = g.y;
+        }
+    }
+    {
+        mlfft_d2v* z = reinterpret_cast<mlfft_d2v*>(xs);
+        for (int e = threadIdx.x; e < 4 * TILE; e += WAVES * 64) z[e] = mlfft_d2v{0.0, 0.0};
+    }
+    // source offsets (from the half's first value in the tile's first column) of this
+    // lane's slots, and which slots hold reduction indices below b in each half
+    const int nv0 = min(HB, b), nv1 = max(0, b - HB);
+    int soff[CPW];
+    unsigned vm0 = 0, vm1 = 0;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const int ch = wave + WAVES * c;
+        const int slot = ch * 64 + lane;
+        const int row = slot / RS, p = slot - row * RS;
+        const bool ok = ch < CHUNKS && row < NT && p < HB;
+        soff[c] = ok ? row * b + p : -1;
+        vm0 |= (ok && p < nv0 ? 1u : 0u) << c;
+        vm1 |= (ok && p < nv1 ? 1u : 0u) << c;
+    }
+    const double2* __restrict__ Xa = static_cast<const double2*>(t.X) + (size_t)kA * W * b;
+    const double2* __restrict__ Xb = static_cast<const double2*>(t.X) + (size_t)kB * W * b;
+    double2* __restrict__ Yk = static_cast<double2*>(t.Y) + (size_t)kw * W * b;
+    auto load_half = [&](int w0, int h) {
+        const int lim = min(NT, W - w0) * b;
+        const unsigned vm = h ? vm1 : vm0;
+#pragma unroll
+        for (int pn = 0; pn < 2; ++pn) {
+            if (pn >= npan) break;
+            const double2* __restrict__ src = (pn ? Xb : Xa) + (size_t)w0 * b + h * HB;
+            double2* dst = xs + (h * 2 + pn) * TILE;
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+                const int ch = wave + WAVES * c;
+                if (ch < CHUNKS && ((vm >> c) & 1u) && soff[c] < lim)
+                    __builtin_amdgcn_global_load_lds(
+                        (const void*)(src + soff[c]),
+                        (__attribute__((address_space(3))) void*)(dst + ch * 64), 16, 0, 0);
+            }
+        }
+    };
+    doublex4 t1, t2, t3;
+    // the products of one half; the other buffer's loads are issued after the first two
+    // steps, so the MFMA pipes already have work while the wave issues them
+    auto products = [&](int h, auto issue) {
+        const double2* xp = xs + (h * 2 + pan) * TILE + j * RS + q;
+#pragma unroll
+        for (int s2 = 0; s2 < SH; ++s2) {
+            const int s = (h ? SH : 0) + s2;
+            const mlfft_d2v u = *reinterpret_cast<const mlfft_d2v*>(xp + 4 * s2);
+            t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[s], u[0], t1, 0, 0, 0);
+            t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[s], u[1], t2, 0, 0, 0);
+            t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[s] + ai[s], u[0] + u[1], t3, 0, 0, 0);
+            if (s2 == (SH > 2 ? 1 : 0)) issue();
+        }
+    };
+    double2 o[4];
+    auto store = [&](int w0) {
+        const int w = w0 + j;
+        if (w < W) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m_base + 4 * r + q;
+                if (m < b) gstore(Yk + (size_t)w * b + m, o[r]);
+            }
+        }
+    };
+    __syncthreads();                                     // zeroing done before any tile lands
+    load_half(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int w0 = 0; w0 < W; w0 += NT) {
+        auto next1 = [&]() { load_half(w0, 1); };
+        auto next0 = [&]() { if (w0 + NT < W) load_half(w0 + NT, 0); };
+        if (active) {
+            t1 = doublex4{0, 0, 0, 0};
+            t2 = doublex4{0, 0, 0, 0};
+            t3 = doublex4{0, 0, 0, 0};
+            products(0, next1);
+        } else {
+            next1();
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (active) {
+            products(1, next0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[r] = make_double2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]);
+        } else {
+            next0();
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (active) store(w0);
+    }
 }
 
 // ------------------------------------------------------------------ BF16

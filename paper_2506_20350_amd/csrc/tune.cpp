@@ -74,8 +74,11 @@ mlfft_status mlfft_autotune(mlfft_ctx ctx, int array_id, int W, int prec, int re
     if (prec != PBF16) {
         for (int m3 : {0, 1, 2, 4}) for (int waves : {4, 8}) {
             if (m3 == 1 && prec != P32) continue;
-            // form 4 (FP32): the flat kernel with direct-to-LDS tiles, eight waves, 16 columns
-            if (m3 == 4 && (prec != P32 || waves != 8 || (a->b & 1) || (a->b + 15) / 16 < 7)) continue;
+            // form 4: the flat kernel with direct-to-LDS tiles, 16 columns, eight waves (FP32,
+            // even b) or four (FP64)
+            if (m3 == 4 && (prec == PBF16 || waves != (prec == P32 ? 8 : 4) || (prec == P32 && (a->b & 1)) ||
+                            (a->b + 15) / 16 < waves - 1))
+                continue;
             // the flat three-product kernels run eight or four waves (FP32, four with
             // 16-column tiles only) or four (FP64)
             if (m3 == 2 && prec == P64 && waves != 4) continue;
@@ -84,7 +87,7 @@ mlfft_status mlfft_autotune(mlfft_ctx ctx, int array_id, int W, int prec, int re
                 // nt 16 is only a shape of the flat FP32 kernel (eight waves: double-buffered
                 // tiles; four waves: single-buffered, two workgroups per CU)
                 if (ci == 2 && !((m3 == 2 || m3 == 4) && prec == P32)) continue;
-                if (m3 == 4 && ci != 2) continue;
+                if (m3 == 4 && (nt != 16 || (prec == P64 && ci == 2))) continue;
                 // four waves: only where the eight-wave flat kernel cannot run (fewer than
                 // seven 16-row slices); at larger b its tiles are re-read from HBM more
                 if (m3 == 2 && prec == P32 && waves == 4 && (nt != 16 || (a->b + 15) / 16 >= 7)) continue;
@@ -191,7 +194,8 @@ mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text) {
                             (a5 == 0 || (a5 == 1 && a1 == 1) || (a5 == 2 && a1 == 1 && a3 == 8 && a4 == 32) ||
                              (a5 == 2 && a1 == 1 && a3 == 8 && a4 == 16) || (a5 == 2 && a1 == 1 && a3 == 4 && a4 == 16) ||
                              (a5 == 2 && a1 == 0 && a3 == 4 && a4 == 16) || (a5 == 2 && a1 == 2 && a3 == 8 && a4 == 32) ||
-                             (a5 == 2 && a1 == 2 && a3 == 4 && a4 == 16) || (a5 == 4 && a1 == 1 && a3 == 8 && a4 == 16))));
+                             (a5 == 2 && a1 == 2 && a3 == 4 && a4 == 16) || (a5 == 4 && a1 == 1 && a3 == 8 && a4 == 16) ||
+                             (a5 == 4 && a1 == 0 && a3 == 4 && a4 == 16))));
             if (!ok) return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
             gemm_set_shape(a1, a2, a3, a4, a5);
         } else if (sscanf(ln.c_str(), "gemmpc %d %d %d %d %d", &a1, &a2, &a3, &a4, &a5) == 5) {

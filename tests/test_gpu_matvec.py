@@ -281,14 +281,18 @@ def test_fft_shape_lines_are_validated(ctx):
         assert e.value.status == abi.MLFFT_E_ARG
 
 
-@pytest.mark.parametrize("b", [24, 120, 200, 13, 40])
-def test_fp64_flat_three_product_matches_oracle(ctx, b):
-    """The FP64 three-product block product with the flat (frequency, slice) assignment."""
+@pytest.mark.parametrize("form", [2, 4])
+@pytest.mark.parametrize("b", [24, 120, 200, 13, 40, 33, 201, 256])
+def test_fp64_flat_three_product_matches_oracle(ctx, b, form):
+    """The FP64 three-product block product with the flat (frequency, slice) assignment: form 2
+    stages X tiles through registers, form 4 loads half-reduction tiles straight into LDS (from
+    b = 33, three slices; b = 13 and 24 fall back).  Odd b (33, 201) leaves a partial last
+    slice and unequal halves; W = 37 a partial last tile."""
     Nx, Ny, W = 3, 4, 37
     blocks = synth.random_blocks(Nx, Ny, b, seed=b + 1)
     ctx.set_blocks(52, blocks)
     bp = (b + 7) // 8 * 8
-    abi.mlfft_tune_import(ctx.h, f"gemm 0 {bp} 4 16 2\n")
+    abi.mlfft_tune_import(ctx.h, f"gemm 0 {bp} 4 16 {form}\n")
     try:
         X = synth.random_vectors(Nx * Ny * b, W, seed=5)
         y = ctx.matvec(52, to_dev(X), prec="fp64")
@@ -298,7 +302,7 @@ def test_fp64_flat_three_product_matches_oracle(ctx, b):
         z = ctx.precond_apply(52, to_dev(R), kind=1, prec="fp64")
         assert relerr(to_host(z), opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)) <= 1e-10
     finally:
-        abi.mlfft_tune_import(ctx.h, f"gemm 0 {bp} 8 {16 if bp > 128 else 32} 0\n")
+        abi.mlfft_tune_import(ctx.h, f"gemm 0 {bp} 0 0 0\n")
 
 
 def test_empty_and_overlapping_arguments(ctx):
