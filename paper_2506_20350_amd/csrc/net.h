@@ -16,8 +16,10 @@ hipError_t n_loss_grad(const float2* yhat, const float* out, const float* tgt, s
                        float* gout, double* loss, hipStream_t s);
 hipError_t n_dgrad(const float* g, const unsigned short* wt, const unsigned short* amask, float* gin, int nimg, int H,
                    int Wd, int cin, int cout, hipStream_t s);
-hipError_t n_wgrad(const float* g, const unsigned short* act, float* dw, int nimg, int H, int Wd, int cin, int cout,
-                   hipStream_t s);
+// the weight gradient sums per-chunk partials (part: n_wgrad_chunks(P, cin, cout) x cout x 9 x cin floats)
+int n_wgrad_chunks(long P, int cin, int cout);
+hipError_t n_wgrad(const float* g, const unsigned short* act, float* dw, float* part, int nimg, int H, int Wd, int cin,
+                   int cout, hipStream_t s);
 hipError_t n_adam(float* wmaster, float* m, float* v, const float* dw, unsigned short* wbf, int cin, int cout, int cinp,
                   float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t n_pack_weights(const float* wmaster, unsigned short* wbf, int cin, int cout, int cinp, int coutp,

@@ -298,59 +298,136 @@ __global__ void __launch_bounds__(256) loss_grad_kernel(const float2* __restrict
     }
 }
 
-// gin[n][p][ci] = relu'(a[n][p][ci]) * sum_{tap, co} w[co][tap][ci] g[n][p - off(tap)][co]
-// (the mask uses the layer's bf16 input activation: a > 0 exactly where relu was active)
-__global__ void __launch_bounds__(256) conv3x3_dgrad_kernel(const float* __restrict__ g, const unsigned short* __restrict__ wt,
-                                                            const unsigned short* __restrict__ amask, float* __restrict__ gin,
-                                                            int nimg, int H, int Wd, int cin, int cout) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int npix = H * Wd;
-    if (t >= (long)nimg * npix * cin) return;
-    const int ci = (int)(t % cin);
-    const long p = t / cin;
-    const int n = (int)(p / npix);
-    const int q = (int)(p - (long)n * npix);
-    const int i = q / Wd, j = q - (q / Wd) * Wd;
-    float acc = 0.f;
-    if (bf16_bits_to_f32(amask[t]) > 0.f) {
-        for (int tap = 0; tap < 9; ++tap) {
-            // output pixel (i - di + 1, j - dj + 1) read this input through tap (di, dj)
-            const int oi = i - (tap / 3) + 1, oj = j - (tap % 3) + 1;
-            if (oi < 0 || oi >= H || oj < 0 || oj >= Wd) continue;
-            const float* gp = g + ((size_t)n * npix + oi * Wd + oj) * cout;
-            const unsigned short* wp = wt + (size_t)tap * cin + ci;
-            for (int co = 0; co < cout; ++co) acc = fmaf(bf16_bits_to_f32(wp[(size_t)co * 9 * cin]), gp[co], acc);
-        }
+// ---------------------------------------------------------------- gradients on MFMA (FP32)
+
+// Pixel p of the batch, decoded as image n and position (i, j), stepped by 4.
+struct PixPos {
+    int n, i, j;
+    __device__ __forceinline__ void set(long p, int H, int Wd) {
+        const int npix = H * Wd;
+        n = (int)(p / npix);
+        const int q = (int)(p - (long)n * npix);
+        i = q / Wd;
+        j = q - i * Wd;
     }
-    gin[t] = acc;
+    __device__ __forceinline__ void advance4(int H, int Wd) {
+        j += 4;
+        while (j >= Wd) { j -= Wd; if (++i == H) { i = 0; ++n; } }
+    }
+};
+
+// Weight gradient as a GEMM over the batch's pixels, split into chunks:
+// part[c][co][tap][ci] = sum over the pixels p of chunk c of g[p][co] a[p + off(tap)][ci]
+// (v_mfma_f32_16x16x4f32: rows co, columns ci, reduction over 4 pixels per step).
+// A wave owns a 16 x 16 (co, ci) tile for all nine taps; the four waves of a
+// workgroup take consecutive ci tiles of one co tile and one pixel chunk.
+// g: FP32 [P][cout]; act: bf16 [P][cin]; cin, cout multiples of 16 (of 32 here).
+__global__ void __launch_bounds__(256) conv3x3_wgrad_mfma_kernel(const float* __restrict__ g,
+                                                                 const unsigned short* __restrict__ act,
+                                                                 float* __restrict__ part, int nimg, int H, int Wd,
+                                                                 int cin, int cout, int pch) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, k = lane >> 4;
+    const int nct = cin >> 4;
+    const int ct = blockIdx.x * 4 + wave;                  // ci tile
+    const int co0 = blockIdx.y * 16, ci0 = ct * 16;
+    const int chunk = blockIdx.z;
+    const long P = (long)nimg * H * Wd;
+    const long p0 = (long)chunk * pch;
+    const long p1 = min(P, p0 + pch);
+    if (ct >= nct) return;
+    floatx4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int npix = H * Wd;
+    PixPos pp;
+    pp.set(p0 + k, H, Wd);
+    for (long p = p0 + k; p - k < p1; p += 4) {
+        const bool in = p < p1;
+        const float av = in ? g[p * cout + co0 + col] : 0.f;
+        float bv[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ii = pp.i + t / 3 - 1, jj = pp.j + t % 3 - 1;
+            const bool ok = in && ii >= 0 && ii < H && jj >= 0 && jj < Wd;
+            bv[t] = ok ? bf16_bits_to_f32(act[((size_t)pp.n * npix + ii * Wd + jj) * cin + ci0 + col]) : 0.f;
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[t], acc[t], 0, 0, 0);
+        pp.advance4(H, Wd);
+    }
+    // lane holds rows co0 + 4k + r of column ci0 + col
+    float* dst = part + (size_t)chunk * cout * 9 * cin;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            dst[((size_t)(co0 + 4 * k + r) * 9 + t) * cin + ci0 + col] = acc[t][r];
 }
 
-// dw[co][tap][ci] = sum_{n, p} g[n][p][co] * a[n][p + off(tap)][ci]   (one thread per weight; fixed order)
-__global__ void __launch_bounds__(256) conv3x3_wgrad_kernel(const float* __restrict__ g, const unsigned short* __restrict__ act,
-                                                            float* __restrict__ dw, int nimg, int H, int Wd, int cin,
-                                                            int cout) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)cout * 9 * cin) return;
-    const int ci = (int)(t % cin);
-    const int tap = (int)((t / cin) % 9);
-    const int co = (int)(t / (9L * cin));
-    const int di = tap / 3 - 1, dj = tap % 3 - 1;
+// dw[e] = sum over the chunks of part[c][e], in chunk order
+__global__ void __launch_bounds__(256) chunk_sum_kernel(const float* __restrict__ part, float* __restrict__ dw, long n,
+                                                        int nchunk) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + e];
+    dw[e] = s;
+}
+
+// Input gradient as a GEMM: gin[p][ci] = relu'(a[p][ci]) sum_{tap, co} g[p - off(tap)][co] w[co][tap][ci]
+// (v_mfma_f32_16x16x4f32: rows = 16 pixels, columns = 16 ci, reduction over 4 co per step and
+// the nine taps).  A wave owns 16 pixels x 64 ci (four column tiles).
+__global__ void __launch_bounds__(256) conv3x3_dgrad_mfma_kernel(const float* __restrict__ g,
+                                                                 const unsigned short* __restrict__ wt,
+                                                                 const unsigned short* __restrict__ amask,
+                                                                 float* __restrict__ gin, int nimg, int H, int Wd,
+                                                                 int cin, int cout) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = lane & 15, k = lane >> 4;
+    const long P = (long)nimg * H * Wd;
     const int npix = H * Wd;
-    float acc = 0.f;
-    for (int n = 0; n < nimg; ++n) {
-        for (int i = 0; i < H; ++i) {
-            const int ii = i + di;
-            if (ii < 0 || ii >= H) continue;
-            for (int j = 0; j < Wd; ++j) {
-                const int jj = j + dj;
-                if (jj < 0 || jj >= Wd) continue;
-                const float gv = g[((size_t)n * npix + i * Wd + j) * cout + co];
-                const float av = bf16_bits_to_f32(act[((size_t)n * npix + ii * Wd + jj) * cin + ci]);
-                acc = fmaf(gv, av, acc);
+    const long pt = ((long)blockIdx.x * 4 + wave) * 16;    // first pixel of the wave's tile
+    const int c0 = blockIdx.y * 64;
+    const int ngroups = min(4, (cin - c0) >> 4);
+    if (pt >= P) return;
+    // this lane's pixel of the A operand (row) and its position
+    const long pa = pt + row;
+    PixPos pp;
+    pp.set(pa < P ? pa : P - 1, H, Wd);
+    floatx4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < 9; ++tap) {
+        // output pixel (i - di + 1, j - dj + 1) read this pixel through tap (di, dj)
+        const int oi = pp.i - tap / 3 + 1, oj = pp.j - tap % 3 + 1;
+        const bool ok = pa < P && oi >= 0 && oi < H && oj >= 0 && oj < Wd;
+        const float* __restrict__ gp = g + ((size_t)pp.n * npix + (ok ? oi * Wd + oj : 0)) * cout;
+        const unsigned short* __restrict__ wp = wt + (size_t)tap * cin;
+        for (int co = 0; co < cout; co += 4) {
+            const float av = ok ? gp[co + k] : 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q < ngroups) {
+                    const float bv = bf16_bits_to_f32(wp[(size_t)(co + k) * 9 * cin + c0 + q * 16 + row]);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[q], 0, 0, 0);
+                }
             }
         }
     }
-    dw[t] = acc;
+    // lane holds rows (pixels) pt + 4k + r of column (ci) c0 + q * 16 + row
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= ngroups) continue;
+        const int ci = c0 + q * 16 + row;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const long p = pt + 4 * k + r;
+            if (p >= P) continue;
+            const size_t e = (size_t)p * cin + ci;
+            gin[e] = bf16_bits_to_f32(amask[e]) > 0.f ? acc[q][r] : 0.f;
+        }
+    }
 }
 
 // Adam on the FP32 master weights (layout [co][ci][3][3] of one layer, unpadded),
@@ -440,15 +517,33 @@ hipError_t n_loss_grad(const float2* yhat, const float* out, const float* tgt, s
 
 hipError_t n_dgrad(const float* g, const unsigned short* wt, const unsigned short* amask, float* gin, int nimg, int H,
                    int Wd, int cin, int cout, hipStream_t s) {
-    hipLaunchKernelGGL(conv3x3_dgrad_kernel, g1((long)nimg * H * Wd * cin), dim3(256), 0, s, g, wt, amask, gin, nimg, H,
-                       Wd, cin, cout);
+    if (cin % 16 || cout % 4) return hipErrorInvalidValue;
+    const long P = (long)nimg * H * Wd;
+    dim3 grid((unsigned)((P + 63) / 64), (unsigned)((cin + 63) / 64));
+    hipLaunchKernelGGL(conv3x3_dgrad_mfma_kernel, grid, dim3(256), 0, s, g, wt, amask, gin, nimg, H, Wd, cin, cout);
     return hipGetLastError();
 }
 
-hipError_t n_wgrad(const float* g, const unsigned short* act, float* dw, int nimg, int H, int Wd, int cin, int cout,
-                   hipStream_t s) {
-    hipLaunchKernelGGL(conv3x3_wgrad_kernel, g1((long)cout * 9 * cin), dim3(256), 0, s, g, act, dw, nimg, H, Wd, cin,
-                       cout);
+int n_wgrad_chunks(long P, int cin, int cout) {
+    // enough (ci tile group, co tile, chunk) workgroups to fill the chip, chunks of at least 64 pixels
+    const long tiles = (long)((cin / 16 + 3) / 4) * (cout / 16);
+    long nc = (2048 + tiles - 1) / tiles;
+    nc = std::min(nc, std::max(1L, P / 64));
+    return (int)std::max(1L, nc);
+}
+
+hipError_t n_wgrad(const float* g, const unsigned short* act, float* dw, float* part, int nimg, int H, int Wd, int cin,
+                   int cout, hipStream_t s) {
+    if (cin % 16 || cout % 16) return hipErrorInvalidValue;
+    const long P = (long)nimg * H * Wd;
+    const int nc = n_wgrad_chunks(P, cin, cout);
+    int pch = (int)((P + nc - 1) / nc);
+    pch = (pch + 3) / 4 * 4;
+    const int nchunk = (int)((P + pch - 1) / pch);
+    dim3 grid((unsigned)((cin / 16 + 3) / 4), (unsigned)(cout / 16), (unsigned)nchunk);
+    hipLaunchKernelGGL(conv3x3_wgrad_mfma_kernel, grid, dim3(256), 0, s, g, act, part, nimg, H, Wd, cin, cout, pch);
+    const long n = (long)cout * 9 * cin;
+    hipLaunchKernelGGL(chunk_sum_kernel, g1(n), dim3(256), 0, s, part, dw, n, nchunk);
     return hipGetLastError();
 }
 

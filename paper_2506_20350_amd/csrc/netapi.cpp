@@ -29,7 +29,7 @@ struct Net {
     Buf dwp[4];                // FP32 padded gradients
     int adam_t = 0;
     // workspaces (grown on demand)
-    Buf act[4], out, yhat, scale, phase, tgt, g0, g1, loss, fb;
+    Buf act[4], out, yhat, scale, phase, tgt, g0, g1, loss, fb, wpart;
     int fb_w = 0;
 };
 
@@ -55,6 +55,10 @@ static mlfft_status ensure_ws(Ctx* c, Net& n, int W, int npix, bool train) {
         HIPCHK(n.g0.ensure(P * cmax * 4), "gradients");
         HIPCHK(n.g1.ensure(P * cmax * 4), "gradients");
         HIPCHK(n.loss.ensure((size_t)W * 8), "loss");
+        size_t pmax = 0;
+        for (int l = 0; l < 4; ++l)
+            pmax = std::max(pmax, (size_t)n_wgrad_chunks((long)P, n.cinp[l], n.coutp[l]) * n.coutp[l] * 9 * n.cinp[l]);
+        HIPCHK(n.wpart.ensure(pmax * 4), "gradient partial sums");
     }
     return MLFFT_OK;
 }
@@ -91,8 +95,8 @@ static mlfft_status forward_backward(Ctx* c, Net& n, int W, int H, int Wd, const
     float* gnext = (float*)n.g1.p;
     for (int l = 3; l >= 0; --l) {
         const int pr = c->prof_begin(PK_NET_BWD, MLFFT_FP32, 0, 4.0 * W * npix * 9.0 * n.cin[l] * n.cout[l]);
-        HIPCHK(n_wgrad(g, (const unsigned short*)n.act[l].p, (float*)n.dwp[l].p, W, H, Wd, n.cinp[l], n.coutp[l], s),
-               "weight gradient");
+        HIPCHK(n_wgrad(g, (const unsigned short*)n.act[l].p, (float*)n.dwp[l].p, (float*)n.wpart.p, W, H, Wd, n.cinp[l],
+                       n.coutp[l], s), "weight gradient");
         if (l > 0) {
             HIPCHK(n_dgrad(g, (const unsigned short*)n.wbf[l].p, (const unsigned short*)n.act[l].p, gnext, W, H, Wd,
                            n.cinp[l], n.coutp[l], s), "input gradient");
@@ -175,7 +179,7 @@ mlfft_status mlfft_net_create(mlfft_ctx ctx, int b, int hidden, unsigned seed) {
     c->net_release();
     Net* n = new Net();
     for (Buf* x : {&n->wmaster, &n->m, &n->v, &n->dw, &n->out, &n->yhat, &n->scale, &n->phase, &n->tgt, &n->g0, &n->g1,
-                   &n->loss, &n->fb})
+                   &n->loss, &n->fb, &n->wpart})
         x->bind(&c->alloc);
     for (int l = 0; l < 4; ++l) {
         n->wbf[l].bind(&c->alloc);
