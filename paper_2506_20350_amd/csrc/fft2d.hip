@@ -519,20 +519,20 @@ static FftChoice choice_of(int prec, int pad, int dir, int Nx, int Ny, int b) {
     return it == g_fft_override.end() ? FftChoice{} : it->second;
 }
 
-// Half-height tile: padded transforms whose lengths are not the primes 17..31
-// (their direct DFTs would spill with a parked half-length vector), by default
-// in both directions and precisions.
+// Half-height tile: by default every padded transform whose lengths are not the
+// primes 17..31; those take it when tuned to (their direct DFTs and the parked
+// half-length vector need the 256-thread bound below).
 bool fft_use_half(int prec, int pad, int dir, int Nx, int Ny, int b) {
-    if (!pad || std::max(len_class(Nx), len_class(Ny)) > 1) return false;
+    if (!pad) return false;
     const FftChoice c = choice_of(prec, pad, dir, Nx, Ny, b);
     if (c.half >= 0) return c.half != 0;
-    return true;
+    return std::max(len_class(Nx), len_class(Ny)) <= 1;
 }
 
-// threads a workgroup may have: the FP64 half-height kernels are bounded at 256
-// so that a wave may hold the parked half-length vector (and the codelet) in up
-// to 512 registers without spilling
-static int thread_limit(int prec, bool half) { return prec == P64 && half ? 256 : 512; }
+// threads a workgroup may have: the FP64 half-height kernels, and the FP32 ones of
+// the prime lengths, are bounded at 256 so that a wave may hold the parked
+// half-length vector (and a direct DFT) in up to 512 registers without spilling
+static int thread_limit(int prec, bool half, int cls) { return half && (prec == P64 || cls == 2) ? 256 : 512; }
 
 // LDS rows of a tile
 static int tile_rows(int pad, bool half, int Ny) { return pad && !half ? 2 * Ny : Ny; }
@@ -553,8 +553,9 @@ static int elem_bytes(int prec) { return prec == P64 ? 16 : 8; }
 static bool cm_fits(int prec, int pad, bool half, int Nx, int Ny, int cm) {
     const int eb = elem_bytes(prec);
     const int Py = tile_rows(pad, half, Ny);
+    const int cls = std::max(len_class(Nx), len_class(Ny));
     return (size_t)Py * tile_stride(eb, Nx, cm) * eb <= kLdsBudget &&
-           (Py > Nx ? Py : Nx) * cm <= thread_limit(prec, half);
+           (Py > Nx ? Py : Nx) * cm <= thread_limit(prec, half, cls);
 }
 
 // largest power-of-two m-chunk (up to 64 and b) the launch limits allow for a tile choice
@@ -631,8 +632,11 @@ static FftKernel pick_kernel(int cls, int pad) {
 template<typename C, int INV>
 static FftKernel pick_half(int cls) {
     constexpr int LB = sizeof(C) == 16 ? 256 : 512;
-    if (cls > 1) return nullptr;
-    if (INV) return with_lds(cls == 0 ? (FftKernel)fft_inv_half_kernel<C, 0, LB> : (FftKernel)fft_inv_half_kernel<C, 1, LB>);
+    if (INV) {
+        if (cls == 2) return with_lds((FftKernel)fft_inv_half_kernel<C, 2, 256>);
+        return with_lds(cls == 0 ? (FftKernel)fft_inv_half_kernel<C, 0, LB> : (FftKernel)fft_inv_half_kernel<C, 1, LB>);
+    }
+    if (cls == 2) return with_lds((FftKernel)fft_fwd_half_kernel<C, 2, 256>);
     return with_lds(cls == 0 ? (FftKernel)fft_fwd_half_kernel<C, 0, LB> : (FftKernel)fft_fwd_half_kernel<C, 1, LB>);
 }
 
@@ -657,7 +661,7 @@ static hipError_t launch_t(const FftTask* th, const FftTask* td, int ntasks, hip
         cls = std::max(cls, std::max(len_class(t.Nx), len_class(t.Ny)));
     }
     if (grid == 0) return hipSuccess;
-    if (block > thread_limit(prec, half) || lds > kLdsBudget) return hipErrorInvalidValue;
+    if (block > thread_limit(prec, half, cls) || lds > kLdsBudget) return hipErrorInvalidValue;
     FftKernel k = half ? pick_half<C, INV>(cls) : pick_kernel<C, INV>(cls, th[0].pad);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, s, th[0], ntasks > 1 ? td : nullptr, ntasks > 1 ? ntasks : 0);

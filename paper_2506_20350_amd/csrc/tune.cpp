@@ -119,7 +119,7 @@ mlfft_status mlfft_autotune(mlfft_ctx ctx, int array_id, int W, int prec, int re
             for (int half : {0, 1}) {
                 if (half && !pad) continue;
                 fft_set_choice(fprec, pad, dir, a->Nx, a->Ny, a->b, 0, half);
-                if (fft_use_half(fprec, pad, dir, a->Nx, a->Ny, a->b) != (half != 0)) continue;   // prime lengths
+                if (fft_use_half(fprec, pad, dir, a->Nx, a->Ny, a->b) != (half != 0)) continue;
                 const int cmax = fft_max_cm(fprec, pad, half, a->Nx, a->Ny, a->b);
                 for (int cm = 1; cm <= cmax; cm *= 2) {
                     fft_set_choice(fprec, pad, dir, a->Nx, a->Ny, a->b, cm, half);

@@ -247,12 +247,14 @@ def test_autotuned_shapes_keep_parity(ctx):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("Nx,Ny,b,W", [(30, 30, 13, 3), (7, 5, 24, 5), (1, 9, 40, 4), (16, 12, 8, 6), (17, 4, 6, 3)])
+@pytest.mark.parametrize("Nx,Ny,b,W", [(30, 30, 13, 3), (7, 5, 24, 5), (1, 9, 40, 4), (16, 12, 8, 6), (17, 4, 6, 3),
+                                        (5, 23, 10, 2), (31, 19, 4, 2)])
 def test_fft_tile_kinds_and_chunks_keep_parity(ctx, prec, Nx, Ny, b, W):
     """Every tile kind (one-pass, half-height) and m-chunk of the padded transforms, forced per
     direction through tuning lines, against the oracle: the product and its fused epilogue
     (alpha Z x + beta v, the true residual's form).  Ragged b leaves a partial last m-chunk;
-    Nx = 1 and the prime 17 (one-pass only) are included."""
+    Nx = 1 and the prime 17 (direct DFT; its half-height kernels run under a 256-thread bound)
+    are included."""
     blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=5)
     ctx.set_blocks(52, blocks)
     X = synth.random_vectors(Nx * Ny * b, W, seed=6)
