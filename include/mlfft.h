@@ -223,16 +223,17 @@ typedef struct {
                             both read the basis twice per step; FP64 sums */
     int x0_given;        /* 1: I holds the initial guess on entry; 0: start from zero (default) */
     int record_history;  /* 1: fill info->history */
-    int use_graph;       /* 1: run the Krylov steps (preconditioner, product, orthogonalisation,
-                            rotation) four at a time as HIP graphs, captured the second time their
-                            launch configuration occurs and replayed afterwards; the host reads the
-                            column states once per graph instead of once per step.  Solutions,
-                            iteration counts and residuals are identical to use_graph = 0; steps
-                            after the last column retires inside a graph are spent (and counted
-                            in matvecs_inner).  Needs a context stream other than the NULL stream
-                            (else the steps run eagerly, one at a time).  Graphs are dropped
-                            whenever a library buffer is reallocated.  Profiling does not see
-                            captured launches. */
+    int use_graph;       /* k in 1..8: run the Krylov steps (preconditioner, product,
+                            orthogonalisation, rotation) k at a time as HIP graphs, captured the
+                            second time their launch configuration occurs and replayed afterwards;
+                            the host reads the column states once per graph instead of once per
+                            step.  Solutions, iteration counts and residuals are identical to
+                            use_graph = 0 (eager launches); with k > 1, steps after the last column
+                            retires inside a graph are spent (and counted in matvecs_inner), so
+                            k = 1 does the eager work with one launch per step.  Needs a context
+                            stream other than the NULL stream (else the steps run eagerly).  Graphs
+                            are dropped whenever a library buffer is reallocated.  Profiling does
+                            not see captured launches.  MLFFT_E_ARG outside 0..8. */
     int mode;            /* 0 (default): one Krylov space per right-hand side (the paper's split
                             mode with all columns batched); 1: global GMRES (eq. ZIVvec), one
                             Krylov space for all W columns (of all arrays of a batch) with

@@ -21,6 +21,9 @@
 
 using namespace mlfft;
 
+// most Krylov steps one captured graph may hold (use_graph)
+static const int kMaxGraphSteps = 8;
+
 #define HIPCHK(call, what)                                   \
     do {                                                     \
         hipError_t e_ = (call);                              \
@@ -100,7 +103,8 @@ static mlfft_status check_opts(Ctx* c, const mlfft_solve_opts& o) {
     if (o.max_outer < 1) return c->fail(MLFFT_E_ARG, "max_outer must be >= 1");
     if (o.precond < 0 || o.precond > 4) return c->fail(MLFFT_E_ARG, "precond must be 0, 1, 2, 3 or 4");
     if (o.orth != 1 && o.orth != 2) return c->fail(MLFFT_E_ARG, "orth must be 1 or 2");
-    if (o.use_graph != 0 && o.use_graph != 1) return c->fail(MLFFT_E_ARG, "use_graph must be 0 or 1");
+    if (o.use_graph < 0 || o.use_graph > kMaxGraphSteps)
+        return c->fail(MLFFT_E_ARG, "use_graph must be in [0, %d]", kMaxGraphSteps);
     if (o.mode != 0 && o.mode != 1) return c->fail(MLFFT_E_ARG, "mode must be 0 (per right-hand side) or 1 (global)");
     if (o.pc_bf16 != 0 && o.pc_bf16 != 1) return c->fail(MLFFT_E_ARG, "pc_bf16 must be 0 or 1");
     if (o.precond == 3 && !c->net_ready()) return c->fail(MLFFT_E_STATE, "learned preconditioner requested but no network is loaded");
@@ -138,8 +142,6 @@ static mlfft_status batch_precond(Ctx* c, std::vector<Seg>& segs, int kind, cons
     return MLFFT_OK;
 }
 
-// Krylov steps per captured graph (use_graph = 1).
-static const int kGraphSteps = 4;
 
 // Launch configuration of one Krylov step: everything its captured kernels and
 // copies depend on (the arrays, the column layout, the workspace addresses and
@@ -149,7 +151,7 @@ static std::string graph_key(Ctx* c, const std::vector<Seg>& segs, const Work& w
     std::string k;
     auto put = [&k](const void* p, size_t n) { k.append((const char*)p, n); };
     const int hl = (info && o.record_history) ? info->history_len : 0;
-    const int ints[] = {j, prec, o.precond, o.orth, o.restart, w.Wt, hl, o.mode, o.pc_bf16};
+    const int ints[] = {j, prec, o.precond, o.orth, o.restart, w.Wt, hl, o.mode, o.pc_bf16, o.use_graph};
     put(ints, sizeof ints);
     const void* ptrs[] = {c->solve_ws.p, c->solve_ws2.p, c->pinned, c->spec_a.p, c->spec_b.p,
                           // the carved workspace (its offsets move with the in-place / staged layout and
@@ -304,10 +306,10 @@ static mlfft_status inner_solve(Ctx* c, std::vector<Seg>& segs, Work& w, const C
                 return MLFFT_OK;
             };
             // Eagerly the host checks the column states after every step.  With graphs,
-            // kGraphSteps steps form one graph and the host checks once per graph: a
+            // use_graph steps form one graph and the host checks once per graph: a
             // column that retires inside it is skipped by the remaining steps (their
             // batched product still spends its work on it).
-            const int nstep = o.use_graph ? std::min(kGraphSteps, m - j) : 1;
+            const int nstep = o.use_graph ? std::min(o.use_graph, m - j) : 1;
             auto steps = [&]() -> mlfft_status {
                 for (int q = j; q < j + nstep; ++q) STCHK(step(q));
                 HIPCHK(hipMemcpyAsync(pinned_state, w.state, Wt * sizeof(int), hipMemcpyDeviceToHost, s), "state");

@@ -229,6 +229,10 @@ def test_solve_rejects_bad_arguments(ctx):
     with pytest.raises(abi.MlfftError) as e:
         ctx.solve(16, bad)
     assert e.value.status == abi.MLFFT_E_ARG
+    for g in (-1, 9):
+        with pytest.raises(abi.MlfftError) as e:
+            ctx.solve(16, V, use_graph=g)
+        assert e.value.status == abi.MLFFT_E_ARG
 
 
 @pytest.mark.parametrize("kd", [2 * np.pi / 3, np.pi])
@@ -315,11 +319,12 @@ def _graph_case(ctx, aid, precond, seed):
     return blocks, to_dev(synth.port_rhs(Nx, Ny, b))
 
 
-@pytest.mark.parametrize("precond", [1, 3])
-def test_graph_captured_steps_match_eager_on_every_replay(ctx, precond):
-    """use_graph = 1 on a side stream: the first solve runs eagerly, the second captures every
-    Krylov step, the later ones replay the graphs.  Eager library work and host synchronisations
-    run between the solves; every solve must equal the eager solve bit for bit."""
+@pytest.mark.parametrize("precond,steps", [(1, 1), (3, 1), (1, 4), (3, 3)])
+def test_graph_captured_steps_match_eager_on_every_replay(ctx, precond, steps):
+    """use_graph = 1, 3 or 4 Krylov steps per graph on a side stream: the first solve runs eagerly,
+    the second captures the steps, the later ones replay the graphs.  Eager library work and host
+    synchronisations run between the solves; every solve must equal the eager solve bit for bit
+    (the steps a multi-step graph spends after the last column retired change nothing)."""
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         if precond == 3:
@@ -331,7 +336,7 @@ def test_graph_captured_steps_match_eager_on_every_replay(ctx, precond):
         I0, info0 = ctx.solve(70, V, tol=1e-10, inner_prec="fp32", precond=precond)
         assert info0["status"] == abi.MLFFT_OK
         for rep in range(4):
-            I, info = ctx.solve(70, V, tol=1e-10, inner_prec="fp32", precond=precond, use_graph=1)
+            I, info = ctx.solve(70, V, tol=1e-10, inner_prec="fp32", precond=precond, use_graph=steps)
             y = ctx.matvec(70, I)                  # eager work between the replays
             side.synchronize()
             assert info["status"] == abi.MLFFT_OK, rep
