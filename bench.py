@@ -289,8 +289,19 @@ def bench_batch(a, torch):
         side.synchronize()
         dg = time.perf_counter() - t2
     gval = sum(int(np.sum(i["relres"] <= a.tol)) for i in ginfos) / dg
+    # the same arrays solved one after the other (one solve call, so one set of launches,
+    # per array): what batching them into one solve gains
+    for i in ids:
+        ctx.solve(i, Vs[i], Is_buf[i], tol=a.tol, **opts)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    sconv = 0
+    for i in ids:
+        sconv += int(np.sum(ctx.solve(i, Vs[i], Is_buf[i], tol=a.tol, **opts)[1]["relres"] <= a.tol))
+    torch.cuda.synchronize()
+    dseq = time.perf_counter() - t3
     log(f"[bench] batch {form}: {dt / a.steps * 1e3:.1f} ms/step, {value:.1f} RHS/s; with graphs "
-        f"{dg / a.steps * 1e3:.1f} ms/step; fp64 {d64 * 1e3:.1f} ms")
+        f"{dg / a.steps * 1e3:.1f} ms/step; one array at a time {dseq * 1e3:.1f} ms; fp64 {d64 * 1e3:.1f} ms")
     out = dict(metric="solved RHS/s @ rel-res 1e-6 (uneven batch of 64 arrays)", value=round(value, 2),
                unit="RHS/s", n_gpus=1, steps=a.steps, warmup=a.warmup, ms_per_step=round(dt / a.steps * 1e3, 3),
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype=DTYPE[form], data="synthetic",
@@ -308,7 +319,10 @@ def bench_batch(a, torch):
                compare=[dict(form="fp64", value=round(int(np.sum(i64["relres"] <= a.tol)) / d64, 2),
                              ms_per_step=round(d64 * 1e3, 3)),
                         dict(form=form + "+graph", value=round(gval, 2), ms_per_step=round(dg / a.steps * 1e3, 3),
-                             note="Krylov steps replayed from captured HIP graphs; not profiled")])
+                             note="Krylov steps replayed from captured HIP graphs, one step per graph; not profiled"),
+                        dict(form=form + ", one array at a time", value=round(sconv / dseq, 2),
+                             ms_per_step=round(dseq * 1e3, 3),
+                             note="the same 64 arrays solved by 64 successive solve calls instead of one batch")])
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -336,7 +350,7 @@ def bench_small(a, torch):
         ctx = Context(0)
         ctx.set_blocks(0, blocks)
         Vd = torch.from_numpy(V).cuda()
-        for graph in (0, 1):
+        for graph in (0, 1, 8):
             opts = dict(inner_prec=cfg["inner_prec"], precond=cfg["precond"], tol=cfg["tol"], use_graph=graph)
             for _ in range(max(a.warmup, 2)):
                 ctx.solve(0, Vd, **opts)
@@ -356,15 +370,19 @@ def bench_small(a, torch):
     err = float(np.linalg.norm(I.cpu().numpy() - direct.lu_solve(tp.dense_Z(blocks), V)) /
                 np.linalg.norm(direct.lu_solve(tp.dense_Z(blocks), V)))
     W = V.shape[0]
-    g = res[1]
+    # the faster of one step per graph and eight steps per graph (which spends the steps
+    # after convergence inside the last graph but reads the column states once per graph)
+    gk = 1 if res[1]["us_per_solve"] <= res[8]["us_per_solve"] else 8
+    g = res[gk]
     out = dict(metric=f"us per solve ({a.workload}: {Nx}x{Ny} array, b={b}, {W} RHS, tol {cfg['tol']:g})",
                value=g["us_per_solve"], unit="us", n_gpus=1, steps=max(a.steps, 20), warmup=max(a.warmup, 2),
                ms_per_step=round(g["us_per_solve"] / 1e3, 4), higher_is_better=False, scaling="weak",
                vs_baseline=None, dtype="f64" if cfg["inner_prec"] == "fp64" else "f32+f64", data="synthetic",
                config=dict(workload=f"{Nx}x{Ny} array, b={b}, kd={cfg['kd']:.4f}, {W} port RHS, "
                                     f"inner {cfg['inner_prec']}, preconditioner {cfg['precond']}, tol {cfg['tol']:g}, "
-                                    "Krylov steps replayed from HIP graphs", Nx=Nx, Ny=Ny, b=b, W=W),
-               graph=res[1], eager=res[0], err_vs_lu=err,
+                                    f"Krylov steps replayed from HIP graphs, {gk} per graph", Nx=Nx, Ny=Ny, b=b,
+                           W=W, use_graph=gk),
+               graph=res[gk], graph1=res[1], graph8=res[8], eager=res[0], err_vs_lu=err,
                note="latency-bound case: no roofline claim")
     print(json.dumps(out), flush=True)
     ctx.close()
