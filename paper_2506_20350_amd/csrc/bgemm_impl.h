@@ -834,10 +834,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
     // steps, so the MFMA pipes already have work while the wave issues them
     auto products = [&](int h, auto issue) {
         const double2* xp = xs + (h * 2 + pan) * TILE + j * RS + q;
+        // B fragments read two steps ahead: with one wave per SIMD nothing else hides
+        // the LDS latency behind the three products of a step
+        mlfft_d2v u0 = *reinterpret_cast<const mlfft_d2v*>(xp);
+        mlfft_d2v u1 = *reinterpret_cast<const mlfft_d2v*>(xp + 4);
 #pragma unroll
         for (int s2 = 0; s2 < SH; ++s2) {
             const int s = (h ? SH : 0) + s2;
-            const mlfft_d2v u = *reinterpret_cast<const mlfft_d2v*>(xp + 4 * s2);
+            const mlfft_d2v u = u0;
+            u0 = u1;
+            if (s2 + 2 < SH) u1 = *reinterpret_cast<const mlfft_d2v*>(xp + 4 * (s2 + 2));
             t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[s], u[0], t1, 0, 0, 0);
             t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[s], u[1], t2, 0, 0, 0);
             t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[s] + ai[s], u[0] + u[1], t3, 0, 0, 0);
