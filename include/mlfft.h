@@ -454,12 +454,15 @@ mlfft_status mlfft_tune_report(mlfft_ctx ctx, int array_id, char* buf, size_t n)
  * m-chunk, 0 for the default rule; half 1 for the half-height tile of a padded
  * transform, 0 for the one-pass tile, -1 for the default), the older
  * "fftcm prec pad Nx Ny b cm" (both directions), and "gemmpc 2 bp waves nt form" for the bf16
- * preconditioner product with bp a multiple of 16 (form 3, bp <= 208: one
- * frequency per workgroup, the default for bp in 112..208; form 2 with 8 waves
- * and 32-column tiles: the flat kernel, the default elsewhere; waves 0 restores
- * the default), "gemmpcwg n" for the number of workgroups a launch of the form-3 kernel
- * aims at (the columns of a frequency are split to reach it; default 512); other
- * lines are ignored.  MLFFT_E_ARG for a malformed gemm, gemmpc, gemmpcwg, fftshape or fftcm line. */
+ * preconditioner product with bp a multiple of 16 (forms 3 and 5, bp <= 208, 8
+ * waves, 32-column tiles: each X tile staged once for all row slices of its
+ * frequency, form 3 with the tiles of one frequency (or a column chunk of it) per
+ * workgroup, form 5 with all (frequency, tile) items split evenly over the
+ * workgroups, the default for bp in 112..208; form 2 with 8 waves and 32-column
+ * tiles: the flat kernel, the default elsewhere; waves 0 restores the default),
+ * "gemmpcwg n" for the number of workgroups a launch of form 3 or 5 aims at (form 3
+ * splits the columns of a frequency to reach it, default 512; form 5 default: the
+ * device's CU count); other lines are ignored.  MLFFT_E_ARG for a malformed gemm, gemmpc, gemmpcwg, fftshape or fftcm line. */
 mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text);
 
 /* ------------------------------------------------------------------ profiling */

@@ -16,9 +16,24 @@ int gemm_bp(int prec, int b) {
 
 static GemmShape g_shape_override[3][33];      // [prec][bp/8]; waves == 0: not tuned
 static GemmShape g_shape_pc16[33];             // bf16 preconditioner product [bp/8]; waves == 0: default
-static int g_pc_wg_target = 512;               // workgroups a launch of the frequency kernel aims at
+// workgroups a launch of the frequency kernel aims at; 0: 512 for form 3, the device's
+// CU count for form 5
+static int g_pc_wg_target = 0;
 
 void gemm_set_pc_wg_target(int n) { if (n >= 1 && n <= (1 << 20)) g_pc_wg_target = n; }
+
+// compute units of the current device (cached per device)
+static int device_cus() {
+    static int cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
 
 static GemmShape default_shape(int prec, int bp) {
     // FP64 from b = 33 (three 16-row slices): the flat three-product kernel with
@@ -39,13 +54,13 @@ GemmShape gemm_shape(int prec, int bp, int tag) {
         // product of the same b when that is an eight-wave flat shape
         const GemmShape& o = g_shape_override[prec][bp / 8];
         if (prec == P32 && (o.m3 == 2 || o.m3 == 4) && o.waves == 8) return o;
-        // the bf16 preconditioner product: one frequency per workgroup (each X tile staged
-        // once for all row slices of its frequency) for padded b in 112..208, unless a shape
-        // was imported for it (below 112 the flat kernels are faster, beyond 208 the
-        // frequency kernel's stationary fragments spill)
+        // the bf16 preconditioner product: each X tile staged once for all row slices of
+        // its frequency, the (frequency, tile) items split evenly over about one workgroup
+        // per CU (form 5), for padded b in 112..208, unless a shape was imported for it
+        // (below 112 the flat kernels are faster, beyond 208 the stationary fragments spill)
         if (prec == PBF16)
             return g_shape_pc16[bp / 8].waves ? g_shape_pc16[bp / 8]
-                                              : (bp >= 112 && bp <= 208) ? GemmShape{8, 32, 3} : GemmShape{8, 32, 2};
+                                              : (bp >= 112 && bp <= 208) ? GemmShape{8, 32, 5} : GemmShape{8, 32, 2};
         return GemmShape{8, 32, 2};
     }
     const GemmShape& o = g_shape_override[prec][bp / 8];
@@ -58,7 +73,8 @@ void gemm_set_shape(int prec, int bp, int waves, int nt, int m3) {
     // BF16 has the eight-row kernel (m3 = 0) and the flat kernel with eight waves and
     // 32-column tiles or four waves and 16-column tiles
     if (prec == PBF16 && (m3 == 1 || (m3 == 2 && !((waves == 8 && nt == 32) || (waves == 4 && nt == 16))) ||
-                          (m3 == 3 && !(waves == 8 && nt == 32)) || m3 > 3)) return;
+                          ((m3 == 3 || m3 == 5) && !(waves == 8 && nt == 32 && bp <= 208)) || m3 == 4 || m3 > 5))
+        return;
     // form 4: the flat kernel with direct-to-LDS tiles, 16-column tiles, eight waves (FP32)
     // or four (FP64)
     if (prec != PBF16 && m3 > 2 && !(m3 == 4 && nt == 16 && waves == (prec == P32 ? 8 : 4))) return;
@@ -88,6 +104,7 @@ static int bp_max_of(int prec, const GemmTask* tasks, int ntasks) {
 // K * ceil(b/16) (frequency, slice) items to eight waves per workgroup
 static int task_blocks(const GemmTask& t, const GemmShape& sh) {
     if (sh.m3 == 3) return t.K * t.mgroups;
+    if (sh.m3 == 5) return t.mgroups;
     if (sh.m3 == 2 || sh.m3 == 4) return (t.K * ((t.b + 15) / 16) + sh.waves - 1) / sh.waves;
     return ((t.K + kXcd - 1) / kXcd) * kXcd * t.mgroups;
 }
@@ -127,15 +144,27 @@ void plan_gemm_tasks(int prec, GemmTask* tasks, int ntasks, int tag, int* grid, 
     const int bpm = bp_max_of(prec, tasks, ntasks);
     const GemmShape sh = launch_shape(prec, tasks, ntasks, tag, bpm);
     const int rows = sh.m3 ? 16 : 8;
+    // form 5: the (frequency, column tile) items of all tasks split over about one
+    // workgroup per CU, each task taking a share proportional to its items
+    long long items = 0;
+    const int target5 = g_pc_wg_target ? g_pc_wg_target : device_cus();
+    if (sh.m3 == 5)
+        for (int i = 0; i < ntasks; ++i) items += (long long)tasks[i].K * ((tasks[i].W + sh.nt - 1) / sh.nt);
     for (int i = 0; i < ntasks; ++i) {
         GemmTask& t = tasks[i];
         const int nslices = (t.b + rows - 1) / rows;
         t.mgroups = (nslices + sh.waves - 1) / sh.waves;
         if (sh.m3 == 3) {
             // one frequency per workgroup; its columns split so that the launch has at
-            // least g_pc_wg_target workgroups, each split reading G once more
+            // least the target number of workgroups, each split reading G once more
             const int tiles = (t.W + sh.nt - 1) / sh.nt;
-            t.mgroups = std::max(1, std::min(tiles, (g_pc_wg_target + t.K - 1) / std::max(t.K, 1)));
+            const int target = g_pc_wg_target ? g_pc_wg_target : 512;
+            t.mgroups = std::max(1, std::min(tiles, (target + t.K - 1) / std::max(t.K, 1)));
+        }
+        if (sh.m3 == 5) {
+            const long long mine = (long long)t.K * ((t.W + sh.nt - 1) / sh.nt);
+            const long long share = items > 0 ? (target5 * mine + items - 1) / items : 1;
+            t.mgroups = (int)std::max(1LL, std::min(mine, share));
         }
         t.block_begin = g;
         g += task_blocks(t, sh);

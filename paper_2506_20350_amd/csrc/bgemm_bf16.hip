@@ -22,11 +22,11 @@ static hipError_t launch_b16_flat_cfg(const GemmTask& t0, const GemmTask* td, in
     return hipGetLastError();
 }
 
-template<int BP, int TAG>
+template<int BP, int TAG, int RANGE>
 static hipError_t launch_b16_freq(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
     constexpr int BP32 = (BP + 31) / 32 * 32;
     const size_t lds = (size_t)4 * 32 * (BP32 + 8) * sizeof(unsigned short);
-    auto k = bgemm_bf16_freq_kernel<BP, 32, TAG>;
+    auto k = bgemm_bf16_freq_kernel<BP, 32, TAG, RANGE>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(grid), dim3(512), lds, s, t0, td, n);
     return hipGetLastError();
@@ -45,12 +45,17 @@ static hipError_t launch_b16_flat(GemmShape sh, const GemmTask& t0, const GemmTa
 #define MLFFT_BP16_FLAT(X) X(48) X(64) X(80) X(96) X(112) X(128) X(144) X(160) X(176) X(192) X(208) X(224) \
     X(240) X(256)
 
+#define MLFFT_BP16_FREQ(X) X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128) X(144) X(160) X(176) X(192) X(208)
+
 hipError_t launch_bgemm_bf16(int bp, GemmShape sh, int tag, const GemmTask& t0, const GemmTask* td, int n, int grid,
                              hipStream_t s) {
-    if (sh.m3 == 3) {
+    if (sh.m3 == 3 || sh.m3 == 5) {
         switch (bp) {
-#define Q16(B) case B: return tag ? launch_b16_freq<B, 1>(t0, td, n, grid, s) : launch_b16_freq<B, 0>(t0, td, n, grid, s);
-            MLFFT_BP16(Q16)
+#define Q16(B) case B: return sh.m3 == 5 ? (tag ? launch_b16_freq<B, 1, 1>(t0, td, n, grid, s)          \
+                                                : launch_b16_freq<B, 0, 1>(t0, td, n, grid, s))          \
+                                         : (tag ? launch_b16_freq<B, 1, 0>(t0, td, n, grid, s)          \
+                                                : launch_b16_freq<B, 0, 0>(t0, td, n, grid, s));
+            MLFFT_BP16_FREQ(Q16)
 #undef Q16
             default: return hipErrorInvalidValue;
         }

@@ -893,6 +893,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 
 // ------------------------------------------------------------------ BF16
 
+// p (wave-uniform) through an empty asm statement: the compiler can neither hoist nor
+// precompute addresses derived from the result
+template<typename T>
+__device__ __forceinline__ const T* opaque_uniform(const T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ unsigned short bf16_rne(float f) { return f32_to_bf16_bits(f); }
 
 template<int BP, int NT, int TAG>
@@ -1141,12 +1152,17 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_bf16_flat_kernel(GemmTask t0
 // the tile is staged as Re X and -Im X planes (bf16 rounding is symmetric, so -Im X
 // rounds to minus the rounded Im X).  A complex product is four MFMAs into two
 // accumulators: Re Y = Re G Re X + Im G (-Im X), Im Y = Im G Re X + (-Re G)(-Im X),
-// with -Re G formed by flipping sign bits.  The reduction runs over b padded to 32.  The columns
-// of a frequency may be split over a few workgroups (mgroups of them) so that a launch
-// has enough workgroups; each reads G once more.  X tiles are double-buffered with the
-// next tile prefetched into registers; a lane's four output rows leave as two 16-byte
-// stores.
-template<int BP, int NT, int TAG>
+// with -Re G formed by flipping sign bits.  The reduction runs over b padded to 32.
+// Work items are (frequency, 32-column tile) pairs, item i being tile i % ntile of
+// frequency i / ntile; a workgroup runs a contiguous range of items, one segment per
+// frequency the range touches (the segment loads that frequency's fragments).
+// RANGE == 0: the range is one of mgroups column chunks of one frequency (K * mgroups
+// workgroups).  RANGE == 1: all K * ntile items are split evenly over mgroups
+// workgroups, about one per CU, so that no partial last round of workgroups leaves CUs
+// idle (30x30, b = 200: 900 frequencies of 29 tiles were 3.5 rounds of one-frequency
+// workgroups).  X tiles are double-buffered with the next tile prefetched into
+// registers; a lane's four output rows leave as two 16-byte stores.
+template<int BP, int NT, int TAG, int RANGE>
 __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
     constexpr int NTH = 512;
     constexpr int BP32 = (BP + 31) / 32 * 32;
@@ -1156,42 +1172,35 @@ __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const
     extern __shared__ unsigned char smem_raw[];
     unsigned short* xs = reinterpret_cast<unsigned short*>(smem_raw);   // [buffer][plane][NT][LDX]
     const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
-    const int b = t.b, W = t.W, K = t.K, ncs = t.mgroups;
-    const int nwg = K * ncs;
+    const int b = t.b, W = t.W, K = t.K;
+    const int ntile = (W + NT - 1) / NT;
     const int local = blockIdx.x - t.block_begin;
+    const int nwg = RANGE ? t.mgroups : K * t.mgroups;
     const int per = nwg >> 3;
     const int grp = local < per * 8 ? (local & 7) * per + (local >> 3) : local;
-    const int k = grp / ncs, chunk = grp - k * ncs;
-    const int ntile = (W + NT - 1) / NT;
-    const int tpc = (ntile + ncs - 1) / ncs;          // tiles per column chunk
-    const int wbeg = chunk * tpc * NT, wend = min(W, (chunk + 1) * tpc * NT);
+    // this workgroup's items [i0, i1): item i is column tile i % ntile of frequency i / ntile
+    int i0, i1;
+    if (RANGE) {
+        const long long T = (long long)K * ntile;
+        i0 = (int)(T * grp / nwg);
+        i1 = (int)(T * (grp + 1) / nwg);
+    } else {
+        const int ncs = t.mgroups;
+        const int k = grp / ncs, chunk = grp - k * ncs;
+        const int tpc = (ntile + ncs - 1) / ncs;      // tiles per column chunk
+        i0 = k * ntile + min(ntile, chunk * tpc);
+        i1 = k * ntile + min(ntile, (chunk + 1) * tpc);
+    }
+    if (i0 >= i1) return;                             // uniform over the workgroup
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = lane & 15, q = lane >> 4;
     const int ns = (b + 15) >> 4;
     bool act[2];
     int mb[2];
-    ushortx8 gr[2][S], gi[2][S];
-    const uint32_t* __restrict__ Gk = static_cast<const uint32_t*>(t.G) + (size_t)k * t.gstride;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int sl = wave + 8 * h;
-        act[h] = sl < ns;
-        mb[h] = sl * 16;
-        const int m = mb[h] + j;
-#pragma unroll
-        for (int st = 0; st < S; ++st) {
-            ushortx8 vr, vi;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int n = 32 * st + 8 * q + e;
-                uint32_t g = 0;
-                if (act[h] && m < b && n < b) g = gload(Gk + (size_t)m * b + n);
-                vr[e] = (unsigned short)(g & 0xffffu);
-                vi[e] = (unsigned short)(g >> 16);
-            }
-            gr[h][st] = vr;
-            gi[h][st] = vi;
-        }
+        act[h] = wave + 8 * h < ns;
+        mb[h] = (wave + 8 * h) * 16;
     }
     // reduction padding n in [b, BP32) of every row, both planes, both buffers
     const int padn = BP32 - b;
@@ -1199,32 +1208,67 @@ __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const
         const int row = e / padn, n = b + (e - row * padn);
         xs[row * LDX + n] = 0;
     }
-    const float2* __restrict__ Xk = static_cast<const float2*>(t.X) + (size_t)k * W * b;
-    float2* __restrict__ Yk = static_cast<float2*>(t.Y) + (size_t)k * W * b;
+    // one segment per frequency the range touches: its fragments, then its tiles
+    for (int k = i0 / ntile; k * ntile < i1; ++k) {
+    // b made opaque per segment: nothing derived from it (bounds tests, LDS offsets) is
+    // hoisted out of the segment loop, where it would be live during the fragment loads
+    int bk = __builtin_amdgcn_readfirstlane(b);
+    asm volatile("" : "+s"(bk));
+    const int wbeg = (max(i0, k * ntile) - k * ntile) * NT;
+    const int wend = min(W, (min(i1, (k + 1) * ntile) - k * ntile) * NT);
+    ushortx8 gr[2][S], gi[2][S];
+    {
+        // G's base made opaque, so that the bounds tests and addresses below are formed
+        // per segment rather than hoisted out of the segment loop
+        const uint32_t* __restrict__ Gk = opaque_uniform(static_cast<const uint32_t*>(t.G) + (size_t)k * t.gstride);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int m = mb[h] + j;
+#pragma unroll
+            for (int st = 0; st < S; ++st) {
+                ushortx8 vr, vi;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int n = 32 * st + 8 * q + e;
+                    uint32_t g = 0;
+                    if (act[h] && m < bk && n < bk) g = gload(Gk + (size_t)m * bk + n);
+                    vr[e] = (unsigned short)(g & 0xffffu);
+                    vi[e] = (unsigned short)(g >> 16);
+                }
+                gr[h][st] = vr;
+                gi[h][st] = vi;
+            }
+        }
+    }
+    const float2* __restrict__ Xk = static_cast<const float2*>(t.X) + (size_t)k * W * bk;
+    float2* __restrict__ Yk = static_cast<float2*>(t.Y) + (size_t)k * W * bk;
     const int plane = NT * LDX, bufsz = 2 * plane;
     float2 pre[PF];
     auto fetch = [&](int w0) {
-        const int have = min(NT, wend - w0) * b;
+        const int have = min(NT, wend - w0) * bk;
+        // the tile's base made opaque, so that the per-load addresses are formed at each
+        // fetch rather than hoisted out of the tile loop into registers of their own
+        const float2* __restrict__ src = opaque_uniform(Xk + (size_t)w0 * bk);
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
             const int e = threadIdx.x + i * NTH;
-            pre[i] = e < have ? gload(Xk + (size_t)w0 * b + e) : make_float2(0.f, 0.f);
+            pre[i] = e < have ? gload(src + e) : make_float2(0.f, 0.f);
         }
     };
     auto stage = [&](unsigned short* buf) {
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
             const int e = threadIdx.x + i * NTH;
-            if (e < NT * b) {
-                const int w = e / b, n = e - w * b;
+            if (e < NT * bk) {
+                const int w = e / bk, n = e - w * bk;
                 buf[w * LDX + n] = f32_to_bf16_bits(pre[i].x);
                 buf[plane + w * LDX + n] = f32_to_bf16_bits(-pre[i].y);
             }
         }
     };
-    const bool even_b = (b & 1) == 0;
-    fetch(wbeg);                          // zeros when the chunk is empty
-    __syncthreads();                      // padding zeroed
+    const bool even_b = (bk & 1) == 0;
+    fetch(wbeg);
+    __syncthreads();                      // padding zeroed; the previous segment's tiles read
     stage(xs);
     if (wbeg + NT < wend) fetch(wbeg + NT);
     __syncthreads();
@@ -1265,14 +1309,14 @@ __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const
 #pragma unroll
                     for (int r = 0; r < 4; ++r) o[r] = make_float2(cr[cg][r], ci[cg][r]);
                     const int m0 = mb[h] + 4 * q;
-                    float2* dst = Yk + (size_t)w * b + m0;
-                    if (even_b && m0 + 4 <= b) {
+                    float2* dst = Yk + (size_t)w * bk + m0;
+                    if (even_b && m0 + 4 <= bk) {
                         gstore2(dst, o[0], o[1]);
                         gstore2(dst + 2, o[2], o[3]);
                     } else {
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            if (m0 + r < b) gstore(dst + r, o[r]);
+                            if (m0 + r < bk) gstore(dst + r, o[r]);
                     }
                 }
             }
@@ -1282,6 +1326,7 @@ __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const
             if (w0 + 2 * NT < wend) fetch(w0 + 2 * NT);
         }
         __syncthreads();
+    }
     }
 }
 

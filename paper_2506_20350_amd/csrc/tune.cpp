@@ -203,7 +203,7 @@ mlfft_status mlfft_tune_import(mlfft_ctx ctx, const char* text) {
             // to 208) or form 2 (the flat kernel, eight waves, 32-column tiles); waves 0 restores
             // the default
             const bool ok = a1 == 2 && a2 >= 16 && a2 <= 256 && a2 % 16 == 0 &&
-                            ((a3 == 8 && a4 == 32 && (a5 == 2 || (a5 == 3 && a2 <= 208))) || a3 == 0);
+                            ((a3 == 8 && a4 == 32 && (a5 == 2 || ((a5 == 3 || a5 == 5) && a2 <= 208))) || a3 == 0);
             if (!ok) return c->fail(MLFFT_E_ARG, "bad tuning line: %s", ln.c_str());
             gemm_set_pc_shape(a2, a3, a4, a5);
         } else if (sscanf(ln.c_str(), "gemmpcwg %d", &a1) == 1) {

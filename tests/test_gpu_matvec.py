@@ -370,32 +370,36 @@ def test_bf16_flat_block_product_in_a_batched_solve(ctx):
 @pytest.mark.parametrize("Nx,Ny,b,W", [(6, 5, 24, 7), (5, 4, 64, 33), (4, 4, 100, 70), (4, 3, 120, 45),
                                         (30, 30, 200, 40), (3, 3, 208, 5)])
 def test_bf16_preconditioner_frequency_kernel_matches_flat_kernel_and_oracle(ctx, Nx, Ny, b, W):
-    """The bf16 preconditioner product with one frequency per workgroup against the flat kernel,
-    each in turn forced through a tuning line where the other is the default (the frequency
-    kernel is the default for padded b in 112..208): both round the same operands to bf16 and
-    accumulate in FP32 in different orders.  Ragged b (24, 100, 120) leaves padded reduction
-    rows and partial 16-row slices; W = 5, 7, 33, 45, 70 leave partial 32-column tiles."""
+    """The bf16 preconditioner product that stages each X tile once for all row slices of its
+    frequency, with the tiles of one frequency per workgroup (form 3) and with all tiles split
+    evenly over about one workgroup per CU, ranges crossing frequencies (form 5), against the
+    flat kernel (form 2), each forced through a tuning line (form 5 is the default for padded
+    b in 112..208, form 2 elsewhere).  Forms 3 and 5 run the same arithmetic per tile, so they
+    agree bit for bit; the flat kernel rounds the same operands to bf16 and accumulates in
+    FP32 in another order.  Ragged b (24, 100, 120) leaves padded reduction rows and partial
+    16-row slices; W = 5, 7, 33, 45, 70 leave partial 32-column tiles."""
     blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=3)
     ctx.set_blocks(9, blocks)
     R = synth.random_vectors(Nx * Ny * b, W, seed=4)
     Rd = to_dev(R, torch.complex64)
     bp = (b + 15) // 16 * 16
     z = {}
-    for form in (2, 3):
+    for form in (2, 3, 5):
         abi.mlfft_tune_import(ctx.h, f"gemmpc 2 {bp} 8 32 {form}\n")
         try:
             z[form] = to_host(ctx.precond_apply(9, Rd, kind=1, prec="bf16"))
         finally:
             abi.mlfft_tune_import(ctx.h, f"gemmpc 2 {bp} 0 0 0\n")
     z_default = to_host(ctx.precond_apply(9, Rd, kind=1, prec="bf16"))
-    assert np.array_equal(z_default, z[3 if 112 <= bp <= 208 else 2])
+    assert np.array_equal(z_default, z[5 if 112 <= bp <= 208 else 2])
+    assert np.array_equal(z[3], z[5])
     assert relerr(z[3], z[2]) <= 1e-5
     assert relerr(z[3], opc.strang_apply(opc.strang_inverse_spectrum(blocks), R)) <= TOL["bf16"]
 
 
 def test_bf16_preconditioner_shape_lines_are_validated(ctx):
     for bad in ("gemmpc 2 224 8 32 3", "gemmpc 2 200 8 32 3", "gemmpc 1 208 8 32 3", "gemmpc 2 208 4 16 3",
-                "gemmpcwg 0"):
+                "gemmpc 2 224 8 32 5", "gemmpc 2 208 4 16 5", "gemmpc 2 208 8 32 4", "gemmpcwg 0"):
         with pytest.raises(abi.MlfftError) as e:
             abi.mlfft_tune_import(ctx.h, bad + "\n")
         assert e.value.status == abi.MLFFT_E_ARG

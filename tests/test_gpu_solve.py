@@ -136,6 +136,29 @@ def test_bf16_preconditioner_product_in_a_batch_of_three_kernels(ctx, use_graph)
                     assert torch.equal(a, b), rep
 
 
+def test_bf16_preconditioner_tiles_split_over_two_arrays_in_one_launch(ctx):
+    """Two arrays of one padded b (120 and 122 pad to 128) share each bf16 preconditioner
+    launch, whose (frequency, tile) items are split evenly over about one workgroup per CU
+    with each array taking a share of workgroups proportional to its items; ragged W (9 and
+    12 ports) leaves partial tiles.  Every array meets its LU solution and agrees with the
+    array solved alone (where its launches hold one task) to the refinement tolerance."""
+    specs = [(3, 3, 120, 5), (4, 3, 122, 6)]
+    ids, Vs, refs = [], [], []
+    for i, (Nx, Ny, b, seed) in enumerate(specs):
+        blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=seed)
+        ctx.set_blocks(40 + i, blocks)
+        V = synth.port_rhs(Nx, Ny, b)
+        ids.append(40 + i)
+        Vs.append(to_dev(V))
+        refs.append(direct.lu_solve(tp.dense_Z(blocks), V))
+    I0, info0 = ctx.solve_batch(ids, Vs, tol=1e-10, inner_prec="fp32", precond=1, pc_bf16=1)
+    assert info0["status"] == abi.MLFFT_OK and np.all(info0["relres"] <= 1e-10)
+    for i, (I, ref) in enumerate(zip(I0, refs)):
+        assert relerr(to_host(I), ref) <= 1e-8
+        Ia, _ = ctx.solve(ids[i], Vs[i], tol=1e-10, inner_prec="fp32", precond=1, pc_bf16=1)
+        assert relerr(to_host(Ia), to_host(I)) <= 1e-9, i
+
+
 def test_bf16_preconditioner_option_is_validated(ctx):
     blocks = synth.green_blocks(3, 3, 8, np.pi, seed=0)
     ctx.set_blocks(32, blocks)
