@@ -368,7 +368,7 @@ def test_bf16_flat_block_product_in_a_batched_solve(ctx):
 
 
 @pytest.mark.parametrize("Nx,Ny,b,W", [(6, 5, 24, 7), (5, 4, 64, 33), (4, 4, 100, 70), (4, 3, 120, 45),
-                                        (30, 30, 200, 40), (3, 3, 208, 5)])
+                                        (4, 3, 161, 11), (30, 30, 200, 40), (3, 3, 208, 5)])
 def test_bf16_preconditioner_frequency_kernel_matches_flat_kernel_and_oracle(ctx, Nx, Ny, b, W):
     """The bf16 preconditioner product that stages each X tile once for all row slices of its
     frequency, with the tiles of one frequency per workgroup (form 3) and with all tiles split
@@ -377,7 +377,7 @@ def test_bf16_preconditioner_frequency_kernel_matches_flat_kernel_and_oracle(ctx
     b in 112..208, form 2 elsewhere).  Forms 3 and 5 run the same arithmetic per tile, so they
     agree bit for bit; the flat kernel rounds the same operands to bf16 and accumulates in
     FP32 in another order.  Ragged b (24, 100, 120) leaves padded reduction rows and partial
-    16-row slices; W = 5, 7, 33, 45, 70 leave partial 32-column tiles."""
+    16-row slices; W = 5, 7, 11, 33, 45, 70 leave partial 32-column tiles."""
     blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=3)
     ctx.set_blocks(9, blocks)
     R = synth.random_vectors(Nx * Ny * b, W, seed=4)
@@ -399,7 +399,8 @@ def test_bf16_preconditioner_frequency_kernel_matches_flat_kernel_and_oracle(ctx
 
 def test_bf16_preconditioner_shape_lines_are_validated(ctx):
     for bad in ("gemmpc 2 224 8 32 3", "gemmpc 2 200 8 32 3", "gemmpc 1 208 8 32 3", "gemmpc 2 208 4 16 3",
-                "gemmpc 2 224 8 32 5", "gemmpc 2 208 4 16 5", "gemmpc 2 208 8 32 4", "gemmpcwg 0"):
+                "gemmpc 2 224 8 32 5", "gemmpc 2 208 4 16 5", "gemmpc 2 208 8 32 4", "gemmpc 2 208 8 32 6",
+                "gemmpcwg 0"):
         with pytest.raises(abi.MlfftError) as e:
             abi.mlfft_tune_import(ctx.h, bad + "\n")
         assert e.value.status == abi.MLFFT_E_ARG
