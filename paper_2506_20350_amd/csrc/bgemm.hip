@@ -187,7 +187,14 @@ hipError_t launch_bgemm(int prec, const GemmTask* th, const GemmTask* td, int nt
     const int n = ntasks > 1 ? ntasks : 0;
     if (prec == P64) return launch_bgemm_f64(bpm, sh, tag, th[0], dt, n, grid, s);
     if (prec == P32) return launch_bgemm_f32(bpm, sh, tag, th[0], dt, n, grid, s);
-    return launch_bgemm_bf16(bpm, sh, tag, th[0], dt, n, grid, s);
+    GemmShape s16 = sh;
+    if (s16.m3 == 5) {
+        bool ok = true;
+        for (int i = 0; i < ntasks; ++i)
+            ok = ok && (th[i].b & 1) == 0 && (reinterpret_cast<uintptr_t>(th[i].X) & 15) == 0;
+        s16.pairs = ok ? 1 : 0;
+    }
+    return launch_bgemm_bf16(bpm, s16, tag, th[0], dt, n, grid, s);
 }
 
 }  // namespace mlfft

@@ -1162,13 +1162,15 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_bf16_flat_kernel(GemmTask t0
 // idle (30x30, b = 200: 900 frequencies of 29 tiles were 3.5 rounds of one-frequency
 // workgroups).  X tiles are double-buffered with the next tile prefetched into
 // registers; a lane's four output rows leave as two 16-byte stores.
-template<int BP, int NT, int TAG, int RANGE>
+template<int BP, int NT, int TAG, int RANGE, int PAIRS>
 __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
     constexpr int NTH = 512;
     constexpr int BP32 = (BP + 31) / 32 * 32;
     constexpr int S = BP32 / 32;                      // reduction steps of 32
     constexpr int LDX = BP32 + 8;                     // bf16 elements per LDS row (16-byte skew)
     constexpr int PF = (NT * BP + NTH - 1) / NTH;      // prefetched complex values per thread
+    constexpr int PF2 = (NT * BP / 2 + NTH - 1) / NTH; // prefetched pairs per thread (even b)
+    constexpr int PFA = PAIRS ? 2 * PF2 : PF;
     extern __shared__ unsigned char smem_raw[];
     unsigned short* xs = reinterpret_cast<unsigned short*>(smem_raw);   // [buffer][plane][NT][LDX]
     const GemmTask t = ntasks > 0 ? *find_gemm_task(tasks, ntasks) : t0;
@@ -1243,30 +1245,61 @@ __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const
     const float2* __restrict__ Xk = static_cast<const float2*>(t.X) + (size_t)k * W * bk;
     float2* __restrict__ Yk = static_cast<float2*>(t.Y) + (size_t)k * W * bk;
     const int plane = NT * LDX, bufsz = 2 * plane;
-    float2 pre[PF];
+    const bool even_b = (bk & 1) == 0;
+    // PAIRS (every b even, spectra 16-byte aligned): a lane moves two consecutive complex
+    // values of one column (one 16-byte load, one 4-byte LDS store per plane); otherwise
+    // one value
+    constexpr bool pairs = PAIRS != 0;
+    float2 pre[PFA];
     auto fetch = [&](int w0) {
         const int have = min(NT, wend - w0) * bk;
         // the tile's base made opaque, so that the per-load addresses are formed at each
         // fetch rather than hoisted out of the tile loop into registers of their own
         const float2* __restrict__ src = opaque_uniform(Xk + (size_t)w0 * bk);
+        if constexpr (pairs) {
 #pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            const int e = threadIdx.x + i * NTH;
-            pre[i] = e < have ? gload(src + e) : make_float2(0.f, 0.f);
-        }
-    };
-    auto stage = [&](unsigned short* buf) {
+            for (int i = 0; i < PF2; ++i) {
+                const int e = 2 * (threadIdx.x + i * NTH);
+                mlfft_f4v v = mlfft_f4v{0.f, 0.f, 0.f, 0.f};
+                if (e < have) v = *(const MLFFT_GLOBAL mlfft_f4v*)(src + e);
+                pre[2 * i] = make_float2(v[0], v[1]);
+                pre[2 * i + 1] = make_float2(v[2], v[3]);
+            }
+        } else {
 #pragma unroll
-        for (int i = 0; i < PF; ++i) {
-            const int e = threadIdx.x + i * NTH;
-            if (e < NT * bk) {
-                const int w = e / bk, n = e - w * bk;
-                buf[w * LDX + n] = f32_to_bf16_bits(pre[i].x);
-                buf[plane + w * LDX + n] = f32_to_bf16_bits(-pre[i].y);
+            for (int i = 0; i < PF; ++i) {
+                const int e = threadIdx.x + i * NTH;
+                pre[i] = e < have ? gload(src + e) : make_float2(0.f, 0.f);
             }
         }
     };
-    const bool even_b = (bk & 1) == 0;
+    auto stage = [&](unsigned short* buf) {
+        if constexpr (pairs) {
+#pragma unroll
+            for (int i = 0; i < PF2; ++i) {
+                const int e = 2 * (threadIdx.x + i * NTH);
+                if (e < NT * bk) {
+                    const int w = e / bk, n = e - w * bk;
+                    const uint32_t re = (uint32_t)f32_to_bf16_bits(pre[2 * i].x) |
+                                        ((uint32_t)f32_to_bf16_bits(pre[2 * i + 1].x) << 16);
+                    const uint32_t im = (uint32_t)f32_to_bf16_bits(-pre[2 * i].y) |
+                                        ((uint32_t)f32_to_bf16_bits(-pre[2 * i + 1].y) << 16);
+                    *reinterpret_cast<uint32_t*>(&buf[w * LDX + n]) = re;
+                    *reinterpret_cast<uint32_t*>(&buf[plane + w * LDX + n]) = im;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < PF; ++i) {
+                const int e = threadIdx.x + i * NTH;
+                if (e < NT * bk) {
+                    const int w = e / bk, n = e - w * bk;
+                    buf[w * LDX + n] = f32_to_bf16_bits(pre[i].x);
+                    buf[plane + w * LDX + n] = f32_to_bf16_bits(-pre[i].y);
+                }
+            }
+        }
+    };
     fetch(wbeg);
     __syncthreads();                      // padding zeroed; the previous segment's tiles read
     stage(xs);

@@ -8,6 +8,7 @@ struct GemmShape {
     int waves;      // waves per workgroup
     int nt;         // columns per LDS tile
     int m3;         // FP32 only: 1 = three real products per complex product
+    int pairs = 0;  // bf16 form 5: every b even and every spectrum 16-byte aligned
 };
 
 GemmShape gemm_shape(int prec, int bp, int tag);
