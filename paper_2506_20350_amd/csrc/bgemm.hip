@@ -86,6 +86,17 @@ void gemm_set_pc_shape(int bp, int waves, int nt, int m3) {
     g_shape_pc16[bp / 8] = waves ? GemmShape{waves, nt, m3} : GemmShape{0, 0, 0};
 }
 
+bool bf16_spectrum_ok(const int* b, int n) {
+    // the preconditioner product of these b (one padded b) reads bf16 spectra when it
+    // runs form 5 with pairs: every b even
+    if (n <= 0) return false;
+    const int bp = gemm_bp(PBF16, b[0]);
+    if (gemm_shape(PBF16, bp, 1).m3 != 5) return false;
+    for (int i = 0; i < n; ++i)
+        if ((b[i] & 1) || gemm_bp(PBF16, b[i]) != bp) return false;
+    return true;
+}
+
 void gemm_get_shape(int prec, int bp, int* waves, int* nt, int* m3) {
     const GemmShape s = gemm_shape(prec, bp, 0);
     *waves = s.waves;
@@ -188,12 +199,18 @@ hipError_t launch_bgemm(int prec, const GemmTask* th, const GemmTask* td, int nt
     if (prec == P64) return launch_bgemm_f64(bpm, sh, tag, th[0], dt, n, grid, s);
     if (prec == P32) return launch_bgemm_f32(bpm, sh, tag, th[0], dt, n, grid, s);
     GemmShape s16 = sh;
+    int nx16 = 0;
+    for (int i = 0; i < ntasks; ++i) nx16 += th[i].x16 ? 1 : 0;
     if (s16.m3 == 5) {
         bool ok = true;
         for (int i = 0; i < ntasks; ++i)
             ok = ok && (th[i].b & 1) == 0 && (reinterpret_cast<uintptr_t>(th[i].X) & 15) == 0;
         s16.pairs = ok ? 1 : 0;
     }
+    // bf16 spectra are only read by the pair-moving form-5 kernel, and by all tasks of a
+    // launch or none (the caller decides per padded b with bf16_spectrum_ok)
+    if (nx16 && (nx16 != ntasks || !s16.pairs)) return hipErrorInvalidValue;
+    s16.x16 = nx16 ? 1 : 0;
     return launch_bgemm_bf16(bpm, s16, tag, th[0], dt, n, grid, s);
 }
 

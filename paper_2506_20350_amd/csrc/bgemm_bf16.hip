@@ -22,11 +22,11 @@ static hipError_t launch_b16_flat_cfg(const GemmTask& t0, const GemmTask* td, in
     return hipGetLastError();
 }
 
-template<int BP, int TAG, int RANGE, int PAIRS = 0>
+template<int BP, int TAG, int RANGE, int PAIRS = 0, int XB = 0>
 static hipError_t launch_b16_freq(const GemmTask& t0, const GemmTask* td, int n, int grid, hipStream_t s) {
     constexpr int BP32 = (BP + 31) / 32 * 32;
     const size_t lds = (size_t)4 * 32 * (BP32 + 8) * sizeof(unsigned short);
-    auto k = bgemm_bf16_freq_kernel<BP, 32, TAG, RANGE, PAIRS>;
+    auto k = bgemm_bf16_freq_kernel<BP, 32, TAG, RANGE, PAIRS, XB>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(grid), dim3(512), lds, s, t0, td, n);
     return hipGetLastError();
@@ -53,8 +53,10 @@ hipError_t launch_bgemm_bf16(int bp, GemmShape sh, int tag, const GemmTask& t0, 
         // form 5 moves pairs of complex values when every task has even b and 16-byte
         // aligned spectra
         const bool pairs = sh.m3 == 5 && sh.pairs;
+        if (sh.x16 && !(pairs && tag)) return hipErrorInvalidValue;
         switch (bp) {
-#define Q16(B) case B: return sh.m3 == 5 ? (pairs ? (tag ? launch_b16_freq<B, 1, 1, 1>(t0, td, n, grid, s)  \
+#define Q16(B) case B: return sh.m3 == 5 ? (pairs ? (tag ? (sh.x16 ? launch_b16_freq<B, 1, 1, 1, 1>(t0, td, n, grid, s) \
+                                                                   : launch_b16_freq<B, 1, 1, 1>(t0, td, n, grid, s))   \
                                                           : launch_b16_freq<B, 0, 1, 1>(t0, td, n, grid, s))  \
                                                   : (tag ? launch_b16_freq<B, 1, 1>(t0, td, n, grid, s)      \
                                                          : launch_b16_freq<B, 0, 1>(t0, td, n, grid, s)))    \

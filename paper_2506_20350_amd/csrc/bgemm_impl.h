@@ -893,6 +893,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
 
 // ------------------------------------------------------------------ BF16
 
+typedef unsigned int mlfft_u2v __attribute__((ext_vector_type(2)));
+
 // p (wave-uniform) through an empty asm statement: the compiler can neither hoist nor
 // precompute addresses derived from the result
 template<typename T>
@@ -1162,7 +1164,7 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_bf16_flat_kernel(GemmTask t0
 // idle (30x30, b = 200: 900 frequencies of 29 tiles were 3.5 rounds of one-frequency
 // workgroups).  X tiles are double-buffered with the next tile prefetched into
 // registers; a lane's four output rows leave as two 16-byte stores.
-template<int BP, int NT, int TAG, int RANGE, int PAIRS>
+template<int BP, int NT, int TAG, int RANGE, int PAIRS, int XB = 0>
 __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
     constexpr int NTH = 512;
     constexpr int BP32 = (BP + 31) / 32 * 32;
@@ -1256,7 +1258,21 @@ __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const
         // the tile's base made opaque, so that the per-load addresses are formed at each
         // fetch rather than hoisted out of the tile loop into registers of their own
         const float2* __restrict__ src = opaque_uniform(Xk + (size_t)w0 * bk);
-        if constexpr (pairs) {
+        if constexpr (XB != 0) {
+            // X already in bf16 (re, im) pairs: a lane loads two values as two 32-bit words,
+            // kept bit for bit in a prefetch slot
+            const mlfft_u2v* __restrict__ s16 = opaque_uniform(static_cast<const mlfft_u2v*>(t.X) +
+                                                               (((size_t)k * W + w0) * bk >> 1));
+#pragma unroll
+            for (int i = 0; i < PF2; ++i) {
+                const int e = 2 * (threadIdx.x + i * NTH);
+                mlfft_u2v v = mlfft_u2v{0u, 0u};
+                if (e < have) v = *(const MLFFT_GLOBAL mlfft_u2v*)(s16 + (e >> 1));
+                // elements copied to scalars first: a bit cast of a vector element reads element 0
+                const unsigned int a0 = v[0], a1 = v[1];
+                pre[2 * i] = make_float2(__uint_as_float(a0), __uint_as_float(a1));
+            }
+        } else if constexpr (pairs) {
 #pragma unroll
             for (int i = 0; i < PF2; ++i) {
                 const int e = 2 * (threadIdx.x + i * NTH);
@@ -1274,7 +1290,23 @@ __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const
         }
     };
     auto stage = [&](unsigned short* buf) {
-        if constexpr (pairs) {
+        if constexpr (XB != 0) {
+#pragma unroll
+            for (int i = 0; i < PF2; ++i) {
+                const int e = 2 * (threadIdx.x + i * NTH);
+                if (e < NT * bk) {
+                    const int w = e / bk, n = e - w * bk;
+                    const float f0 = pre[2 * i].x, f1 = pre[2 * i].y;
+                    const uint32_t w0v = __float_as_uint(f0), w1v = __float_as_uint(f1);
+                    // Re X of both values; -Im X by flipping the sign bits (bf16 rounding is
+                    // symmetric, so this is the rounded -Im X)
+                    const uint32_t re = (w0v & 0xffffu) | (w1v << 16);
+                    const uint32_t im = ((w0v >> 16) | (w1v & 0xffff0000u)) ^ 0x80008000u;
+                    *reinterpret_cast<uint32_t*>(&buf[w * LDX + n]) = re;
+                    *reinterpret_cast<uint32_t*>(&buf[plane + w * LDX + n]) = im;
+                }
+            }
+        } else if constexpr (pairs) {
 #pragma unroll
             for (int i = 0; i < PF2; ++i) {
                 const int e = 2 * (threadIdx.x + i * NTH);

@@ -9,6 +9,7 @@ struct GemmShape {
     int nt;         // columns per LDS tile
     int m3;         // FP32 only: 1 = three real products per complex product
     int pairs = 0;  // bf16 form 5: every b even and every spectrum 16-byte aligned
+    int x16 = 0;    // bf16 form 5 with pairs: X in bf16 (re, im) pairs (GemmTask::x16 of every task)
 };
 
 GemmShape gemm_shape(int prec, int bp, int tag);

@@ -143,7 +143,8 @@ struct FwdX {
         if (tid >= Py * cm) return;
         const int ky = tid / cm, mi = tid - ky * cm;
         if (mi >= wk.mlen) return;
-        C* __restrict__ dst = static_cast<C*>(t->out) + (size_t)wk.w * b + wk.m0 + mi;
+        const size_t base = (size_t)wk.w * b + wk.m0 + mi;
+        C* __restrict__ dst = static_cast<C*>(t->out) + base;
         const size_t ks = (size_t)W * b;
         for (int g = 0; g < H; ++g) {
             C v[NX];
@@ -151,6 +152,19 @@ struct FwdX {
             for (int ix = 0; ix < NX; ++ix) v[ix] = tile[ky * t->rs + ix * cm + mi];
             if (g) Fft<C, NX, -1>::tw2(v);
             Fft<C, NX, -1>::run(v);
+            if constexpr (std::is_same<C, float2>::value) {
+                if (t->out16) {
+                    // bf16 spectrum for the bf16 block product: (re, im) rounded to nearest even
+                    uint32_t* __restrict__ d16 = static_cast<uint32_t*>(t->out) + base;
+#pragma unroll
+                    for (int i = 0; i < NX; ++i) {
+                        const int kx = t->pad ? 2 * i + g : i;
+                        d16[(size_t)(ky * Px + kx) * ks] =
+                            (uint32_t)f32_to_bf16_bits(v[i].x) | ((uint32_t)f32_to_bf16_bits(v[i].y) << 16);
+                    }
+                    continue;
+                }
+            }
 #pragma unroll
             for (int i = 0; i < NX; ++i) {
                 const int kx = t->pad ? 2 * i + g : i;

@@ -30,6 +30,9 @@ struct FftTask {
     int colpad = 0;         // elements after each spatial column of in (forward) / out and addend (inverse):
                             // spatial columns start every Ny Nx b + colpad elements (the border unknowns of
                             // the full system follow the array's in every column); 0: back to back
+    int out16 = 0;          // forward FP32, one-pass tile only: the spectrum is stored as bf16 (re, im) pairs
+                            // (round to nearest even), 4 bytes per value, same layout
+    int reserved = 0;       // fills the tail: a task's bytes are all defined (tables are cached by content)
 };
 
 // One array's share of a grouped per-frequency block product
@@ -42,11 +45,11 @@ struct GemmTask {
     int K, b, W;
     int mgroups;            // workgroups per frequency (row groups)
     int block_begin;
-    int reserved = 0;       // fills the tail: a task's bytes are all defined (tables are cached by content)
+    int x16 = 0;            // bf16 product form 5 only: X holds bf16 (re, im) pairs instead of FP32 complex
 };
 
 // no padding bytes: the members add up to the size
-static_assert(sizeof(FftTask) == 5 * 8 + 10 * 4, "FftTask must have no padding");
+static_assert(sizeof(FftTask) == 5 * 8 + 12 * 4, "FftTask must have no padding");
 static_assert(sizeof(GemmTask) == 4 * 8 + 6 * 4, "GemmTask must have no padding");
 
 enum Prec { P64 = 0, P32 = 1, PBF16 = 2 };
@@ -83,6 +86,9 @@ void gemm_set_shape(int prec, int bp, int waves, int nt, int m3);
 void gemm_set_pc_shape(int bp, int waves, int nt, int m3);
 // workgroups a launch of the bf16 preconditioner's frequency kernel aims at (columns split to reach it)
 void gemm_set_pc_wg_target(int n);
+// whether the bf16 preconditioner product of arrays with these b (all of one padded b)
+// reads its spectra in bf16 (form 5 moving pairs; every b even)
+bool bf16_spectrum_ok(const int* b, int n);
 void gemm_get_shape(int prec, int bp, int* waves, int* nt, int* m3);
 int gemm_bp(int prec, int b);
 

@@ -360,19 +360,32 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
     }
     HIPCHK(spec_a.ensure(need), "preconditioner workspace");
     HIPCHK(spec_b.ensure(need), "preconditioner workspace");
+    // bf16 products that read bf16 spectra (decided per padded b, the unit of a product
+    // launch): the forward transform then stores its spectrum in bf16 pairs, which halves
+    // its writes and the product's reads, with the same rounding the product would apply
+    std::map<int, bool> spec16;
+    if (prec == PBF16) {
+        std::map<int, std::vector<int>> bs;
+        for (const MatvecItem& it : items) bs[gemm_bp(PBF16, it.arr->b)].push_back(it.arr->b);
+        for (auto& kv : bs) spec16[kv.first] = bf16_spectrum_ok(kv.second.data(), (int)kv.second.size());
+    }
     std::vector<FftTask> fw(nt), iv(nt);
     std::vector<GemmTask> gm(nt);
+    std::vector<int> x16(nt, 0);
     for (int i = 0; i < nt; ++i) {
         const MatvecItem& it = items[i];
         const Array* a = it.arr;
+        x16[i] = prec == PBF16 && spec16[gemm_bp(PBF16, a->b)] ? 1 : 0;
         FftTask t{};
         t.in = it.x; t.out = (char*)spec_a.p + off[i]; t.alpha = 1.0;
         t.Nx = a->Nx; t.Ny = a->Ny; t.b = a->b; t.W = it.W; t.pad = 0; t.colpad = a->Nc;
+        t.out16 = x16[i];
         fw[i] = t;
         GemmTask g{};
         g.G = prec == P64 ? a->S64.p : prec == P32 ? a->S32.p : a->S16.p;
         g.X = (char*)spec_a.p + off[i]; g.Y = (char*)spec_b.p + off[i];
         g.K = a->Nx * a->Ny; g.b = a->b; g.W = it.W; g.gstride = (long)a->b * a->b;
+        g.x16 = x16[i];
         gm[i] = g;
         FftTask u{};
         u.in = (char*)spec_b.p + off[i]; u.out = it.y; u.addend = it.addend;
@@ -380,16 +393,18 @@ mlfft_status Ctx::precond_group(const std::vector<MatvecItem>& items, int kind, 
         u.Nx = a->Nx; u.Ny = a->Ny; u.b = a->b; u.W = it.W; u.pad = 0; u.colpad = a->Nc;
         iv[i] = u;
     }
-    double bf = 0, bg = 0, fl = 0;
+    double bf = 0, bfw = 0, bg = 0, fl = 0;
     const double s = eb, sg = prec == P64 ? 16 : prec == P32 ? 8 : 4;
     for (int i = 0; i < nt; ++i) {
         const Array* a = items[i].arr;
         const double N = (double)a->Nx * a->Ny * a->b * items[i].W;
+        const double sx = x16[i] ? 4 : s;       // bytes per value of the forward spectrum
         bf += s * 2 * N;
-        bg += s * 2 * N + sg * (double)a->Nx * a->Ny * a->b * a->b;
+        bfw += (s + sx) * N;
+        bg += (sx + s) * N + sg * (double)a->Nx * a->Ny * a->b * a->b;
         fl += 8.0 * a->Nx * a->Ny * (double)a->b * a->b * items[i].W;
     }
-    int pr = prof_begin(PK_PC_FFT_FWD, prec, bf, 0);
+    int pr = prof_begin(PK_PC_FFT_FWD, prec, bfw, 0);
     STCHK(fft_grouped(prec, fw, false, "preconditioner FFT launch"));
     prof_end(pr);
     pr = prof_begin(PK_PC_GEMM, prec, bg, fl);

@@ -375,8 +375,10 @@ def test_bf16_preconditioner_frequency_kernel_matches_flat_kernel_and_oracle(ctx
     evenly over about one workgroup per CU, ranges crossing frequencies (form 5), against the
     flat kernel (form 2), each forced through a tuning line (form 5 is the default for padded
     b in 112..208, form 2 elsewhere).  Forms 3 and 5 run the same arithmetic per tile, so they
-    agree bit for bit; the flat kernel rounds the same operands to bf16 and accumulates in
-    FP32 in another order.  Ragged b (24, 100, 120) leaves padded reduction rows and partial
+    agree bit for bit; with even b, form 5 reads the spectrum that the forward transform stored
+    as bf16 pairs (form 3 rounds an FP32 spectrum as it stages it), so this also pins the bf16
+    spectrum path.  The flat kernel rounds the same operands to bf16 and accumulates in FP32
+    in another order.  Ragged b (24, 100, 120) leaves padded reduction rows and partial
     16-row slices; W = 5, 7, 11, 33, 45, 70 leave partial 32-column tiles."""
     blocks = synth.green_blocks(Nx, Ny, b, np.pi, seed=3)
     ctx.set_blocks(9, blocks)
