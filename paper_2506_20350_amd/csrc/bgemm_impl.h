@@ -1163,7 +1163,10 @@ __global__ void __launch_bounds__(64 * WAVES) bgemm_bf16_flat_kernel(GemmTask t0
 // workgroups, about one per CU, so that no partial last round of workgroups leaves CUs
 // idle (30x30, b = 200: 900 frequencies of 29 tiles were 3.5 rounds of one-frequency
 // workgroups).  X tiles are double-buffered with the next tile prefetched into
-// registers; a lane's four output rows leave as two 16-byte stores.
+// registers; a lane's four output rows leave as two 16-byte stores.  PAIRS (every b
+// even, spectra 16-byte aligned): a lane moves two consecutive values of a column.
+// XB (with PAIRS): X holds bf16 (re, im) pairs already rounded by the transform that
+// wrote it, so a value is 4 bytes read and nothing is converted.
 template<int BP, int NT, int TAG, int RANGE, int PAIRS, int XB = 0>
 __global__ void __launch_bounds__(512) bgemm_bf16_freq_kernel(GemmTask t0, const GemmTask* tasks, int ntasks) {
     constexpr int NTH = 512;
